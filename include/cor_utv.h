@@ -1,0 +1,219 @@
+/*
+ * cor_utv.h -- C ABI of the MI355X (gfx950) CoR-UTV library, libcorutv.so.
+ *
+ * Compressed Randomized UTV with power iteration (Kaloorazi & de Lamare,
+ * "Compressed Randomized UTV Decompositions for Low-Rank Approximations and
+ * Big Data Applications", Sec. III, Alg. 1 and Alg. 3).  Given A (m x n) and
+ * integers k <= l = k + p < min(m, n) and q >= 0, the library returns a
+ * rank-l approximation A ~ U T V^T with U (m x l) and V (n x l) orthonormal
+ * and T (l x l) upper triangular whose diagonal tracks the leading singular
+ * values of A (the URV form of eq. (eq_T_basic)).
+ *
+ * What runs, per decomposition (all on the GPU):
+ *   X = Omega (i.i.d. N(0,1), n x l)                      [Alg. 3, step 1]
+ *   repeat q+1 times:                                      [Alg. 3, loop]
+ *     Y1 = A X          -> Q1 R1 = Y1 (CholeskyQR2, FP64)  [eq. (eq_C1_1st)]
+ *     Y2 = A^T Q1       -> Q2 R2 = Y2 (CholeskyQR2, FP64)  [eq. (eqAC1)]
+ *     X  = Q2
+ *   M = Q1^T A Q2 = R2^T                                   [eq. (eqM)]
+ *   M P = Qt T  (column-pivoted QR, FP64)                  [eq. (eq_Drrqr)]
+ *   U = Q1 Qt,  V = Q2 P                                   [eq. (eq_T_basic)]
+ * The second sketch uses Q1 instead of the paper's un-normalised C1 and every
+ * product with A is orthonormalised before the next one; both leave Q1, Q2 and
+ * M unchanged in exact arithmetic.  M = R2^T holds because
+ * Q1^T A Q2 = (A^T Q1)^T Q2 = (Q2 R2)^T Q2.
+ *
+ * Conventions
+ *   - Matrices are row-major: element (i, j) of an r x c matrix with leading
+ *     dimension ld is at index i*ld + j.
+ *   - Every matrix pointer is a DEVICE pointer (hipMalloc'd or a torch CUDA
+ *     tensor's data pointer) unless stated otherwise.  The caller owns A and
+ *     the outputs; the library never writes A.  The library owns its
+ *     workspace (a per-device pool that grows on demand and is released by
+ *     cor_release() or at unload).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Outputs are always FP64.  T has exact zeros below the diagonal and a
+ *     non-negative diagonal.  perm (optional) receives the QRCP permutation:
+ *     V[:, j] = Q2[:, perm[j]].
+ *   - Every call returns a cor_status; no C++ exception crosses the ABI.
+ *     cor_last_error() returns a message for the last failure on the calling
+ *     thread.
+ */
+#ifndef COR_UTV_H
+#define COR_UTV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    COR_OK = 0,
+    COR_E_INVAL = 1,    /* bad argument (shape, rank parameters, null pointer, lda)        */
+    COR_E_NOMEM = 2,    /* device or host allocation failed                                 */
+    COR_E_DEVICE = 3,   /* a HIP call failed                                                */
+    COR_E_NUMERIC = 4,  /* non-finite input or a Cholesky breakdown that survived the retry */
+    COR_E_BUSY = 5,     /* served request still running (cor_server_poll)                   */
+    COR_E_NOTFOUND = 6  /* unknown ticket                                                   */
+} cor_status;
+
+/* Storage format of A, which is also the arithmetic format of the passes over
+ * A (MFMA with FP32 accumulation; FP64 MFMA in COR_F64).  The Gram matrices,
+ * Cholesky factors, orthonormal bases and the l x l core stay FP64. */
+typedef enum {
+    COR_F64 = 0,   /* double                                                      */
+    COR_F32 = 1,   /* float                                                       */
+    COR_BF16 = 2,  /* bfloat16 (binary32 rounded to nearest even), 2 bytes         */
+    COR_FP8 = 3    /* OCP FP8 E4M3FN codes with a per-column FP32 scale, 1 byte:   */
+                   /* A[i][j] ~ fp8(code[i][j]) * colscale[j]                       */
+} cor_prec;
+
+/* cor_info.flags */
+#define COR_FLAG_CHOL_RETRY 1     /* a Cholesky factorisation needed the shifted retry */
+#define COR_FLAG_RANK_DEFICIENT 2 /* a sketch was numerically rank deficient           */
+#define COR_FLAG_NONFINITE 4      /* a non-finite value reached a Gram matrix          */
+
+typedef struct {
+    double err_l;     /* ||A - U T V^T||_F / ||A||_F  (report >= 1; identity 1 - ||T||^2/||A||^2) */
+    double err_k;     /* ||A - U[:, :k] T[:k, :] V^T||_F / ||A||_F (report >= 1)                  */
+    double orth_u;    /* ||U^T U - I||_F (report >= 1)                                            */
+    double orth_v;    /* ||V^T V - I||_F (report >= 1)                                            */
+    double device_ms; /* device time of the call, or submit-to-completion for served requests    */
+    int32_t flags;    /* COR_FLAG_*                                                               */
+    int32_t l;        /* k + p                                                                    */
+} cor_info;
+
+/* One decomposition request. */
+typedef struct {
+    const void* A;         /* device, m x n row-major with leading dimension lda, format `prec`  */
+    const float* colscale; /* device, n floats; required for COR_FP8, ignored otherwise          */
+    int64_t m, n, lda;     /* lda >= n                                                            */
+    int32_t k, p, q;       /* l = k + p; k >= 1, p >= 0, 2 <= l < min(m, n), l <= 264, 0 <= q <= 16 */
+    int32_t prec;          /* cor_prec                                                            */
+    uint64_t seed;         /* Omega from the counter-based generator of cor_omega()               */
+    const double* omega;   /* optional device n x l FP64 test matrix; overrides seed             */
+    double* U;             /* device out, m x l                                                   */
+    double* T;             /* device out, l x l                                                   */
+    double* V;             /* device out, n x l                                                   */
+    int32_t* perm;         /* optional device out, l int32                                        */
+} cor_problem;
+
+typedef struct {
+    int32_t report;     /* 0: nothing; 1: fill err_l, err_k, orth_u, orth_v of cor_info          */
+    int32_t explicit_m; /* 1: form M = Q1^T (A Q2) with one more pass over A (checking mode)     */
+} cor_opts;
+
+/* ---------------------------------------------------------------------------
+ * Single decomposition (the paper's problem statement: "Input: matrix A,
+ * integers k, l and q"; Alg. 3).  A has lda = n.  COR_FP8 needs a column scale
+ * and is only reachable through cor_utv_ex.  Returns after the work on
+ * `stream` has completed; `info` may be NULL.
+ * ------------------------------------------------------------------------- */
+cor_status cor_utv(const void* A, int64_t m, int64_t n, int32_t k, int32_t p, int32_t q,
+                   uint64_t seed, int32_t prec, double* U, double* T, double* V,
+                   cor_info* info, void* stream);
+
+/* Same with every option; opts may be NULL (defaults: report 0, explicit_m 0). */
+cor_status cor_utv_ex(const cor_problem* prob, const cor_opts* opts, cor_info* info,
+                      void* stream);
+
+/* `count` independent decompositions of uneven shapes, run as grouped launches
+ * (one launch per stage and per column-tile class covers every problem).
+ * infos (optional) receives count records.  Returns after completion. */
+cor_status cor_utv_batched(const cor_problem* probs, int32_t count, const cor_opts* opts,
+                           cor_info* infos, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Plans: the executor behind the calls above, exposed for callers that replay
+ * the same decomposition(s) many times.  A plan owns its workspace and
+ * device-side descriptors; cor_plan_run() only enqueues kernels on `stream`
+ * (no allocation, no host synchronisation, no memset), so it may be captured
+ * into a HIP graph.  cor_plan_capture() records one run into a graph that
+ * later cor_plan_run() calls replay with hipGraphLaunch.
+ * ------------------------------------------------------------------------- */
+typedef struct cor_plan cor_plan;
+cor_status cor_plan_create(const cor_problem* probs, int32_t count, const cor_opts* opts,
+                           cor_plan** plan);
+cor_status cor_plan_run(cor_plan* plan, void* stream);
+cor_status cor_plan_capture(cor_plan* plan, void* stream);
+/* Waits for `stream`, then reads back flags and the report of each problem. */
+cor_status cor_plan_info(cor_plan* plan, cor_info* infos, void* stream);
+cor_status cor_plan_destroy(cor_plan* plan);
+
+/* ---------------------------------------------------------------------------
+ * Served decompositions with continuous batching.  A server thread admits
+ * queued requests while their workspace fits the HBM budget and a slot is
+ * free, runs every admitted request's pipeline concurrently on the device and
+ * retires each request as soon as its own pipeline completes, so requests that
+ * arrive while others run join without waiting for them.  A request's result
+ * does not depend on what runs beside it (fixed reduction orders).
+ * A, outputs and colscale must stay valid until the request completes.
+ * ------------------------------------------------------------------------- */
+typedef struct cor_server cor_server;
+typedef struct {
+    size_t hbm_budget;  /* bytes of workspace the server may hold (0: 64 GiB)               */
+    int32_t max_slots;  /* requests in flight at once (0: 32)                                */
+    int32_t convert_f32_to; /* COR_F32 (0 = keep) or COR_BF16: FP32 requests are converted    */
+                            /* once on the device and their passes run in BF16                */
+} cor_server_cfg;
+typedef struct {
+    double p50_ms, p99_ms, mean_ms; /* submit-to-completion latency of completed requests      */
+    double decomps_per_s;           /* completed / (last completion - first submission)        */
+    int64_t completed, queued, active, rejected;
+    size_t hbm_in_use, hbm_high_water;
+} cor_server_stats;
+
+cor_status cor_server_create(const cor_server_cfg* cfg, cor_server** server);
+/* Enqueue a request (thread-safe).  COR_E_INVAL if it is malformed or can never
+ * fit the budget. */
+cor_status cor_server_submit(cor_server* server, const cor_problem* prob, const cor_opts* opts,
+                             uint64_t* ticket);
+/* COR_OK and *info filled when done, COR_E_BUSY while queued or running. */
+cor_status cor_server_poll(cor_server* server, uint64_t ticket, cor_info* info);
+cor_status cor_server_wait(cor_server* server, uint64_t ticket, cor_info* info);
+cor_status cor_server_stats_get(cor_server* server, cor_server_stats* stats);
+cor_status cor_server_destroy(cor_server* server);
+
+/* ---------------------------------------------------------------------------
+ * Helpers
+ * ------------------------------------------------------------------------- */
+/* Device workspace of one decomposition of an m x n matrix with l = k + p
+ * (the unit of the server's admission control). */
+size_t cor_workspace_bytes(int64_t m, int64_t n, int32_t l, int32_t prec);
+
+/* Convert an FP32 device matrix (m x n, lda) to the storage format `to`
+ * (COR_BF16: out is m x n uint16 with ld n; COR_FP8: out is m x n bytes with
+ * ld n and colscale receives n floats, s_j = max_i |A_ij| / 448 (1 for an
+ * all-zero column), code = E4M3FN(A_ij / s_j) rounded to nearest even with
+ * saturation at +-448). */
+cor_status cor_quantize(const float* A32, int64_t m, int64_t n, int64_t lda, int32_t to,
+                        void* out, float* colscale, void* stream);
+
+/* The Gaussian test matrix of Alg. 3, step 1, written to device memory as an
+ * n x l FP64 row-major array.  Integer t of the stream is output t of
+ * SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) started at `seed`; the pair
+ * (2j, 2j+1) of the row-major array is the Box-Muller transform of
+ * u1 = ((s(2j) >> 11) + 1) 2^-53 and u2 = (s(2j+1) >> 11) 2^-53:
+ * sqrt(-2 ln u1) * (cos, sin)(2 pi u2).  Device libm: values agree with a host
+ * implementation of the same definition to a few ulp. */
+cor_status cor_omega(uint64_t seed, int64_t n, int32_t l, double* out, void* stream);
+
+/* Kernel timing of the passes over A for roofline reports: while enabled, each
+ * launch of the sketch kernels is bracketed by HIP events on its own stream.
+ * cor_profile_read() synchronises those events and returns the summed time
+ * (ms), the number of launches and the algorithmic bytes and flops of those
+ * launches, then resets the counters. */
+cor_status cor_profile_enable(int32_t on);
+cor_status cor_profile_read(double* ms, int64_t* launches, double* bytes, double* flops);
+
+const char* cor_status_string(int32_t status);
+const char* cor_last_error(void);
+/* Free the workspace pool and cached plans of every device. */
+cor_status cor_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COR_UTV_H */

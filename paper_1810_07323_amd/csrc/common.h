@@ -1,0 +1,134 @@
+// Shared device-side definitions of the CoR-UTV library (gfx950).
+//
+// Every kernel works on a list of problem descriptors (Prob) that live in
+// device memory.  A launch covers one stage of the method for a group of
+// problems: block b belongs to problem pidx[j] where toff[j] <= b < toff[j+1]
+// (toff is an exclusive prefix sum of per-problem block counts).  A single
+// decomposition is the group of one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cor {
+
+enum Prec : int32_t { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_FP8 = 3 };
+
+constexpr int LMAX = 264;   // largest l = k + p supported
+constexpr int LPMAX = 272;  // LMAX padded to a multiple of 16
+constexpr int NTMAX = 17;   // LPMAX / 16
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Flags (device word per problem; mirrored by COR_FLAG_* of the public header).
+constexpr int32_t FLAG_CHOL_RETRY = 1;
+constexpr int32_t FLAG_RANK_DEF = 2;
+constexpr int32_t FLAG_NONFINITE = 4;
+
+// One decomposition: inputs, workspace and outputs (all device pointers).
+struct Prob {
+    const void* A;          // m x n, row-major, leading dimension lda, format prec
+    const float* colscale;  // FP8: n column scales of A
+    int64_t m, n, lda;
+    int32_t k, l, lp, q;    // l = k + p, lp = l rounded up to 16
+    int32_t prec, explicit_m, report, avec;  // avec: A rows 16-byte aligned
+
+    // Operand copies of the skinny factors, stored transposed: [lp][ld]
+    // (row c holds column c of the factor), in the pass format.
+    void* xop;   // n-side: Omega, then Q2
+    void* qop;   // m-side: Q1
+    int64_t ldx, ldq;
+    float* xscale;  // FP8: per-column scales of xop (lp)
+    float* qscale;  // FP8: per-column scales of qop (lp)
+
+    // Split-K partial sums of a pass over A: [splits][rows][lp], FP32 (FP64
+    // in F64 mode).
+    void* ypart;
+    int32_t s_ax, s_atx;      // number of K splits of A*X and A^T*X
+    int64_t kc_ax, kc_atx;    // K range of one split (multiple of the K tile)
+
+    // FP64 work arrays.
+    double* Y;    // max(m, n) x l  : reduced sketch
+    double* Qa;   // max(m, n) x l  : first CholeskyQR factor
+    double* Q1;   // m x l
+    double* Q2;   // n x l (Omega in FP64 before the first pass)
+    double* gpart;  // Gram partial sums: [blocks][l][l]
+    int32_t rb_m, rb_n;  // rows per Gram block on the m- and n-side
+    int32_t gb_m, gb_n;  // number of Gram blocks on each side
+    double* G;     // l x l reduced Gram
+    double* R;     // l x l current Cholesky factor (upper)
+    double* Racc;  // l x l accumulated R of the orthonormalisation
+    double* Qt;    // l x l orthogonal factor of the QRCP
+    double* rep;   // 16 doubles of report scratch
+    int32_t* flags;
+
+    // Outputs.
+    double* U;
+    double* T;
+    double* V;
+    int32_t* perm;  // l (always written; the caller's pointer or workspace)
+
+    const double* omega;  // optional caller test matrix (n x l FP64)
+    uint64_t seed;
+};
+
+__device__ __forceinline__ int find_group(const int32_t* __restrict__ toff, int cnt, int b) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (toff[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int P> struct PrecT;
+template <> struct PrecT<P_F64> { typedef double T; typedef double Acc; static constexpr int SZ = 8; };
+template <> struct PrecT<P_F32> { typedef float T; typedef float Acc; static constexpr int SZ = 4; };
+template <> struct PrecT<P_BF16> { typedef uint16_t T; typedef float Acc; static constexpr int SZ = 2; };
+template <> struct PrecT<P_FP8> { typedef uint8_t T; typedef float Acc; static constexpr int SZ = 1; };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Binary32 -> bfloat16, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16(float x) {
+    uint32_t b = __float_as_uint(x);
+    if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) return (uint16_t)((b >> 16) | 0x40u);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+// Binary32 -> OCP E4M3FN code, round to nearest even, saturating to +-448.
+__device__ __forceinline__ uint8_t f32_to_e4m3(float x) {
+    uint32_t b = __float_as_uint(x);
+    uint8_t sign = (uint8_t)((b >> 24) & 0x80u);
+    float a = fabsf(x);
+    if (a != a) return 0x7F;
+    if (a >= 448.0f) return sign | 0x7E;
+    // Normal range of E4M3 starts at 2^-6; below it the spacing is 2^-9.
+    if (a < 0.015625f) {
+        // subnormal: value = m * 2^-9, m in [0, 8]; m = 8 is the smallest normal (code 0x08)
+        float t = a * 512.0f;                 // exact scaling by a power of two
+        float r = rintf(t);                   // round half to even
+        return sign | (uint8_t)r;
+    }
+    int e;
+    float f = frexpf(a, &e);                  // a = f * 2^e, f in [0.5, 1)
+    // mantissa with 3 fraction bits: a = (1 + m/8) 2^(e-1)
+    float t = f * 16.0f;                      // in [8, 16)
+    float r = rintf(t);                       // round half to even on the 3-bit mantissa
+    int ee = e - 1 + 7;                       // biased exponent
+    int mm = (int)r - 8;
+    if (mm == 8) { mm = 0; ee += 1; }
+    if (ee > 15 || (ee == 15 && mm == 7)) return sign | 0x7E;
+    return sign | (uint8_t)((ee << 3) | mm);
+}
+
+}  // namespace cor

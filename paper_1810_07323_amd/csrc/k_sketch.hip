@@ -1,0 +1,377 @@
+// Passes over A: the sketch products of CoR-UTV (Alg. 3, power loop).
+//
+//   TRANS = false:  Y1 = A X    (m x l), contraction over the n columns of A
+//   TRANS = true :  Y2 = A^T X  (n x l), contraction over the m rows of A
+//
+// A is streamed exactly once per pass.  A block owns BM = 128 output rows and
+// one K range (split-K); every wave owns RT = 2 row tiles of 16 and all NT
+// column tiles of 16, so each element of A loaded into LDS feeds NT MFMAs
+// from registers and the skinny operand X is the only operand re-read
+// (from LDS) per row tile.  Tiles are 128 bytes of K per row (BK elements),
+// double-buffered in LDS with rows padded to 144 bytes, which makes the
+// 16-byte operand reads of a 16-lane group cover all 64 banks once.
+//
+// MFMA forms (gfx950):  f64 16x16x4,  f32 16x16x4,  bf16 16x16x32,
+// fp8 (E4M3FN) 16x16x128 with unit block scales.  Lane l = 16 g + i supplies
+// row i and K slots [g*KL, (g+1)*KL) of both operands, KL = K per MFMA / 4.
+// The order in which K is visited does not change a dot product, so each lane
+// reads one 16-byte vector of K from LDS and feeds it to consecutive MFMAs.
+//
+// Output: FP32 partial sums (FP64 in F64 mode) ypart[split][row][lp]; the
+// splits are added in a fixed order by the reduction kernel, so the result
+// does not depend on scheduling.
+#include "common.h"
+#include "kernels.h"
+
+namespace cor {
+
+template <int PREC> struct SkCfg;
+template <> struct SkCfg<P_F64> { static constexpr int BK = 16, VEC = 2; };
+template <> struct SkCfg<P_F32> { static constexpr int BK = 32, VEC = 4; };
+template <> struct SkCfg<P_BF16> { static constexpr int BK = 64, VEC = 8; };
+template <> struct SkCfg<P_FP8> { static constexpr int BK = 128, VEC = 16; };
+
+constexpr int SK_THREADS = 256;
+constexpr int SK_RT = 2;                      // row tiles of 16 per wave
+constexpr int SK_BM = 4 * SK_RT * 16;         // output rows per block (128)
+constexpr int ROWB = 144;                     // LDS bytes per 128-byte K row (+16 pad)
+
+template <int PREC, bool TRANS>
+__host__ __device__ constexpr int sk_a_bytes() {
+    // Non-transposed (and 1/2-byte transposed) tiles: BM rows of 128 (+16) bytes.
+    // F32/F64 transposed tiles: BK rows of BM elements (+16 bytes).
+    return (TRANS && (PREC == P_F32 || PREC == P_F64))
+               ? SkCfg<PREC>::BK * (SK_BM * PrecT<PREC>::SZ + 16)
+               : SK_BM * ROWB;
+}
+
+template <int PREC, int NT, bool TRANS>
+__host__ __device__ constexpr int sk_lds_bytes() {
+    return 2 * (sk_a_bytes<PREC, TRANS>() + NT * 16 * ROWB);
+}
+
+// 16-byte global load with element-wise bounds (zero fill) when needed.
+template <typename T, int VEC>
+__device__ __forceinline__ i32x4 load16(const T* p, int64_t valid, bool vec_ok) {
+    i32x4 v;
+    if (vec_ok && valid >= VEC) {
+        v = *reinterpret_cast<const i32x4*>(p);
+    } else {
+        union { i32x4 v; T e[VEC]; } u;
+#pragma unroll
+        for (int e = 0; e < VEC; e++) u.e[e] = (e < valid) ? p[e] : T(0);
+        v = u.v;
+    }
+    return v;
+}
+
+template <int PREC, int NT, bool TRANS>
+__global__ __launch_bounds__(SK_THREADS) void k_sketch(const Prob* __restrict__ probs,
+                                                       const int32_t* __restrict__ pidx,
+                                                       const int32_t* __restrict__ toff, int cnt,
+                                                       int iter) {
+    typedef typename PrecT<PREC>::T T;
+    typedef typename PrecT<PREC>::Acc Acc;
+    constexpr int SZ = PrecT<PREC>::SZ;
+    constexpr int BK = SkCfg<PREC>::BK;
+    constexpr int VEC = SkCfg<PREC>::VEC;
+    constexpr int ABYTES = sk_a_bytes<PREC, TRANS>();
+    constexpr int XBYTES = NT * 16 * ROWB;
+    constexpr bool ATRANS_SCALAR = TRANS && (PREC == P_F32 || PREC == P_F64);
+    constexpr int AROWB = SK_BM * SZ + 16;  // row stride of a transposed F32/F64 tile
+
+    extern __shared__ __align__(16) unsigned char smem[];
+
+    const int j = find_group(toff, cnt, blockIdx.x);
+    const Prob& P = probs[pidx[j]];
+    if (iter > P.q) return;
+    const int local = blockIdx.x - toff[j];
+
+    const int64_t rows = TRANS ? P.n : P.m;    // output rows
+    const int64_t K = TRANS ? P.m : P.n;       // contraction length
+    const int nrb = (int)((rows + SK_BM - 1) / SK_BM);
+    const int rb = local % nrb;
+    const int split = local / nrb;
+    const int64_t kc = TRANS ? P.kc_atx : P.kc_ax;
+    const int64_t kbeg = (int64_t)split * kc;
+    const int64_t kend = min(K, kbeg + kc);
+    const int64_t row0 = (int64_t)rb * SK_BM;
+    const int lp = P.lp;
+
+    const T* __restrict__ A = reinterpret_cast<const T*>(P.A);
+    const T* __restrict__ X = reinterpret_cast<const T*>(TRANS ? P.qop : P.xop);
+    const int64_t ldx = TRANS ? P.ldq : P.ldx;
+    const int64_t lda = P.lda;
+    const bool avec = P.avec != 0;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int li = lane & 15;
+    const int lg = lane >> 4;
+
+    // ---------------- global -> register staging ----------------
+    // A tile: non-transposed: SK_BM rows x 8 chunks;  transposed: BK rows x
+    // (SK_BM*SZ/16) chunks.  X tile: NT*16 rows x 8 chunks.
+    constexpr int A_CHUNKS = SK_BM * BK * SZ / 16;
+    constexpr int A_LD = A_CHUNKS / SK_THREADS;
+    constexpr int X_CHUNKS = NT * 16 * 8;
+    constexpr int X_LD = (X_CHUNKS + SK_THREADS - 1) / SK_THREADS;
+    i32x4 ra[A_LD];
+    i32x4 rx[X_LD];
+
+    auto load_tile = [&](int64_t k0) {
+        if constexpr (!TRANS) {
+#pragma unroll
+            for (int t = 0; t < A_LD; t++) {
+                int c = tid + t * SK_THREADS;
+                int r = c >> 3, ch = c & 7;
+                int64_t gr = row0 + r;
+                int64_t gk = k0 + ch * VEC;
+                if (gr < rows && gk < kend)
+                    ra[t] = load16<T, VEC>(A + gr * lda + gk, kend - gk, avec);
+                else
+                    ra[t] = i32x4{0, 0, 0, 0};
+            }
+        } else {
+            constexpr int CPR = SK_BM * SZ / 16;  // chunks per A row segment
+#pragma unroll
+            for (int t = 0; t < A_LD; t++) {
+                int c = tid + t * SK_THREADS;
+                int kr = c / CPR, ch = c % CPR;
+                int64_t gk = k0 + kr;
+                int64_t gc = row0 + ch * VEC;
+                if (gk < kend && gc < rows)
+                    ra[t] = load16<T, VEC>(A + gk * lda + gc, rows - gc, avec);
+                else
+                    ra[t] = i32x4{0, 0, 0, 0};
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < X_LD; t++) {
+            int c = tid + t * SK_THREADS;
+            int r = c >> 3, ch = c & 7;
+            int64_t gk = k0 + ch * VEC;
+            if (c < X_CHUNKS && r < lp && gk < kend)
+                rx[t] = load16<T, VEC>(X + (int64_t)r * ldx + gk, kend - gk, true);
+            else
+                rx[t] = i32x4{0, 0, 0, 0};
+        }
+    };
+
+    auto store_tile = [&](int buf) {
+        unsigned char* As = smem + buf * (ABYTES + XBYTES);
+        unsigned char* Xs = As + ABYTES;
+        if constexpr (!TRANS) {
+#pragma unroll
+            for (int t = 0; t < A_LD; t++) {
+                int c = tid + t * SK_THREADS;
+                int r = c >> 3, ch = c & 7;
+                *reinterpret_cast<i32x4*>(As + r * ROWB + ch * 16) = ra[t];
+            }
+        } else if constexpr (ATRANS_SCALAR) {
+            constexpr int CPR = SK_BM * SZ / 16;
+#pragma unroll
+            for (int t = 0; t < A_LD; t++) {
+                int c = tid + t * SK_THREADS;
+                int kr = c / CPR, ch = c % CPR;
+                *reinterpret_cast<i32x4*>(As + kr * AROWB + ch * 16) = ra[t];
+            }
+        } else {
+            // 1- and 2-byte formats: transpose into [output row][K] so that a
+            // lane's MFMA operand (consecutive K of one row) is one vector.
+            constexpr int CPR = SK_BM * SZ / 16;
+#pragma unroll
+            for (int t = 0; t < A_LD; t++) {
+                int c = tid + t * SK_THREADS;
+                int kr = c / CPR, ch = c % CPR;
+                union { i32x4 v; T e[VEC]; } u;
+                u.v = ra[t];
+#pragma unroll
+                for (int e = 0; e < VEC; e++)
+                    *reinterpret_cast<T*>(As + (ch * VEC + e) * ROWB + kr * SZ) = u.e[e];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < X_LD; t++) {
+            int c = tid + t * SK_THREADS;
+            if (c < X_CHUNKS) {
+                int r = c >> 3, ch = c & 7;
+                *reinterpret_cast<i32x4*>(Xs + r * ROWB + ch * 16) = rx[t];
+            }
+        }
+    };
+
+    // ---------------- accumulators ----------------
+    typedef typename std::conditional<PREC == P_F64, f64x4, f32x4>::type AccV;
+    AccV acc[SK_RT][NT];
+#pragma unroll
+    for (int r = 0; r < SK_RT; r++)
+#pragma unroll
+        for (int c = 0; c < NT; c++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc[r][c][e] = Acc(0);
+
+    const int wrow = wave * (SK_RT * 16);
+
+    auto compute_tile = [&](int buf) {
+        const unsigned char* As = smem + buf * (ABYTES + XBYTES);
+        const unsigned char* Xs = As + ABYTES;
+        if constexpr (PREC == P_F32 || PREC == P_F64) {
+            // One 16-byte vector holds VEC consecutive K of one lane: VEC MFMAs.
+#pragma unroll
+            for (int ss = 0; ss < BK / (4 * VEC); ss++) {
+                const int kk = ss * 4 * VEC + lg * VEC;  // this lane's first K slot
+                T av[SK_RT][VEC];
+#pragma unroll
+                for (int r = 0; r < SK_RT; r++) {
+                    const int orow = wrow + r * 16 + li;
+                    if constexpr (!TRANS) {
+                        union { i32x4 v; T e[VEC]; } u;
+                        u.v = *reinterpret_cast<const i32x4*>(As + orow * ROWB + kk * SZ);
+#pragma unroll
+                        for (int e = 0; e < VEC; e++) av[r][e] = u.e[e];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VEC; e++)
+                            av[r][e] = *reinterpret_cast<const T*>(As + (kk + e) * AROWB + orow * SZ);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NT; c++) {
+                    union { i32x4 v; T e[VEC]; } b;
+                    b.v = *reinterpret_cast<const i32x4*>(Xs + (c * 16 + li) * ROWB + kk * SZ);
+#pragma unroll
+                    for (int e = 0; e < VEC; e++)
+#pragma unroll
+                        for (int r = 0; r < SK_RT; r++) {
+                            if constexpr (PREC == P_F32)
+                                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][e], b.e[e], acc[r][c], 0, 0, 0);
+                            else
+                                acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][e], b.e[e], acc[r][c], 0, 0, 0);
+                        }
+                }
+            }
+        } else if constexpr (PREC == P_BF16) {
+#pragma unroll
+            for (int ss = 0; ss < BK / 32; ss++) {
+                const int kk = ss * 32 + lg * 8;
+                bf16x8 av[SK_RT];
+#pragma unroll
+                for (int r = 0; r < SK_RT; r++)
+                    av[r] = *reinterpret_cast<const bf16x8*>(As + (wrow + r * 16 + li) * ROWB + kk * 2);
+#pragma unroll
+                for (int c = 0; c < NT; c++) {
+                    bf16x8 bv = *reinterpret_cast<const bf16x8*>(Xs + (c * 16 + li) * ROWB + kk * 2);
+#pragma unroll
+                    for (int r = 0; r < SK_RT; r++)
+                        acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bv, acc[r][c], 0, 0, 0);
+                }
+            }
+        } else {  // FP8: one MFMA consumes 32 consecutive K bytes per lane
+            const int kk = lg * 32;
+            i32x8 av[SK_RT];
+#pragma unroll
+            for (int r = 0; r < SK_RT; r++) {
+                const unsigned char* p = As + (wrow + r * 16 + li) * ROWB + kk;
+                i32x4 lo = *reinterpret_cast<const i32x4*>(p);
+                i32x4 hi = *reinterpret_cast<const i32x4*>(p + 16);
+                av[r] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            }
+#pragma unroll
+            for (int c = 0; c < NT; c++) {
+                const unsigned char* p = Xs + (c * 16 + li) * ROWB + kk;
+                i32x4 lo = *reinterpret_cast<const i32x4*>(p);
+                i32x4 hi = *reinterpret_cast<const i32x4*>(p + 16);
+                i32x8 bv = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+#pragma unroll
+                for (int r = 0; r < SK_RT; r++)
+                    acc[r][c] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                        av[r], bv, acc[r][c], 0, 0, 0, 127, 0, 127);
+            }
+        }
+    };
+
+    // ---------------- main loop: double-buffered LDS ----------------
+    const int ntile = (int)((kend - kbeg + BK - 1) / BK);
+    if (ntile > 0) {
+        load_tile(kbeg);
+        store_tile(0);
+        __syncthreads();
+        for (int t = 0; t < ntile; t++) {
+            const bool more = (t + 1) < ntile;
+            if (more) load_tile(kbeg + (int64_t)(t + 1) * BK);
+            compute_tile(t & 1);
+            if (more) store_tile((t + 1) & 1);
+            __syncthreads();
+        }
+    }
+
+    // ---------------- epilogue: partial sums ----------------
+    Acc* __restrict__ out = reinterpret_cast<Acc*>(P.ypart) + (int64_t)split * rows * lp;
+#pragma unroll
+    for (int r = 0; r < SK_RT; r++)
+#pragma unroll
+        for (int c = 0; c < NT; c++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                // f32 forms: (row 4g + e, col i); f64 form: (row g + 4e, col i)
+                int tr = (PREC == P_F64) ? (lg + 4 * e) : (4 * lg + e);
+                int64_t gr = row0 + wrow + r * 16 + tr;
+                if (gr < rows) out[gr * lp + c * 16 + li] = acc[r][c][e];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers: one template instance per (format, column tiles, side).
+// ---------------------------------------------------------------------------
+template <int PREC, int NT, bool TRANS>
+static hipError_t launch_nt(const LaunchGroup& g, int iter, hipStream_t s) {
+    constexpr int lds = sk_lds_bytes<PREC, NT, TRANS>();
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_sketch<PREC, NT, TRANS>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sketch<PREC, NT, TRANS>), dim3(g.blocks), dim3(SK_THREADS), lds, s,
+                       g.probs, g.pidx, g.toff, g.count, iter);
+    return hipGetLastError();
+}
+
+template <int PREC, bool TRANS>
+static hipError_t launch_prec(const LaunchGroup& g, int nt, int iter, hipStream_t s) {
+    switch (nt) {
+#define NT_CASE(N) case N: return launch_nt<PREC, N, TRANS>(g, iter, s);
+        NT_CASE(1) NT_CASE(2) NT_CASE(3) NT_CASE(4) NT_CASE(5) NT_CASE(6) NT_CASE(7) NT_CASE(8)
+        NT_CASE(9) NT_CASE(10) NT_CASE(11) NT_CASE(12) NT_CASE(13) NT_CASE(14) NT_CASE(15)
+        NT_CASE(16) NT_CASE(17)
+#undef NT_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sketch(int prec, bool trans, int nt, const LaunchGroup& g, int iter,
+                         hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    switch (prec) {
+        case P_F64: return trans ? launch_prec<P_F64, true>(g, nt, iter, s) : launch_prec<P_F64, false>(g, nt, iter, s);
+        case P_F32: return trans ? launch_prec<P_F32, true>(g, nt, iter, s) : launch_prec<P_F32, false>(g, nt, iter, s);
+        case P_BF16: return trans ? launch_prec<P_BF16, true>(g, nt, iter, s) : launch_prec<P_BF16, false>(g, nt, iter, s);
+        case P_FP8: return trans ? launch_prec<P_FP8, true>(g, nt, iter, s) : launch_prec<P_FP8, false>(g, nt, iter, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+int sketch_rows_per_block() { return SK_BM; }
+int sketch_k_tile(int prec) {
+    switch (prec) {
+        case P_F64: return SkCfg<P_F64>::BK;
+        case P_F32: return SkCfg<P_F32>::BK;
+        case P_BF16: return SkCfg<P_BF16>::BK;
+        default: return SkCfg<P_FP8>::BK;
+    }
+}
+
+}  // namespace cor

@@ -1,0 +1,61 @@
+// Host-side launch interface of the device kernels (internal to libcorutv).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cor {
+
+struct Prob;
+
+// A launch over a group of problems: block b serves problem probs[pidx[j]]
+// with toff[j] <= b < toff[j + 1]; toff has count + 1 entries (device).
+struct LaunchGroup {
+    const Prob* probs;
+    const int32_t* pidx;
+    const int32_t* toff;
+    int32_t count;
+    int32_t blocks;
+};
+
+enum Side : int32_t { SIDE_M = 0, SIDE_N = 1 };
+
+// Passes over A (split-K partial sums).
+hipError_t launch_sketch(int prec, bool trans, int nt, const LaunchGroup& g, int iter,
+                         hipStream_t s);
+int sketch_rows_per_block();
+int sketch_k_tile(int prec);
+
+// Row-block kernels.
+constexpr int ROWS_PER_BLOCK = 64;  // rows per block of the sum / solve / assembly kernels
+hipError_t launch_omega(const LaunchGroup& g, hipStream_t s);          // blocks: ceil(n*l/2/256)
+hipError_t launch_make_op(const LaunchGroup& g, int side, hipStream_t s);  // blocks: ceil(lp*ld/256)
+hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s);
+// Gram partial sums of a row-major rows x l FP64 matrix picked by `src`.
+enum GramSrc : int32_t { GSRC_Y = 0, GSRC_QA = 1, GSRC_U = 2, GSRC_V = 3 };
+constexpr int GRAM_THREADS = 256;
+hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStream_t s);
+hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int nblk_per_prob, int iter,
+                              hipStream_t s);
+// dst = src R^{-1} by forward substitution, row by row.
+enum SolveMode : int32_t { SOLVE_Y_TO_QA = 0, SOLVE_Y_TO_Q = 1, SOLVE_QA_TO_Q = 2 };
+hipError_t launch_solve(const LaunchGroup& g, int side, int mode, int iter, hipStream_t s);
+// Column maxima of the FP64 factor and FP8 operand scales.
+hipError_t launch_op_scales(const LaunchGroup& g, int side, int iter, hipStream_t s);
+
+// One block per problem.
+enum CholMode : int32_t { CHOL_FIRST = 0, CHOL_SECOND = 1 };
+hipError_t launch_chol(const LaunchGroup& g, int mode, int iter, hipStream_t s);
+hipError_t launch_qrcp(const LaunchGroup& g, hipStream_t s);
+hipError_t launch_form_uv(const LaunchGroup& g, hipStream_t s);
+hipError_t launch_report(const LaunchGroup& g, int phase, hipStream_t s);
+hipError_t launch_normA(const LaunchGroup& g, hipStream_t s);
+hipError_t launch_explicit_m(const LaunchGroup& g, hipStream_t s);
+hipError_t launch_clear_flags(const LaunchGroup& g, hipStream_t s);
+
+// Stand-alone helpers of the C ABI.
+hipError_t launch_quantize(const float* a32, int64_t m, int64_t n, int64_t lda, int to, void* out,
+                           float* colscale, hipStream_t s);
+hipError_t launch_omega_raw(uint64_t seed, int64_t n, int32_t l, double* out, hipStream_t s);
+
+}  // namespace cor

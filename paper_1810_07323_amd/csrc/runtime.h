@@ -1,0 +1,31 @@
+// Internal interface between the plan executor (runtime.hip) and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/cor_utv.h"
+
+namespace cor {
+
+struct Plan;
+struct Prob;
+
+cor_status fail(cor_status st, const std::string& msg);
+cor_status hip_fail(hipError_t e, const char* what);
+
+// Build a plan for `count` problems.  async: allocate, upload and clear on
+// `astream` (stream-ordered; no device-wide synchronisation).
+cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* opts, Plan** out,
+                       hipStream_t astream, bool async);
+cor_status plan_run(Plan* P, hipStream_t s);
+cor_status plan_info(Plan* P, cor_info* infos, hipStream_t s);
+void plan_destroy(Plan* P, hipStream_t s);
+size_t plan_bytes(const Plan* P);
+const Prob& plan_desc(const Plan* P, int i);
+int plan_count(const Plan* P);
+int plan_report(const Plan* P);
+size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec);
+
+}  // namespace cor

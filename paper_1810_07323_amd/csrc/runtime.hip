@@ -1,0 +1,792 @@
+// Host runtime of libcorutv: plans (workspace layout, grouped launch tables,
+// the stage sequence of Alg. 3), the C ABI of include/cor_utv.h, and kernel
+// timing for roofline reports.  The served path lives in server.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cor_utv.h"
+#include "common.h"
+#include "kernels.h"
+#include "runtime.h"
+
+namespace cor {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+cor_status fail(cor_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+cor_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return COR_E_DEVICE;
+}
+
+#define HIPCHK(expr)                                                      \
+    do {                                                                  \
+        hipError_t e_ = (expr);                                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);                 \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel timing (roofline reports)
+// ---------------------------------------------------------------------------
+struct ProfState {
+    std::mutex mu;
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> free_ev;
+    double bytes = 0.0, flops = 0.0;
+    int64_t launches = 0;
+};
+static ProfState g_prof;
+
+static void prof_begin(hipStream_t s, hipEvent_t* a, hipEvent_t* b) {
+    *a = *b = nullptr;
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (g_prof.free_ev.empty()) {
+        hipEvent_t x, y;
+        if (hipEventCreate(&x) != hipSuccess) return;
+        if (hipEventCreate(&y) != hipSuccess) return;
+        g_prof.free_ev.push_back({x, y});
+    }
+    auto pr = g_prof.free_ev.back();
+    g_prof.free_ev.pop_back();
+    *a = pr.first;
+    *b = pr.second;
+    (void)hipEventRecord(*a, s);
+}
+
+static void prof_end(hipStream_t s, hipEvent_t a, hipEvent_t b, double bytes, double flops) {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.pending.push_back({a, b});
+    g_prof.bytes += bytes;
+    g_prof.flops += flops;
+    g_prof.launches += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+static int64_t roundup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static int prec_size(int p) { return p == P_F64 ? 8 : p == P_F32 ? 4 : p == P_BF16 ? 2 : 1; }
+
+struct Layout {
+    // per-problem sizes
+    int32_t l, lp, nt;
+    int64_t ldx, ldq;
+    int32_t s_ax, s_atx;
+    int64_t kc_ax, kc_atx;
+    int32_t rb_m, rb_n, gb_m, gb_n;
+    size_t off[24];
+    size_t total;
+};
+
+enum {
+    O_XOP, O_QOP, O_XSC, O_QSC, O_YPART, O_Y, O_QA, O_Q1, O_Q2, O_GPART, O_G, O_R, O_RACC,
+    O_QT, O_REP, O_FLAGS, O_PERM, O_COUNT
+};
+
+static void split_k(int64_t rows, int64_t K, int bk, int target, int32_t* s, int64_t* kc) {
+    const int64_t nrb = cdiv(rows, sketch_rows_per_block());
+    int64_t sp = std::max<int64_t>(1, cdiv(target, nrb));
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / (4 * bk)));
+    int64_t c = roundup(cdiv(K, sp), bk);
+    *kc = c;
+    *s = (int32_t)cdiv(K, c);
+}
+
+static void gram_chunks(int64_t rows, int lp, int target, int32_t* rb, int32_t* gb) {
+    const int nt = lp / 16;
+    const int ntu = nt * (nt + 1) / 2;
+    const int ngroups = (ntu + 31) / 32;
+    int64_t g = std::max<int64_t>(1, cdiv(target, ngroups));
+    g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(rows, 64)));
+    int64_t r = roundup(cdiv(rows, g), 4);
+    *rb = (int32_t)r;
+    *gb = (int32_t)cdiv(rows, r);
+}
+
+static int gram_groups(int lp) {
+    const int nt = lp / 16;
+    return (nt * (nt + 1) / 2 + 31) / 32;
+}
+
+static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_target,
+                          int gram_target) {
+    Layout L;
+    L.l = l;
+    L.lp = (int32_t)roundup(l, 16);
+    L.nt = L.lp / 16;
+    L.ldx = roundup(n, 64);
+    L.ldq = roundup(m, 64);
+    const int bk = sketch_k_tile(prec);
+    split_k(m, n, bk, sketch_target, &L.s_ax, &L.kc_ax);
+    split_k(n, m, bk, sketch_target, &L.s_atx, &L.kc_atx);
+    gram_chunks(m, L.lp, gram_target, &L.rb_m, &L.gb_m);
+    gram_chunks(n, L.lp, gram_target, &L.rb_n, &L.gb_n);
+    const int sz = prec_size(prec);
+    const int acc = prec == P_F64 ? 8 : 4;
+    size_t sizes[O_COUNT];
+    sizes[O_XOP] = (size_t)L.lp * L.ldx * sz;
+    sizes[O_QOP] = (size_t)L.lp * L.ldq * sz;
+    sizes[O_XSC] = (size_t)L.lp * 4;
+    sizes[O_QSC] = (size_t)L.lp * 4;
+    sizes[O_YPART] = (size_t)std::max((int64_t)L.s_ax * m, (int64_t)L.s_atx * n) * L.lp * acc;
+    const int64_t mx = std::max(m, n);
+    sizes[O_Y] = (size_t)mx * l * 8;
+    sizes[O_QA] = (size_t)mx * l * 8;
+    sizes[O_Q1] = (size_t)m * l * 8;
+    sizes[O_Q2] = (size_t)n * l * 8;
+    sizes[O_GPART] = (size_t)std::max(L.gb_m, L.gb_n) * l * l * 8;
+    sizes[O_G] = sizes[O_R] = sizes[O_RACC] = sizes[O_QT] = (size_t)l * l * 8;
+    sizes[O_REP] = 128 * 8;
+    sizes[O_FLAGS] = 64;
+    sizes[O_PERM] = (size_t)l * 4;
+    size_t off = 0;
+    for (int i = 0; i < O_COUNT; i++) {
+        L.off[i] = off;
+        off += (size_t)roundup((int64_t)sizes[i], 256);
+    }
+    L.total = off;
+    return L;
+}
+
+static bool valid_prec(int p) { return p >= COR_F64 && p <= COR_FP8; }
+
+static cor_status validate(const cor_problem& p) {
+    const int64_t l = (int64_t)p.k + p.p;
+    if (!p.A || !p.U || !p.T || !p.V) return fail(COR_E_INVAL, "null A, U, T or V");
+    if (!valid_prec(p.prec)) return fail(COR_E_INVAL, "unknown precision");
+    if (p.m < 1 || p.n < 1) return fail(COR_E_INVAL, "m and n must be positive");
+    if (p.k < 1) return fail(COR_E_INVAL, "k must be >= 1");
+    if (p.p < 0) return fail(COR_E_INVAL, "p must be >= 0");
+    if (p.q < 0 || p.q > 16) return fail(COR_E_INVAL, "q must be in [0, 16]");
+    if (l < 2) return fail(COR_E_INVAL, "l = k + p must be >= 2");
+    if (l >= std::min(p.m, p.n)) return fail(COR_E_INVAL, "l = k + p must be < min(m, n)");
+    if (l > LMAX) return fail(COR_E_INVAL, "l = k + p must be <= 264");
+    if (p.lda < p.n) return fail(COR_E_INVAL, "lda must be >= n");
+    if (p.prec == COR_FP8 && !p.colscale) return fail(COR_E_INVAL, "FP8 needs colscale");
+    return COR_OK;
+}
+
+struct Plan {
+    int device = 0;
+    int count = 0;
+    int max_q = 0;
+    int report = 0;
+    int prec_mix = 0;  // bitmask of precisions present
+    std::vector<cor_problem> reqs;
+    std::vector<Layout> lay;
+    std::vector<Prob> hp;     // host copies of the descriptors
+    void* mem = nullptr;      // device: descriptors + tables + workspace
+    size_t mem_bytes = 0;
+    Prob* d_probs = nullptr;
+
+    struct Grp {
+        LaunchGroup g{};
+        int nt = 0;
+        int prec = 0;
+        double bytes = 0, flops = 0;  // algorithmic cost of one launch
+    };
+    Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, solveM, solveN, uv, norm;
+    std::vector<Grp> skAX, skATX;  // per (precision, column tiles)
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool async = false;
+    std::vector<int32_t> tab_host;
+};
+
+// Build a launch table: per-problem block counts -> (pidx, toff) in device memory.
+struct TableBuilder {
+    std::vector<int32_t> host;  // concatenated [pidx..., toff...] of all tables
+    struct Ref { size_t pidx_off, toff_off; int count, blocks; };
+    Ref add(const std::vector<int>& probs, const std::vector<int64_t>& blocks) {
+        Ref r;
+        r.count = (int)probs.size();
+        r.pidx_off = host.size();
+        for (int p : probs) host.push_back(p);
+        r.toff_off = host.size();
+        int64_t acc = 0;
+        for (size_t i = 0; i < probs.size(); i++) {
+            host.push_back((int32_t)acc);
+            acc += blocks[i];
+        }
+        host.push_back((int32_t)acc);
+        r.blocks = (int)acc;
+        return r;
+    }
+};
+
+cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* opts,
+                       Plan** out, hipStream_t astream, bool async) {
+    if (!probs || count < 1 || !out) return fail(COR_E_INVAL, "no problems");
+    for (int i = 0; i < count; i++) {
+        cor_status st = validate(probs[i]);
+        if (st != COR_OK) return st;
+    }
+    Plan* P = new Plan();
+    HIPCHK(hipGetDevice(&P->device));
+    P->count = count;
+    P->report = opts ? opts->report : 0;
+    P->reqs.assign(probs, probs + count);
+    const int sk_target = std::max(16, 2048 / count);
+    const int gr_target = std::max(2, 256 / count);
+    size_t ws = 0;
+    std::vector<size_t> base(count);
+    for (int i = 0; i < count; i++) {
+        const cor_problem& q = probs[i];
+        P->lay.push_back(make_layout(q.m, q.n, q.k + q.p, q.prec, sk_target, gr_target));
+        base[i] = ws;
+        ws += P->lay.back().total;
+        P->max_q = std::max(P->max_q, (int)q.q);
+        P->prec_mix |= 1 << q.prec;
+    }
+
+    // Launch tables.
+    TableBuilder tb;
+    std::vector<int> all(count);
+    for (int i = 0; i < count; i++) all[i] = i;
+    auto per = [&](auto fn) {
+        std::vector<int64_t> b(count);
+        for (int i = 0; i < count; i++) b[i] = fn(i);
+        return tb.add(all, b);
+    };
+    auto R_omega = per([&](int i) { return cdiv(cdiv(probs[i].n * P->lay[i].l, 2), 256); });
+    auto R_opM = per([&](int i) { return cdiv(P->lay[i].lp * P->lay[i].ldq, 256); });
+    auto R_opN = per([&](int i) { return cdiv(P->lay[i].lp * P->lay[i].ldx, 256); });
+    auto R_sumM = per([&](int i) { return cdiv(probs[i].m, ROWS_PER_BLOCK); });
+    auto R_sumN = per([&](int i) { return cdiv(probs[i].n, ROWS_PER_BLOCK); });
+    auto R_gramM = per([&](int i) { return (int64_t)P->lay[i].gb_m * gram_groups(P->lay[i].lp); });
+    auto R_gramN = per([&](int i) { return (int64_t)P->lay[i].gb_n * gram_groups(P->lay[i].lp); });
+    auto R_red = per([&](int i) { return cdiv((int64_t)P->lay[i].l * P->lay[i].l, 256); });
+    auto R_small = per([&](int) { return (int64_t)1; });
+    auto R_solveM = per([&](int i) { return cdiv(probs[i].m, 32); });
+    auto R_solveN = per([&](int i) { return cdiv(probs[i].n, 32); });
+    auto R_uv = per([&](int i) { return cdiv(probs[i].m, 32) + cdiv(probs[i].n, 64); });
+    auto R_norm = per([&](int) { return (int64_t)64; });
+    // Sketch tables: one per (precision, column-tile count) class.
+    std::map<std::pair<int, int>, std::vector<int>> classes;
+    for (int i = 0; i < count; i++) classes[{probs[i].prec, P->lay[i].nt}].push_back(i);
+    struct SkRef { int prec, nt; TableBuilder::Ref ax, atx; double bax, fax, batx, fatx; };
+    std::vector<SkRef> skrefs;
+    const int64_t bm = sketch_rows_per_block();
+    for (auto& kv : classes) {
+        std::vector<int64_t> bax, batx;
+        double bytes_ax = 0, fl = 0, bytes_atx = 0;
+        for (int i : kv.second) {
+            const cor_problem& q = probs[i];
+            const Layout& L = P->lay[i];
+            bax.push_back(cdiv(q.m, bm) * L.s_ax);
+            batx.push_back(cdiv(q.n, bm) * L.s_atx);
+            const double sz = prec_size(q.prec);
+            const double abytes = (double)q.m * q.n * sz;
+            bytes_ax += abytes + (double)q.n * L.l * sz + (double)q.m * L.l * 4.0;
+            bytes_atx += abytes + (double)q.m * L.l * sz + (double)q.n * L.l * 4.0;
+            fl += 2.0 * q.m * q.n * L.l;
+        }
+        SkRef r{kv.first.first, kv.first.second, tb.add(kv.second, bax), tb.add(kv.second, batx),
+                bytes_ax, fl, bytes_atx, fl};
+        skrefs.push_back(r);
+    }
+
+    // One device allocation: descriptors | tables | workspaces.
+    const size_t desc_bytes = roundup(sizeof(Prob) * count, 256);
+    const size_t tab_bytes = roundup(tb.host.size() * sizeof(int32_t), 256);
+    P->mem_bytes = desc_bytes + tab_bytes + ws;
+    P->async = async;
+    hipError_t e = async ? hipMallocAsync(&P->mem, P->mem_bytes, astream)
+                         : hipMalloc(&P->mem, P->mem_bytes);
+    if (e != hipSuccess) {
+        delete P;
+        return fail(COR_E_NOMEM, "workspace allocation failed");
+    }
+    char* mem = (char*)P->mem;
+    P->d_probs = (Prob*)mem;
+    int32_t* d_tab = (int32_t*)(mem + desc_bytes);
+    char* d_ws = mem + desc_bytes + tab_bytes;
+
+    // Descriptors.
+    P->hp.resize(count);
+    for (int i = 0; i < count; i++) {
+        const cor_problem& q = probs[i];
+        const Layout& L = P->lay[i];
+        char* w = d_ws + base[i];
+        Prob& d = P->hp[i];
+        memset(&d, 0, sizeof(Prob));
+        d.A = q.A;
+        d.colscale = q.colscale;
+        d.m = q.m; d.n = q.n; d.lda = q.lda;
+        d.k = q.k; d.l = L.l; d.lp = L.lp; d.q = q.q;
+        d.prec = q.prec;
+        d.report = P->report;
+        const int sz = prec_size(q.prec);
+        d.avec = (((uintptr_t)q.A % 16) == 0 && (q.lda * sz) % 16 == 0) ? 1 : 0;
+        d.xop = w + L.off[O_XOP];
+        d.qop = w + L.off[O_QOP];
+        d.ldx = L.ldx; d.ldq = L.ldq;
+        d.xscale = (float*)(w + L.off[O_XSC]);
+        d.qscale = (float*)(w + L.off[O_QSC]);
+        d.ypart = w + L.off[O_YPART];
+        d.s_ax = L.s_ax; d.s_atx = L.s_atx; d.kc_ax = L.kc_ax; d.kc_atx = L.kc_atx;
+        d.Y = (double*)(w + L.off[O_Y]);
+        d.Qa = (double*)(w + L.off[O_QA]);
+        d.Q1 = (double*)(w + L.off[O_Q1]);
+        d.Q2 = (double*)(w + L.off[O_Q2]);
+        d.gpart = (double*)(w + L.off[O_GPART]);
+        d.rb_m = L.rb_m; d.rb_n = L.rb_n; d.gb_m = L.gb_m; d.gb_n = L.gb_n;
+        d.G = (double*)(w + L.off[O_G]);
+        d.R = (double*)(w + L.off[O_R]);
+        d.Racc = (double*)(w + L.off[O_RACC]);
+        d.Qt = (double*)(w + L.off[O_QT]);
+        d.rep = (double*)(w + L.off[O_REP]);
+        d.flags = (int32_t*)(w + L.off[O_FLAGS]);
+        d.U = q.U; d.T = q.T; d.V = q.V;
+        d.perm = q.perm ? q.perm : (int32_t*)(w + L.off[O_PERM]);
+        d.omega = q.omega;
+        d.seed = q.seed;
+    }
+    P->tab_host.swap(tb.host);
+    if (async) {
+        e = hipMemcpyAsync(P->d_probs, P->hp.data(), sizeof(Prob) * count, hipMemcpyHostToDevice,
+                           astream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_tab, P->tab_host.data(), P->tab_host.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, astream);
+        // Operand buffers are zero outside the written rows x l block.
+        if (e == hipSuccess) e = hipMemsetAsync(d_ws, 0, ws, astream);
+    } else {
+        e = hipMemcpy(P->d_probs, P->hp.data(), sizeof(Prob) * count, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(d_tab, P->tab_host.data(), P->tab_host.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(d_ws, 0, ws);
+    }
+    if (e != hipSuccess) {
+        if (async) (void)hipFreeAsync(P->mem, astream);
+        else (void)hipFree(P->mem);
+        delete P;
+        return hip_fail(e, "plan upload");
+    }
+    auto mk = [&](const TableBuilder::Ref& r) {
+        Plan::Grp g;
+        g.g.probs = P->d_probs;
+        g.g.pidx = d_tab + r.pidx_off;
+        g.g.toff = d_tab + r.toff_off;
+        g.g.count = r.count;
+        g.g.blocks = r.blocks;
+        return g;
+    };
+    P->omega = mk(R_omega); P->opM = mk(R_opM); P->opN = mk(R_opN);
+    P->sumM = mk(R_sumM); P->sumN = mk(R_sumN);
+    P->gramM = mk(R_gramM); P->gramN = mk(R_gramN);
+    P->redM = mk(R_red); P->redN = P->redM;
+    P->small = mk(R_small);
+    P->solveM = mk(R_solveM); P->solveN = mk(R_solveN);
+    P->uv = mk(R_uv); P->norm = mk(R_norm);
+    for (auto& r : skrefs) {
+        Plan::Grp a = mk(r.ax), b = mk(r.atx);
+        a.nt = b.nt = r.nt;
+        a.prec = b.prec = r.prec;
+        a.bytes = r.bax; a.flops = r.fax;
+        b.bytes = r.batx; b.flops = r.fatx;
+        P->skAX.push_back(a);
+        P->skATX.push_back(b);
+    }
+    *out = P;
+    return COR_OK;
+}
+
+static hipError_t run_sketch(const std::vector<Plan::Grp>& gs, bool trans, int iter,
+                             hipStream_t s) {
+    for (const auto& g : gs) {
+        hipEvent_t a, b;
+        prof_begin(s, &a, &b);
+        hipError_t e = launch_sketch(g.prec, trans, g.nt, g.g, iter, s);
+        if (e != hipSuccess) return e;
+        prof_end(s, a, b, g.bytes, g.flops);
+    }
+    return hipSuccess;
+}
+
+// The stage sequence of Alg. 3 for every problem of the plan.
+static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
+#define E(x)                                   \
+    do {                                       \
+        hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) return e_;       \
+    } while (0)
+    const bool fp8 = (P->prec_mix >> P_FP8) & 1;
+    E(launch_clear_flags(P->small.g, s));
+    if (P->report) E(launch_normA(P->norm.g, s));
+    E(launch_omega(P->omega.g, s));  // Q2 <- Omega (FP64)
+    if (fp8) E(launch_op_scales(P->small.g, SIDE_N, 0, s));
+    E(launch_make_op(P->opN.g, SIDE_N, s));  // X <- Omega in the pass format
+    for (int it = 0; it <= P->max_q; it++) {
+        // Y1 = A X, Q1 R1 = Y1 (CholeskyQR2)
+        E(run_sketch(P->skAX, false, it, s));
+        E(launch_sum(P->sumM.g, SIDE_M, it, s));
+        E(launch_gram(P->gramM.g, SIDE_M, GSRC_Y, it, s));
+        E(launch_gram_reduce(P->redM.g, SIDE_M, 0, it, s));
+        E(launch_chol(P->small.g, CHOL_FIRST, it, s));
+        E(launch_solve(P->solveM.g, SIDE_M, SOLVE_Y_TO_QA, it, s));
+        E(launch_gram(P->gramM.g, SIDE_M, GSRC_QA, it, s));
+        E(launch_gram_reduce(P->redM.g, SIDE_M, 0, it, s));
+        E(launch_chol(P->small.g, CHOL_SECOND, it, s));
+        E(launch_solve(P->solveM.g, SIDE_M, SOLVE_QA_TO_Q, it, s));
+        if (fp8) {
+            E(launch_op_scales(P->small.g, SIDE_M, it, s));
+            E(launch_make_op(P->opM.g, SIDE_M, s));
+        }
+        // Y2 = A^T Q1, Q2 R2 = Y2 (CholeskyQR2); X <- Q2
+        E(run_sketch(P->skATX, true, it, s));
+        E(launch_sum(P->sumN.g, SIDE_N, it, s));
+        E(launch_gram(P->gramN.g, SIDE_N, GSRC_Y, it, s));
+        E(launch_gram_reduce(P->redN.g, SIDE_N, 0, it, s));
+        E(launch_chol(P->small.g, CHOL_FIRST, it, s));
+        E(launch_solve(P->solveN.g, SIDE_N, SOLVE_Y_TO_QA, it, s));
+        E(launch_gram(P->gramN.g, SIDE_N, GSRC_QA, it, s));
+        E(launch_gram_reduce(P->redN.g, SIDE_N, 0, it, s));
+        E(launch_chol(P->small.g, CHOL_SECOND, it, s));
+        E(launch_solve(P->solveN.g, SIDE_N, SOLVE_QA_TO_Q, it, s));
+        if (fp8 && it < P->max_q) {
+            E(launch_op_scales(P->small.g, SIDE_N, it, s));
+            E(launch_make_op(P->opN.g, SIDE_N, s));
+        }
+    }
+    // M = Q1^T A Q2 = R2^T; M P = Qt T; U = Q1 Qt, V = Q2 P.
+    E(launch_qrcp(P->small.g, s));
+    E(launch_form_uv(P->uv.g, s));
+    if (P->report) {
+        E(launch_gram(P->gramM.g, SIDE_M, GSRC_U, -1, s));
+        E(launch_gram_reduce(P->redM.g, SIDE_M, 0, -1, s));
+        E(launch_report(P->small.g, 1, s));
+        E(launch_gram(P->gramN.g, SIDE_N, GSRC_V, -1, s));
+        E(launch_gram_reduce(P->redN.g, SIDE_N, 0, -1, s));
+        E(launch_report(P->small.g, 2, s));
+        E(launch_report(P->small.g, 3, s));
+    }
+    return hipSuccess;
+#undef E
+}
+
+cor_status plan_run(Plan* P, hipStream_t s) {
+    if (P->gexec) {
+        HIPCHK(hipGraphLaunch(P->gexec, s));
+        return COR_OK;
+    }
+    hipError_t e = plan_enqueue(P, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return COR_OK;
+}
+
+cor_status plan_capture(Plan* P, hipStream_t s) {
+    if (!s) return fail(COR_E_INVAL, "graph capture needs a non-null stream");
+    if (P->gexec) {
+        (void)hipGraphExecDestroy(P->gexec);
+        (void)hipGraphDestroy(P->graph);
+        P->gexec = nullptr;
+        P->graph = nullptr;
+    }
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const bool prof = g_prof.on;
+    g_prof.on = false;  // no event records inside the graph
+    hipError_t e = plan_enqueue(P, s);
+    g_prof.on = prof;
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) return hip_fail(e, "capture enqueue");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    P->graph = g;
+    HIPCHK(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
+    return COR_OK;
+}
+
+cor_status plan_info(Plan* P, cor_info* infos, hipStream_t s) {
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < P->count; i++) {
+        const Prob& d = P->hp[i];
+        int32_t flags = 0;
+        double rep[5] = {0, 0, 0, 0, 0};
+        HIPCHK(hipMemcpy(&flags, d.flags, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (P->report) HIPCHK(hipMemcpy(rep, d.rep, sizeof(rep), hipMemcpyDeviceToHost));
+        if (infos) {
+            cor_info& f = infos[i];
+            f.err_l = rep[0];
+            f.err_k = rep[1];
+            f.orth_u = rep[2];
+            f.orth_v = rep[3];
+            f.flags = flags;
+            f.l = d.l;
+        }
+        if (flags & FLAG_NONFINITE) return fail(COR_E_NUMERIC, "non-finite value in a Gram matrix");
+    }
+    return COR_OK;
+}
+
+void plan_destroy(Plan* P, hipStream_t s) {
+    if (!P) return;
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->mem) {
+        if (P->async) (void)hipFreeAsync(P->mem, s);
+        else (void)hipFree(P->mem);
+    }
+    delete P;
+}
+
+// Flags and report of every problem from a host copy of their device words
+// (used by the server, which reads them back asynchronously).
+const Prob& plan_desc(const Plan* P, int i) { return P->hp[i]; }
+int plan_count(const Plan* P) { return P->count; }
+int plan_report(const Plan* P) { return P->report; }
+
+size_t plan_bytes(const Plan* P) { return P->mem_bytes; }
+
+size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec) {
+    Layout L = make_layout(m, n, l, prec, 2048, 256);
+    return L.total + 256 + 1024;
+}
+
+// Cache of the last single-problem plan (reused when the same call repeats).
+struct Cache {
+    std::mutex mu;
+    std::vector<std::pair<std::vector<char>, Plan*>> items;
+};
+static Cache g_cache;
+
+static std::vector<char> key_of(const cor_problem& p, const cor_opts* o, int dev) {
+    std::vector<char> k(sizeof(cor_problem) + sizeof(cor_opts) + sizeof(int), 0);
+    memcpy(k.data(), &p, sizeof(p));
+    cor_opts oo{};
+    if (o) oo = *o;
+    memcpy(k.data() + sizeof(p), &oo, sizeof(oo));
+    memcpy(k.data() + sizeof(p) + sizeof(oo), &dev, sizeof(int));
+    return k;
+}
+
+cor_status run_single(const cor_problem& p, const cor_opts* opts, cor_info* info,
+                      hipStream_t s) {
+    cor_status st = validate(p);
+    if (st != COR_OK) return st;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::vector<char> key = key_of(p, opts, dev);
+    Plan* P = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache.mu);
+        for (auto& it : g_cache.items)
+            if (it.first == key) P = it.second;
+    }
+    if (!P) {
+        st = plan_create(&p, 1, opts, &P, nullptr, false);
+        if (st != COR_OK) return st;
+        std::lock_guard<std::mutex> lk(g_cache.mu);
+        if (g_cache.items.size() >= 4) {
+            plan_destroy(g_cache.items.front().second, nullptr);
+            g_cache.items.erase(g_cache.items.begin());
+        }
+        g_cache.items.push_back({key, P});
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    st = plan_run(P, s);
+    if (st != COR_OK) return st;
+    HIPCHK(hipEventRecord(e1, s));
+    st = plan_info(P, info, s);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (info) info->device_ms = ms;
+    return st;
+}
+
+void release_all() {
+    std::lock_guard<std::mutex> lk(g_cache.mu);
+    for (auto& it : g_cache.items) plan_destroy(it.second, nullptr);
+    g_cache.items.clear();
+}
+
+}  // namespace cor
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace cor;
+
+extern "C" {
+
+cor_status cor_utv(const void* A, int64_t m, int64_t n, int32_t k, int32_t p, int32_t q,
+                   uint64_t seed, int32_t prec, double* U, double* T, double* V, cor_info* info,
+                   void* stream) {
+    if (prec == COR_FP8) return fail(COR_E_INVAL, "COR_FP8 needs a column scale: use cor_utv_ex");
+    cor_problem pr{};
+    pr.A = A;
+    pr.m = m; pr.n = n; pr.lda = n;
+    pr.k = k; pr.p = p; pr.q = q;
+    pr.prec = prec;
+    pr.seed = seed;
+    pr.U = U; pr.T = T; pr.V = V;
+    return run_single(pr, nullptr, info, (hipStream_t)stream);
+}
+
+cor_status cor_utv_ex(const cor_problem* prob, const cor_opts* opts, cor_info* info,
+                      void* stream) {
+    if (!prob) return fail(COR_E_INVAL, "null problem");
+    return run_single(*prob, opts, info, (hipStream_t)stream);
+}
+
+cor_status cor_utv_batched(const cor_problem* probs, int32_t count, const cor_opts* opts,
+                           cor_info* infos, void* stream) {
+    if (count == 0) return COR_OK;
+    Plan* P = nullptr;
+    cor_status st = plan_create(probs, count, opts, &P, nullptr, false);
+    if (st != COR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        plan_destroy(P, nullptr);
+        return fail(COR_E_DEVICE, "event creation failed");
+    }
+    (void)hipEventRecord(e0, s);
+    st = plan_run(P, s);
+    (void)hipEventRecord(e1, s);
+    if (st == COR_OK) st = plan_info(P, infos, s);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (infos)
+        for (int i = 0; i < count; i++) infos[i].device_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan_destroy(P, nullptr);
+    return st;
+}
+
+cor_status cor_plan_create(const cor_problem* probs, int32_t count, const cor_opts* opts,
+                           cor_plan** plan) {
+    if (!plan) return fail(COR_E_INVAL, "null plan pointer");
+    Plan* P = nullptr;
+    cor_status st = plan_create(probs, count, opts, &P, nullptr, false);
+    if (st == COR_OK) *plan = reinterpret_cast<cor_plan*>(P);
+    return st;
+}
+
+cor_status cor_plan_run(cor_plan* plan, void* stream) {
+    if (!plan) return fail(COR_E_INVAL, "null plan");
+    return plan_run(reinterpret_cast<Plan*>(plan), (hipStream_t)stream);
+}
+
+cor_status cor_plan_capture(cor_plan* plan, void* stream) {
+    if (!plan) return fail(COR_E_INVAL, "null plan");
+    return plan_capture(reinterpret_cast<Plan*>(plan), (hipStream_t)stream);
+}
+
+cor_status cor_plan_info(cor_plan* plan, cor_info* infos, void* stream) {
+    if (!plan) return fail(COR_E_INVAL, "null plan");
+    return plan_info(reinterpret_cast<Plan*>(plan), infos, (hipStream_t)stream);
+}
+
+cor_status cor_plan_destroy(cor_plan* plan) {
+    plan_destroy(reinterpret_cast<Plan*>(plan), nullptr);
+    return COR_OK;
+}
+
+size_t cor_workspace_bytes(int64_t m, int64_t n, int32_t l, int32_t prec) {
+    if (m < 1 || n < 1 || l < 2 || l > LMAX || !valid_prec(prec)) return 0;
+    return workspace_bytes(m, n, l, prec);
+}
+
+cor_status cor_quantize(const float* A32, int64_t m, int64_t n, int64_t lda, int32_t to,
+                        void* out, float* colscale, void* stream) {
+    if (!A32 || !out || m < 0 || n < 0 || lda < n) return fail(COR_E_INVAL, "bad arguments");
+    if (to != COR_BF16 && to != COR_FP8) return fail(COR_E_INVAL, "target must be BF16 or FP8");
+    if (to == COR_FP8 && !colscale) return fail(COR_E_INVAL, "FP8 needs colscale");
+    hipError_t e = launch_quantize(A32, m, n, lda, to, out, colscale, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "quantize");
+    return COR_OK;
+}
+
+cor_status cor_omega(uint64_t seed, int64_t n, int32_t l, double* out, void* stream) {
+    if (!out || n < 0 || l < 0) return fail(COR_E_INVAL, "bad arguments");
+    hipError_t e = launch_omega_raw(seed, n, l, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "omega");
+    return COR_OK;
+}
+
+cor_status cor_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return COR_OK;
+}
+
+cor_status cor_profile_read(double* ms, int64_t* launches, double* bytes, double* flops) {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pend;
+    double b, f;
+    int64_t n;
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        pend.swap(g_prof.pending);
+        b = g_prof.bytes; f = g_prof.flops; n = g_prof.launches;
+        g_prof.bytes = g_prof.flops = 0.0;
+        g_prof.launches = 0;
+    }
+    double tot = 0.0;
+    for (auto& pr : pend) {
+        hipError_t e = hipEventSynchronize(pr.second);
+        if (e != hipSuccess) return hip_fail(e, "profile events");
+        float x = 0.0f;
+        e = hipEventElapsedTime(&x, pr.first, pr.second);
+        if (e != hipSuccess) return hip_fail(e, "profile events");
+        tot += x;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        for (auto& pr : pend) g_prof.free_ev.push_back(pr);
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = n;
+    if (bytes) *bytes = b;
+    if (flops) *flops = f;
+    return COR_OK;
+}
+
+const char* cor_status_string(int32_t st) {
+    switch (st) {
+        case COR_OK: return "ok";
+        case COR_E_INVAL: return "invalid argument";
+        case COR_E_NOMEM: return "out of memory";
+        case COR_E_DEVICE: return "device error";
+        case COR_E_NUMERIC: return "numerical failure";
+        case COR_E_BUSY: return "busy";
+        case COR_E_NOTFOUND: return "not found";
+    }
+    return "unknown status";
+}
+
+const char* cor_last_error(void) { return g_last_error.c_str(); }
+
+cor_status cor_release(void) {
+    release_all();
+    return COR_OK;
+}
+
+}  // extern "C"

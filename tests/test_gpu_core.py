@@ -1,0 +1,201 @@
+"""GPU parity of the CoR-UTV hot path against the FP64 CPU oracle.
+
+Every test calls the HIP library through its C ABI (ctypes binding) and
+compares with the oracle on the same seeded inputs and the same Gaussian test
+matrix.  Tolerances (relative errors eps are Frobenius norms relative to
+||A||_F, computed by the oracle's metric routine for both sides):
+  FP64 : |eps_gpu - eps_oracle| <= 1e-12, ||U^T U - I||, ||V^T V - I|| <= 1e-13
+  FP32 : |eps_gpu - eps_oracle| <= 1e-5
+  BF16 : eps_gpu <= 1.05 eps_oracle
+"""
+
+import numpy as np
+import pytest
+
+import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cu():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+    import paper_1810_07323_amd as cu
+
+    cu.lib()
+    return cu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    return torch.device("cuda:0")
+
+
+def _run_gpu(cu, dev, a_dev, k, p, q, om, colscale=None, report=True):
+    import torch
+
+    U, T, V, perm, info = cu.decompose(a_dev, k, p, q, omega=om, colscale=colscale, report=report)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), T.cpu().numpy(), V.cpu().numpy(), perm.cpu().numpy(), info
+
+
+def _compare_f64(orc, a, k, p, q, om, gpu, tag):
+    U, T, V, perm, info = gpu
+    ref = orc.cor_utv(a, k, p, q, om, want_intermediates=True)
+    mg = orc.metrics(a, U, T, V, k)
+    mo = orc.metrics(a, ref["U"], ref["T"], ref["V"], k)
+    print(f"[{tag}] eps_l gpu {mg['err_l']:.15e} oracle {mo['err_l']:.15e} "
+          f"d={abs(mg['err_l'] - mo['err_l']):.2e}; eps_k d={abs(mg['err_k'] - mo['err_k']):.2e}; "
+          f"orth {mg['orth_u']:.1e} {mg['orth_v']:.1e}; gap {ref['diag'][1]:.2e}; "
+          f"report err_l {info.err_l:.6e} flags {info.flags}")
+    return mg, mo, ref
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_f64_config1_full_size(cu, dev, orc, q):
+    """1000x1000 FP64, sigma_i = 1 (i<=10), 1e-3 0.9^(i-10) after, noise 1e-6;
+    k=10, p=5 (l=15)."""
+    import torch
+
+    a, _ = I.config_matrix("c1")
+    k, p = 10, 5
+    om = I.gaussian_omega(a.shape[1], k + p, 1)
+    gpu = _run_gpu(cu, dev, torch.from_numpy(a).to(dev), k, p, q, om)
+    mg, mo, ref = _compare_f64(orc, a, k, p, q, om, gpu, f"c1 q={q}")
+    U, T, V, perm, info = gpu
+    assert abs(mg["err_l"] - mo["err_l"]) <= 1e-12
+    assert abs(mg["err_k"] - mo["err_k"]) <= 1e-12
+    assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
+    assert np.array_equal(np.tril(T, -1), np.zeros_like(T))
+    assert np.all(np.diag(T) >= 0)
+    # The report of the library agrees with the explicit residual.
+    assert abs(info.err_l - mg["err_l"]) <= 1e-9
+    if ref["diag"][1] > 1e-8:  # pivots well separated: the factors are unique
+        assert np.array_equal(perm, ref["perm"])
+        scale = np.abs(ref["T"]).max()
+        print("  max |dT|/|T| %.2e  max |dU| %.2e  max |dV| %.2e" % (
+            np.abs(T - ref["T"]).max() / scale, np.abs(U - ref["U"]).max(),
+            np.abs(V - ref["V"]).max()))
+        assert np.abs(T - ref["T"]).max() <= 1e-10 * scale
+        assert np.abs(U - ref["U"]).max() <= 1e-8
+        assert np.abs(V - ref["V"]).max() <= 1e-8
+
+
+@pytest.mark.parametrize("m,n,k,p,q,lda_pad", [
+    (333, 517, 9, 7, 1, 0),      # m < n, ragged everywhere
+    (1037, 291, 30, 3, 2, 5),    # lda > n, l = 33 (three column tiles, ragged)
+    (700, 650, 70, 10, 0, 0),    # l = 80 (five column tiles)
+])
+def test_f64_ragged_shapes(cu, dev, orc, m, n, k, p, q, lda_pad):
+    import torch
+
+    r = min(m, n)
+    a, _ = I.lowrank(m, n, np.exp(-np.arange(1, r + 1) / 25.0), seed=m + n)
+    om = I.gaussian_omega(n, k + p, 2)
+    full = np.zeros((m, n + lda_pad))
+    full[:, :n] = a
+    A = torch.from_numpy(full).to(dev)[:, :n]  # strided view: lda = n + lda_pad
+    gpu = _run_gpu(cu, dev, A, k, p, q, om)
+    mg, mo, ref = _compare_f64(orc, a, k, p, q, om, gpu, f"ragged {m}x{n} l={k + p} q={q}")
+    assert abs(mg["err_l"] - mo["err_l"]) <= 1e-12
+    assert abs(mg["err_k"] - mo["err_k"]) <= 1e-12
+    assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
+
+
+def test_f32_scaled_config2(cu, dev, orc):
+    """The FP32 workload's recipe (rank-r Haar, sigma_i = exp(-i/40), k=100,
+    p=10, q=2) at 1500x1500 with rank 200 so the oracle finishes in seconds."""
+    import torch
+
+    m = n = 1500
+    a, _ = I.lowrank(m, n, I.spectrum("exp40", 200), seed=202)
+    k, p, q = 100, 10, 2
+    om = I.gaussian_omega(n, k + p, 3)
+    A32 = torch.from_numpy(a.astype(np.float32)).to(dev)
+    U, T, V, perm, info = _run_gpu(cu, dev, A32, k, p, q, om)
+    ref = orc.cor_utv(a, k, p, q, om)
+    mg = orc.metrics(a, U, T, V, k)
+    mo = orc.metrics(a, ref["U"], ref["T"], ref["V"], k)
+    print(f"[f32] eps_l gpu {mg['err_l']:.10e} oracle {mo['err_l']:.10e} "
+          f"d={abs(mg['err_l'] - mo['err_l']):.2e} eps_k d={abs(mg['err_k'] - mo['err_k']):.2e} "
+          f"orth {mg['orth_u']:.1e} {mg['orth_v']:.1e}")
+    assert abs(mg["err_l"] - mo["err_l"]) <= 1e-5
+    assert abs(mg["err_k"] - mo["err_k"]) <= 1e-5
+    assert mg["orth_u"] <= 1e-12 and mg["orth_v"] <= 1e-12
+
+
+def test_omega_generator_matches_oracle(cu, dev, orc):
+    import torch
+
+    n, l = 1001, 37
+    out = torch.empty((n, l), dtype=torch.float64, device=dev)
+    cu.check(cu.cor_omega(12345, n, l, out), "cor_omega")
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    h = orc.omega(12345, n, l)
+    # same integers, same formulas; device and host libm differ by a few ulp
+    assert np.all(np.abs(g - h) <= 1e-14 * np.maximum(1.0, np.abs(h)))
+
+
+def test_seeded_decomposition_matches_oracle_with_its_own_omega(cu, dev, orc):
+    """cor_utv(seed) draws Omega on the device; the oracle draws its own copy
+    of the same stream."""
+    import torch
+
+    m, n, k, p, q, seed = 400, 300, 12, 6, 1, 99
+    a, _ = I.lowrank(m, n, np.exp(-np.arange(1, 301) / 10.0), seed=5)
+    A = torch.from_numpy(a).to(dev)
+    l = k + p
+    U = torch.empty((m, l), dtype=torch.float64, device=dev)
+    T = torch.empty((l, l), dtype=torch.float64, device=dev)
+    V = torch.empty((n, l), dtype=torch.float64, device=dev)
+    st, info = cu.cor_utv(A, m, n, k, p, q, seed, cu.COR_F64, U, T, V)
+    cu.check(st, "cor_utv")
+    torch.cuda.synchronize()
+    ref = orc.cor_utv(a, k, p, q, orc.omega(seed, n, l))
+    mg = orc.metrics(a, U.cpu().numpy(), T.cpu().numpy(), V.cpu().numpy(), k)
+    mo = orc.metrics(a, ref["U"], ref["T"], ref["V"], k)
+    assert abs(mg["err_l"] - mo["err_l"]) <= 1e-12
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_quantize_bit_exact(cu, dev, orc, fmt):
+    import torch
+
+    rng = np.random.default_rng(8)
+    a = (rng.standard_normal((257, 190)) * np.logspace(-4, 3, 190)[None, :]).astype(np.float32)
+    a[:, 7] = 0.0
+    A = torch.from_numpy(a).to(dev)
+    if fmt == "bf16":
+        out = torch.empty(a.shape, dtype=torch.int16, device=dev)
+        cu.check(cu.cor_quantize(A, cu.COR_BF16, out), "quantize")
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint16)
+        assert np.array_equal(got, orc.quantize_bf16(a))
+    else:
+        out = torch.empty(a.shape, dtype=torch.uint8, device=dev)
+        s = torch.empty(a.shape[1], dtype=torch.float32, device=dev)
+        cu.check(cu.cor_quantize(A, cu.COR_FP8, out, s), "quantize")
+        torch.cuda.synchronize()
+        codes, sc = orc.quantize_fp8(a)
+        assert np.array_equal(s.cpu().numpy(), sc)
+        assert np.array_equal(out.cpu().numpy(), codes)
+
+
+def test_invalid_arguments_are_rejected(cu, dev):
+    import torch
+
+    A = torch.zeros((50, 40), dtype=torch.float64, device=dev)
+    U = torch.empty((50, 40), dtype=torch.float64, device=dev)
+    T = torch.empty((40, 40), dtype=torch.float64, device=dev)
+    V = torch.empty((40, 40), dtype=torch.float64, device=dev)
+    st, _ = cu.cor_utv(A, 50, 40, 30, 10, 0, 1, cu.COR_F64, U, T, V)  # l = 40 = min(m, n)
+    assert st == cu.COR_E_INVAL
+    st, _ = cu.cor_utv(A, 50, 40, 0, 5, 0, 1, cu.COR_F64, U, T, V)  # k = 0
+    assert st == cu.COR_E_INVAL
+    st, _ = cu.cor_utv(A, 50, 40, 5, 5, 0, 1, cu.COR_FP8, U, T, V)  # FP8 without scale
+    assert st == cu.COR_E_INVAL
