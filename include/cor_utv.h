@@ -101,8 +101,10 @@ typedef struct {
 } cor_problem;
 
 typedef struct {
-    int32_t report;     /* 0: nothing; 1: fill err_l, err_k, orth_u, orth_v of cor_info          */
-    int32_t explicit_m; /* 1: form M = Q1^T (A Q2) with one more pass over A (checking mode)     */
+    int32_t report;      /* 0: nothing; 1: fill err_l, err_k, orth_u, orth_v of cor_info         */
+    int32_t cholqr2_all; /* 0 (default): one CholeskyQR pass after each product inside the power  */
+                         /*   loop and two for the final pair (the spans are the same in exact    */
+                         /*   arithmetic); 1: two passes after every product                      */
 } cor_opts;
 
 /* ---------------------------------------------------------------------------
@@ -115,7 +117,7 @@ cor_status cor_utv(const void* A, int64_t m, int64_t n, int32_t k, int32_t p, in
                    uint64_t seed, int32_t prec, double* U, double* T, double* V,
                    cor_info* info, void* stream);
 
-/* Same with every option; opts may be NULL (defaults: report 0, explicit_m 0). */
+/* Same with every option; opts may be NULL (defaults: report 0, cholqr2_all 0). */
 cor_status cor_utv_ex(const cor_problem* prob, const cor_opts* opts, cor_info* info,
                       void* stream);
 

@@ -38,7 +38,7 @@ class cor_problem(C.Structure):
 
 
 class cor_opts(C.Structure):
-    _fields_ = [("report", C.c_int32), ("explicit_m", C.c_int32)]
+    _fields_ = [("report", C.c_int32), ("cholqr2_all", C.c_int32)]
 
 
 class cor_server_cfg(C.Structure):

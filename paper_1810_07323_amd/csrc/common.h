@@ -35,7 +35,7 @@ struct Prob {
     const float* colscale;  // FP8: n column scales of A
     int64_t m, n, lda;
     int32_t k, l, lp, q;    // l = k + p, lp = l rounded up to 16
-    int32_t prec, explicit_m, report, avec;  // avec: A rows 16-byte aligned
+    int32_t prec, cholqr2_all, report, avec;  // avec: A rows 16-byte aligned
 
     // Operand copies of the skinny factors, stored transposed: [lp][ld]
     // (row c holds column c of the factor), in the pass format.
@@ -61,8 +61,11 @@ struct Prob {
     int32_t gb_m, gb_n;  // number of Gram blocks on each side
     double* G;     // l x l reduced Gram
     double* R;     // l x l current Cholesky factor (upper)
-    double* Racc;  // l x l accumulated R of the orthonormalisation
-    double* Qt;    // l x l orthogonal factor of the QRCP
+    double* Rinv;  // l x l its inverse (upper)
+    double* Racc;  // l x l R of the first CholeskyQR pass
+    double* R2;    // l x l R factor of the last Y2 = A^T Q1 (M = R2^T)
+    double* Qt;    // l x l reflectors of the QRCP (row j = v_j)
+    double* tau;   // 2 LMAX: tau[j] of the reflectors, then the column signs of T
     double* rep;   // 16 doubles of report scratch
     int32_t* flags;
 
@@ -75,6 +78,13 @@ struct Prob {
     const double* omega;  // optional caller test matrix (n x l FP64)
     uint64_t seed;
 };
+
+// Whether the orthonormalisation of this iteration takes the second
+// CholeskyQR pass: always for the final pair (iteration q), and inside the
+// power loop only when asked for.  iter < 0 marks calls outside the loop.
+__device__ __forceinline__ bool second_pass(const Prob& P, int iter) {
+    return iter < 0 || iter == P.q || P.cholqr2_all != 0;
+}
 
 __device__ __forceinline__ int find_group(const int32_t* __restrict__ toff, int cnt, int b) {
     int lo = 0, hi = cnt - 1;
@@ -94,6 +104,24 @@ template <> struct PrecT<P_FP8> { typedef uint8_t T; typedef float Acc; static c
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// DPP lane moves of a double (two 32-bit halves); CTRL is a DPP control word.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over each aligned group of 8 lanes, result in every lane of the group:
+// swap neighbours (quad_perm 1,0,3,2), swap pairs (quad_perm 2,3,0,1), then
+// mirror each half-row of 8 (row_half_mirror), which pairs the two quads.
+__device__ __forceinline__ double sum8_dpp(double v) {
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
     return v;
 }
 

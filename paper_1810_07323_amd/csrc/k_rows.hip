@@ -4,7 +4,7 @@
 //   - the fixed-order reduction of split-K partial sums into the FP64 sketch;
 //   - CholeskyQR pieces of the orthonormalisation (QR of C1 and C2, Alg. 3):
 //     Gram partial sums on FP64 MFMA, their fixed-order reduction, and the
-//     row-wise triangular solve Q = Y R^{-1}.
+//     products Q = Y R^{-1}; the assembly U = Q1 Qt and V = Q2 P.
 #include <type_traits>
 
 #include "common.h"
@@ -178,30 +178,9 @@ hipError_t launch_op_scales(const LaunchGroup& g, int side, int iter, hipStream_
 // ---------------------------------------------------------------------------
 // Split-K reduction: Y[r][c] = sum_s ypart[s][r][c], s in increasing order,
 // in FP64; FP8 scale folding (m-side: column scale of X; n-side: column
-// scale of A on rows and of Q1 on columns).  Blocks of ROWS_PER_BLOCK rows.
+// scale of A on rows and of Q1 on columns).  One thread per 4 columns of a
+// row (16-byte loads of the FP32 partials).
 // ---------------------------------------------------------------------------
-template <typename Acc>
-__device__ void sum_body(const Prob& P, int side, int local) {
-    const int64_t rows = side == SIDE_M ? P.m : P.n;
-    const int S = side == SIDE_M ? P.s_ax : P.s_atx;
-    const Acc* yp = reinterpret_cast<const Acc*>(P.ypart);
-    const int64_t r0 = (int64_t)local * ROWS_PER_BLOCK;
-    const int l = P.l, lp = P.lp;
-    const bool fp8 = P.prec == P_FP8;
-    for (int e = threadIdx.x; e < ROWS_PER_BLOCK * l; e += 256) {
-        const int rr = e / l, c = e % l;
-        const int64_t r = r0 + rr;
-        if (r >= rows) break;
-        double acc = 0.0;
-        for (int sp = 0; sp < S; sp++) acc += (double)yp[((int64_t)sp * rows + r) * lp + c];
-        if (fp8) {
-            if (side == SIDE_M) acc *= (double)P.xscale[c];
-            else acc *= (double)P.colscale[r] * (double)P.qscale[c];
-        }
-        P.Y[r * l + c] = acc;
-    }
-}
-
 __global__ __launch_bounds__(256) void k_sum(const Prob* __restrict__ probs,
                                              const int32_t* __restrict__ pidx,
                                              const int32_t* __restrict__ toff, int cnt, int side,
@@ -209,8 +188,42 @@ __global__ __launch_bounds__(256) void k_sum(const Prob* __restrict__ probs,
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter > P.q) return;
-    if (P.prec == P_F64) sum_body<double>(P, side, local);
-    else sum_body<float>(P, side, local);
+    const int64_t rows = side == SIDE_M ? P.m : P.n;
+    const int S = side == SIDE_M ? P.s_ax : P.s_atx;
+    const int l = P.l, lp = P.lp, nq = lp / 4;
+    const int64_t idx = (int64_t)local * 256 + threadIdx.x;
+    const int64_t r = idx / nq;
+    const int c0 = (int)(idx % nq) * 4;
+    if (r >= rows || c0 >= l) return;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (P.prec == P_F64) {
+        const double* yp = reinterpret_cast<const double*>(P.ypart);
+#pragma unroll 4
+        for (int sp = 0; sp < S; sp++) {
+            const double* p = yp + ((int64_t)sp * rows + r) * lp + c0;
+            const double2 u = *reinterpret_cast<const double2*>(p);
+            const double2 v = *reinterpret_cast<const double2*>(p + 2);
+            acc[0] += u.x; acc[1] += u.y; acc[2] += v.x; acc[3] += v.y;
+        }
+    } else {
+        const float* yp = reinterpret_cast<const float*>(P.ypart);
+#pragma unroll 8
+        for (int sp = 0; sp < S; sp++) {
+            const float4 u = *reinterpret_cast<const float4*>(yp + ((int64_t)sp * rows + r) * lp + c0);
+            acc[0] += (double)u.x; acc[1] += (double)u.y; acc[2] += (double)u.z; acc[3] += (double)u.w;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const int c = c0 + e;
+        if (c >= l) break;
+        double v = acc[e];
+        if (P.prec == P_FP8) {
+            if (side == SIDE_M) v *= (double)P.xscale[c];
+            else v *= (double)P.colscale[r] * (double)P.qscale[c];
+        }
+        P.Y[r * l + c] = v;
+    }
 }
 
 hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s) {
@@ -224,11 +237,12 @@ hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s) {
 // Gram partial sums G_b = Z_b^T Z_b of a row chunk Z_b of an FP64 rows x l
 // matrix, on FP64 MFMA 16x16x4.  A block is (row chunk, group of upper
 // 16x16 tiles); each wave holds GT_PER_WAVE tile accumulators across the
-// whole chunk.  Partials: gpart[chunk][l][l], upper tiles only (entries with
-// a <= b are all written).
+// chunk, whose rows are staged through LDS 32 at a time.  Partials:
+// gpart[chunk][l][l], upper tiles only (every entry with a <= b is written).
 // ---------------------------------------------------------------------------
 constexpr int GT_PER_WAVE = 8;
 constexpr int GT_PER_BLOCK = 4 * GT_PER_WAVE;
+constexpr int GR_ROWS = 32;
 
 __device__ __forceinline__ void tile_of(int t, int nt, int& ta, int& tb) {
     // t-th upper tile (ta <= tb) in row-major order over ta.
@@ -238,15 +252,18 @@ __device__ __forceinline__ void tile_of(int t, int nt, int& ta, int& tb) {
     tb = a + rem;
 }
 
+template <int SRC>
 __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ probs,
                                                       const int32_t* __restrict__ pidx,
                                                       const int32_t* __restrict__ toff, int cnt,
-                                                      int side, int src, int iter) {
+                                                      int side, int iter) {
+    extern __shared__ __align__(16) double zs[];  // GR_ROWS x lp
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter >= 0 && iter > P.q) return;
-    const int l = P.l;
-    const int nt = P.lp / 16;
+    if (SRC == GSRC_QA && !second_pass(P, iter)) return;
+    const int l = P.l, lp = P.lp;
+    const int nt = lp / 16;
     const int ntu = nt * (nt + 1) / 2;
     const int ngroups = (ntu + GT_PER_BLOCK - 1) / GT_PER_BLOCK;
     const int chunk = local / ngroups;
@@ -255,7 +272,7 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     const int rb = side == SIDE_M ? P.rb_m : P.rb_n;
     const int64_t r0 = (int64_t)chunk * rb;
     const int64_t r1 = min(rows, r0 + rb);
-    const double* Z = src == GSRC_Y ? P.Y : src == GSRC_QA ? P.Qa : src == GSRC_U ? P.U : P.V;
+    const double* Z = SRC == GSRC_Y ? P.Y : SRC == GSRC_QA ? P.Qa : SRC == GSRC_U ? P.U : P.V;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -269,17 +286,24 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
         tile_of(act[t] ? tt : 0, nt, ta[t], tb[t]);
         acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
     }
-    for (int64_t kb = r0; kb < r1; kb += 4) {  // uniform trip count across the wave
-        const int64_t r = kb + lg;
-        const bool rv = r < r1;
-        const double* zr = Z + (rv ? r : r0) * l;
+    for (int64_t rs = r0; rs < r1; rs += GR_ROWS) {
+        __syncthreads();
+#pragma unroll 8
+        for (int e = threadIdx.x; e < GR_ROWS * lp; e += GRAM_THREADS) {
+            const int rr = e / lp, c = e % lp;
+            const int64_t r = rs + rr;
+            zs[e] = (r < r1 && c < l) ? Z[r * l + c] : 0.0;
+        }
+        __syncthreads();
 #pragma unroll
-        for (int t = 0; t < GT_PER_WAVE; t++) {
-            if (!act[t]) continue;
-            const int ca = ta[t] * 16 + li, cb = tb[t] * 16 + li;
-            const double a = (rv && ca < l) ? zr[ca] : 0.0;
-            const double b = (rv && cb < l) ? zr[cb] : 0.0;
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        for (int kk = 0; kk < GR_ROWS; kk += 4) {
+            const double* zr = zs + (kk + lg) * lp;
+#pragma unroll
+            for (int t = 0; t < GT_PER_WAVE; t++) {
+                if (!act[t]) continue;
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(zr[ta[t] * 16 + li], zr[tb[t] * 16 + li],
+                                                             acc[t], 0, 0, 0);
+            }
         }
     }
     double* out = P.gpart + (int64_t)chunk * l * l;
@@ -295,117 +319,195 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     }
 }
 
-hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStream_t s) {
-    if (g.blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gram, dim3(g.blocks), dim3(GRAM_THREADS), 0, s, g.probs, g.pidx, g.toff,
-                       g.count, side, src, iter);
+template <int SRC>
+static hipError_t launch_gram_t(const LaunchGroup& g, int side, int iter, hipStream_t s) {
+    const size_t lds = sizeof(double) * GR_ROWS * LPMAX;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_gram<SRC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_gram<SRC>, dim3(g.blocks), dim3(GRAM_THREADS), lds, s, g.probs, g.pidx,
+                       g.toff, g.count, side, iter);
     return hipGetLastError();
 }
 
-// G[a][b] = G[b][a] = sum over chunks (increasing) of gpart[chunk][min][max].
+hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    switch (src) {
+        case GSRC_Y: return launch_gram_t<GSRC_Y>(g, side, iter, s);
+        case GSRC_QA: return launch_gram_t<GSRC_QA>(g, side, iter, s);
+        case GSRC_U: return launch_gram_t<GSRC_U>(g, side, iter, s);
+        case GSRC_V: return launch_gram_t<GSRC_V>(g, side, iter, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// G[a][b] = G[b][a] = sum over chunks of gpart[chunk][min][max].  A block
+// covers 64 entries; its four waves add chunks c = w (mod 4) in increasing
+// order and the four parts are added in wave order: a fixed summation order.
 __global__ __launch_bounds__(256) void k_gram_reduce(const Prob* __restrict__ probs,
                                                      const int32_t* __restrict__ pidx,
                                                      const int32_t* __restrict__ toff, int cnt,
-                                                     int side, int iter) {
+                                                     int side, int second, int iter) {
+    __shared__ double part[4][64];
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter >= 0 && iter > P.q) return;
+    if (second && !second_pass(P, iter)) return;
     const int l = P.l;
-    const int e = local * 256 + threadIdx.x;
-    if (e >= l * l) return;
-    const int a = e / l, b = e % l;
-    const int lo = min(a, b), hi = max(a, b);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e = local * 64 + lane;
     const int nb = side == SIDE_M ? P.gb_m : P.gb_n;
     double s = 0.0;
-    for (int c = 0; c < nb; c++) s += P.gpart[(int64_t)c * l * l + (int64_t)lo * l + hi];
-    P.G[e] = s;
-    if (!isfinite(s)) atomicOr(P.flags, FLAG_NONFINITE);
+    if (e < l * l) {
+        const int a = e / l, b = e % l;
+        const int64_t o = (int64_t)min(a, b) * l + max(a, b);
+        const int64_t ll = (int64_t)l * l;
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int c = wave;
+        for (; c + 12 < nb; c += 16) {
+            s += P.gpart[c * ll + o];
+            s1 += P.gpart[(c + 4) * ll + o];
+            s2 += P.gpart[(c + 8) * ll + o];
+            s3 += P.gpart[(c + 12) * ll + o];
+        }
+        for (; c < nb; c += 4) s += P.gpart[c * ll + o];
+        s = (s + s1) + (s2 + s3);
+    }
+    part[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && e < l * l) {
+        const double g = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        P.G[e] = g;
+        if (!isfinite(g)) atomicOr(P.flags, FLAG_NONFINITE);
+    }
 }
 
-hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int nblk, int iter, hipStream_t s) {
-    (void)nblk;
+hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int iter, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gram_reduce, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff,
-                       g.count, side, iter);
+                       g.count, side, second, iter);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Row-wise forward substitution  X R = Z  (R upper, l x l, FP64):
-//   X[r][c] = (Z[r][c] - sum_{a<c} X[r][a] R[a][c]) / R[c][c].
-// Eight lanes share a row; lane k owns the columns a = k (mod 8) of the dot
-// products, so it only ever reads back values it wrote itself.  Rows are
-// staged in LDS; the result is written coalesced, optionally with the
-// transposed operand copy in the pass format.
+// dst = src S for a block of AP_ROWS rows, S l x l FP64 (R^{-1} of a
+// CholeskyQR pass).  The rows sit in LDS; S streams through LDS in panels as
+// large as the remaining LDS allows (all of S at l <= 122); each thread
+// accumulates 8 rows x NJ columns (columns cg + 64 j).  Optionally writes
+// the transposed operand copy of dst in the pass format.
+// The stage (source, destination, right factor) is a template parameter: a
+// run-time switch over these pointers was mis-compiled by the gfx950 backend
+// (the default branch kept the source of another case).
 // ---------------------------------------------------------------------------
-constexpr int SOLVE_ROWS = 32;
-constexpr int SOLVE_PANEL = 16;  // columns of R staged in LDS at a time
+constexpr int AP_ROWS = 32;
+constexpr int AP_LDS_DOUBLES = 19456;  // 152 KB
 
 template <typename T>
 __device__ void write_op_rows(const Prob& P, int side, int64_t r0, int nrows, const double* xs) {
     const int l = P.l;
     T* op = reinterpret_cast<T*>(side == SIDE_M ? P.qop : P.xop);
     const int64_t ld = side == SIDE_M ? P.ldq : P.ldx;
-    for (int e = threadIdx.x; e < l * SOLVE_ROWS; e += 256) {
-        const int c = e / SOLVE_ROWS, rr = e % SOLVE_ROWS;
+    for (int e = threadIdx.x; e < l * AP_ROWS; e += 256) {
+        const int c = e / AP_ROWS, rr = e % AP_ROWS;
         if (rr < nrows) op[(int64_t)c * ld + r0 + rr] = conv_op<T>(xs[rr * l + c], 1.0f);
     }
 }
 
-__global__ __launch_bounds__(256) void k_solve(const Prob* __restrict__ probs,
+template <int MODE, int NJ>
+__global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
                                                const int32_t* __restrict__ pidx,
                                                const int32_t* __restrict__ toff, int cnt,
-                                               int side, int mode, int iter) {
+                                               int side, int iter) {
     extern __shared__ __align__(16) double lds[];
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
-    if (iter > P.q) return;
+    if (iter >= 0 && iter > P.q) return;
+    const bool two = second_pass(P, iter);
+    if (MODE == AP_QA_RINV_Q && !two) return;
     const int l = P.l;
-    double* xs = lds;                         // SOLVE_ROWS x l
-    double* rp = lds + SOLVE_ROWS * l;        // SOLVE_PANEL x l : rp[cc][a] = R[a][c0 + cc]
+    constexpr int SPW = 64 * NJ;
+    double* xs = lds;                 // AP_ROWS x l
+    double* sp = lds + AP_ROWS * l;   // PR x SPW
+    const int PR = min(l, (AP_LDS_DOUBLES - AP_ROWS * l) / SPW);
     const int64_t rows = side == SIDE_M ? P.m : P.n;
-    const int64_t r0 = (int64_t)local * SOLVE_ROWS;
-    const int nrows = (int)min((int64_t)SOLVE_ROWS, rows - r0);
-    const double* Z = mode == SOLVE_QA_TO_Q ? P.Qa : P.Y;
-    double* D = mode == SOLVE_Y_TO_QA ? P.Qa : (side == SIDE_M ? P.Q1 : P.Q2);
-    const double* __restrict__ R = P.R;
-
-    for (int e = threadIdx.x; e < SOLVE_ROWS * l; e += 256) {
+    const int64_t r0 = (int64_t)local * AP_ROWS;
+    const int nrows = (int)min((int64_t)AP_ROWS, rows - r0);
+    const double* src = (MODE == AP_QA_RINV_Q) ? P.Qa : P.Y;
+    const double* S = P.Rinv;
+    // First pass: into Qa when a second pass follows, else straight into Q.
+    double* const qdst = side == SIDE_M ? P.Q1 : P.Q2;
+    double* const dst = (MODE == AP_Y_RINV_QA && two) ? P.Qa : qdst;
+    const bool op = !(MODE == AP_Y_RINV_QA && two);
+    const int tid = threadIdx.x;
+#pragma unroll 8
+    for (int e = tid; e < AP_ROWS * l; e += 256) {
         const int rr = e / l;
-        xs[e] = rr < nrows ? Z[(r0 + rr) * l + (e % l)] : 0.0;
+        xs[e] = rr < nrows ? src[(r0 + rr) * l + (e % l)] : 0.0;
     }
-
-    const int rr = threadIdx.x >> 3;  // row within the block
-    const int k = threadIdx.x & 7;    // lane within the row group
-    double* x = xs + rr * l;
-    for (int c0 = 0; c0 < l; c0 += SOLVE_PANEL) {
-        const int pc = min(SOLVE_PANEL, l - c0);
-        __syncthreads();  // previous panel fully used (and xs loaded)
-        for (int e = threadIdx.x; e < SOLVE_PANEL * l; e += 256) {
-            const int cc = e / l, a = e % l;
-            rp[e] = (cc < pc && a <= c0 + cc) ? R[(int64_t)a * l + c0 + cc] : 0.0;
+    const int cg = tid & 63, rg = tid >> 6;
+    double acc[8][NJ];
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+#pragma unroll
+        for (int j = 0; j < NJ; j++) acc[r][j] = 0.0;
+    for (int a0 = 0; a0 < l; a0 += PR) {
+        const int pt = min(PR, l - a0);
+        __syncthreads();
+#pragma unroll 8
+        for (int e = tid; e < pt * SPW; e += 256) {
+            const int t = e / SPW, c = e % SPW;
+            sp[e] = c < l ? S[(int64_t)(a0 + t) * l + c] : 0.0;
         }
         __syncthreads();
-        for (int cc = 0; cc < pc; cc++) {
-            const int c = c0 + cc;
-            const double* rc = rp + cc * l;
-            double part = 0.0;
-            for (int a = k; a < c; a += 8) part += x[a] * rc[a];
-            part += __shfl_xor(part, 1, 64);
-            part += __shfl_xor(part, 2, 64);
-            part += __shfl_xor(part, 4, 64);
-            const double zc = x[c];
-            __builtin_amdgcn_wave_barrier();
-            const double xc = (zc - part) / rc[c];
-            if ((c & 7) == k) x[c] = xc;
+        int t = 0;
+        for (; t + 4 <= pt; t += 4) {  // four rows of S per batch of LDS loads
+            double sv[4][NJ], xv[4][8];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+#pragma unroll
+                for (int j = 0; j < NJ; j++) sv[u][j] = sp[(t + u) * SPW + cg + 64 * j];
+#pragma unroll
+                for (int r = 0; r < 8; r++) xv[u][r] = xs[(rg * 8 + r) * l + a0 + t + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int r = 0; r < 8; r++)
+#pragma unroll
+                    for (int j = 0; j < NJ; j++) acc[r][j] += xv[u][r] * sv[u][j];
+        }
+        for (; t < pt; t++) {
+            double sv[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; j++) sv[j] = sp[t * SPW + cg + 64 * j];
+#pragma unroll
+            for (int r = 0; r < 8; r++) {
+                const double x = xs[(rg * 8 + r) * l + a0 + t];
+#pragma unroll
+                for (int j = 0; j < NJ; j++) acc[r][j] += x * sv[j];
+            }
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < SOLVE_ROWS * l; e += 256) {
-        const int r = e / l;
-        if (r < nrows) D[(r0 + r) * l + (e % l)] = xs[e];
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+        const int rr = rg * 8 + r;
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            const int c = cg + 64 * j;
+            if (c < l) xs[rr * l + c] = acc[r][j];
+        }
     }
-    if (mode != SOLVE_Y_TO_QA && P.prec != P_FP8) {
+    __syncthreads();
+    for (int e = tid; e < AP_ROWS * l; e += 256) {
+        const int r = e / l;
+        if (r < nrows) dst[(r0 + r) * l + (e % l)] = xs[e];
+    }
+    if (op && P.prec != P_FP8) {
         switch (P.prec) {
             case P_F64: write_op_rows<double>(P, side, r0, nrows, xs); break;
             case P_F32: write_op_rows<float>(P, side, r0, nrows, xs); break;
@@ -414,18 +516,59 @@ __global__ __launch_bounds__(256) void k_solve(const Prob* __restrict__ probs,
     }
 }
 
-hipError_t launch_solve(const LaunchGroup& g, int side, int mode, int iter, hipStream_t s) {
-    if (g.blocks <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * (SOLVE_ROWS + SOLVE_PANEL) * LMAX;
+template <int MODE, int NJ>
+static hipError_t launch_apply_t(const LaunchGroup& g, int side, int iter, hipStream_t s) {
+    const size_t lds = sizeof(double) * AP_LDS_DOUBLES;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_solve,
+        hipError_t e = hipFuncSetAttribute((const void*)k_apply<MODE, NJ>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(k_solve, dim3(g.blocks), dim3(256), lds, s, g.probs, g.pidx, g.toff,
-                       g.count, side, mode, iter);
+    hipLaunchKernelGGL((k_apply<MODE, NJ>), dim3(g.blocks), dim3(256), lds, s, g.probs, g.pidx,
+                       g.toff, g.count, side, iter);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_apply_m(const LaunchGroup& g, int side, int nj, int iter, hipStream_t s) {
+    switch (nj) {
+        case 1: return launch_apply_t<MODE, 1>(g, side, iter, s);
+        case 2: return launch_apply_t<MODE, 2>(g, side, iter, s);
+        case 3: return launch_apply_t<MODE, 3>(g, side, iter, s);
+        case 4: return launch_apply_t<MODE, 4>(g, side, iter, s);
+        default: return launch_apply_t<MODE, 5>(g, side, iter, s);
+    }
+}
+
+hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int nj, int iter, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    switch (mode) {
+        case AP_Y_RINV_QA: return launch_apply_m<AP_Y_RINV_QA>(g, side, nj, iter, s);
+        case AP_QA_RINV_Q: return launch_apply_m<AP_QA_RINV_Q>(g, side, nj, iter, s);
+        case AP_Y_RINV_Q: return launch_apply_m<AP_Y_RINV_Q>(g, side, nj, iter, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// V = Q2 P: V[r][c] = Q2[r][perm[c]].
+__global__ __launch_bounds__(256) void k_gather_v(const Prob* __restrict__ probs,
+                                                  const int32_t* __restrict__ pidx,
+                                                  const int32_t* __restrict__ toff, int cnt) {
+    int local;
+    const Prob& P = group_prob(probs, pidx, toff, cnt, local);
+    const int l = P.l;
+    const int64_t e = (int64_t)local * 256 + threadIdx.x;
+    if (e >= P.n * l) return;
+    const int64_t r = e / l;
+    const int c = (int)(e % l);
+    P.V[e] = P.Q2[r * l + P.perm[c]];
+}
+
+hipError_t launch_gather_v(const LaunchGroup& g, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_v, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff, g.count);
     return hipGetLastError();
 }
 

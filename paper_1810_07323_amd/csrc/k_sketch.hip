@@ -237,20 +237,28 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch(const Prob* __restrict__ 
                             av[r][e] = *reinterpret_cast<const T*>(As + (kk + e) * AROWB + orow * SZ);
                     }
                 }
+                // All NT operand vectors first, then MFMAs ordered so that the
+                // RT*NT accumulators are visited round-robin: consecutive MFMAs
+                // never update the same accumulator.
+                T bv[NT][VEC];
 #pragma unroll
                 for (int c = 0; c < NT; c++) {
                     union { i32x4 v; T e[VEC]; } b;
                     b.v = *reinterpret_cast<const i32x4*>(Xs + (c * 16 + li) * ROWB + kk * SZ);
 #pragma unroll
-                    for (int e = 0; e < VEC; e++)
+                    for (int e = 0; e < VEC; e++) bv[c][e] = b.e[e];
+                }
+#pragma unroll
+                for (int e = 0; e < VEC; e++)
+#pragma unroll
+                    for (int c = 0; c < NT; c++)
 #pragma unroll
                         for (int r = 0; r < SK_RT; r++) {
                             if constexpr (PREC == P_F32)
-                                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][e], b.e[e], acc[r][c], 0, 0, 0);
+                                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][e], bv[c][e], acc[r][c], 0, 0, 0);
                             else
-                                acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][e], b.e[e], acc[r][c], 0, 0, 0);
+                                acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][e], bv[c][e], acc[r][c], 0, 0, 0);
                         }
-                }
             }
         } else if constexpr (PREC == P_BF16) {
 #pragma unroll

@@ -11,9 +11,8 @@
 
 namespace cor {
 
-constexpr int SMALL_THREADS = 1024;
-constexpr int CHOL_LDS_MAX = 140;  // l*l doubles + scratch fit in 160 KB of LDS
-constexpr int QRCP_LDS_MAX = 136;
+constexpr int CHOL_LDS_MAX = 128;  // l*l + 16*l doubles + scratch fit in 160 KB of LDS
+constexpr int QRCP_LDS_MAX = 136;  // l*l doubles + scratch
 
 __device__ __forceinline__ const Prob& group_prob2(const Prob* probs, const int32_t* pidx,
                                                    const int32_t* toff, int cnt, int& local) {
@@ -23,172 +22,460 @@ __device__ __forceinline__ const Prob& group_prob2(const Prob* probs, const int3
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky G = R^T R, right-looking with one barrier per column; row j is
-// scaled by 1/sqrt(d_j) one step later so no thread reads a row while it is
-// rescaled.  A pivot d_j <= l 2^-52 max_i G_ii is clamped to that threshold
-// (numerically rank-deficient sketch) and flagged.  mode FIRST: Racc = R;
-// SECOND: Racc = R Racc (the R factor of the two CholeskyQR passes).
+// Cholesky G = R^T R and R^{-1} (one block of 256 threads per problem).
+//   Factorisation: right-looking, one barrier per column.  The thread that
+//   updates the next diagonal entry also derives that pivot's scalars
+//   (d, 1/d, sqrt d, 1/sqrt d) into a double-buffered LDS slot, so no other
+//   thread computes a division or a square root.  Row j is scaled one step
+//   later, so no thread reads a row while it is being rescaled.  A pivot
+//   d_j <= l 2^-52 max_i G_ii is clamped to that threshold (numerically
+//   rank-deficient sketch) and flagged.
+//   Inverse: 16 x 16 blocks.  Each wave inverts diagonal blocks by back
+//   substitution (lane = column, so a lane only reads values it wrote); the
+//   off-diagonal blocks follow block row by block row from the bottom:
+//   X_ij = -X_ii sum_{i<k<=j} R_ik X_kj.  The strict upper part of R^{-1} is
+//   kept transposed in the free lower triangle of the work array.
+// Outputs: R, Rinv; mode FIRST also keeps R in Racc (for R2 = R' R).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(SMALL_THREADS) void k_chol(const Prob* __restrict__ probs,
-                                                        const int32_t* __restrict__ pidx,
-                                                        const int32_t* __restrict__ toff, int cnt,
-                                                        int mode, int iter) {
+constexpr int CHOL_THREADS = 256;
+
+__device__ __forceinline__ void chol_pivot(double d, double tol, double* sc, int* clamped) {
+    if (!(d > tol)) {
+        d = tol;
+        *clamped = 1;
+    }
+    const double sq = sqrt(d);
+    sc[0] = d;
+    sc[1] = 1.0 / d;
+    sc[2] = sq;
+    sc[3] = 1.0 / sq;
+}
+
+// IN_LDS selects where the l x l work array lives; a pointer that may point
+// to either LDS or global memory would force flat (global-latency) accesses.
+template <bool IN_LDS>
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol(const Prob* __restrict__ probs,
+                                                       const int32_t* __restrict__ pidx,
+                                                       const int32_t* __restrict__ toff, int cnt,
+                                                       int mode, int iter) {
     extern __shared__ __align__(16) double sm[];
     __shared__ double s_tol;
+    __shared__ double s_sc[2][4];
+    __shared__ double s_dinv[LMAX];
+    __shared__ int s_clamped;
     int local;
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
     if (iter >= 0 && iter > P.q) return;
+    if (mode == CHOL_SECOND && !second_pass(P, iter)) return;
     const int l = P.l;
-    const int tid = threadIdx.x;
-    const bool in_lds = l <= CHOL_LDS_MAX;
-    double* W = in_lds ? sm : P.R;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = CHOL_THREADS / 64;
+    constexpr bool in_lds = IN_LDS;
+    if (IN_LDS != (l <= CHOL_LDS_MAX)) return;
+    double* W;
+    double* Tm;  // (nb - 1) * 256 <= 16 l doubles
+    if constexpr (IN_LDS) { W = sm; Tm = sm + l * l; }
+    else { W = P.R; Tm = P.G; }
+    const int nb = (l + 15) / 16;
 
-    for (int e = tid; e < l * l; e += SMALL_THREADS) W[e] = P.G[e];
+#pragma unroll 8
+    for (int e = tid; e < l * l; e += CHOL_THREADS) W[e] = P.G[e];
     if (tid < 64) {
         double mx = 0.0;
         for (int i = tid; i < l; i += 64) mx = fmax(mx, fabs(P.G[i * l + i]));
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if (tid == 0) s_tol = (double)l * 0x1.0p-52 * mx;
+        if (tid == 0) {
+            const double t = (double)l * 0x1.0p-52 * mx;
+            s_tol = t > 0.0 ? t : 0x1.0p-1000;
+            s_clamped = 0;
+        }
     }
     __syncthreads();
-    const double tol = s_tol > 0.0 ? s_tol : 0x1.0p-1000;
+    const double tol = s_tol;
+    if (tid == 0) chol_pivot(W[0], tol, s_sc[0], &s_clamped);
+    __syncthreads();
 
-    double dprev = 1.0;
-    bool clamped = false;
+    double psq = 1.0, pisq = 1.0;  // scalars of the previous pivot
     for (int j = 0; j < l; j++) {
-        double d = W[j * l + j];
-        if (!(d > tol)) {
-            clamped = true;
-            d = tol;
-        }
-        const double inv_d = 1.0 / d;
-        if (j > 0) {
-            const double sc = 1.0 / sqrt(dprev);
-            for (int c = j - 1 + tid; c < l; c += SMALL_THREADS)
-                W[(j - 1) * l + c] = (c == j - 1) ? sqrt(dprev) : W[(j - 1) * l + c] * sc;
-        }
-        const int n1 = l - j - 1;
+        const double inv_d = s_sc[j & 1][1];
+        const double csq = s_sc[j & 1][2], cisq = s_sc[j & 1][3];
+        if (j > 0)
+            for (int c = j - 1 + tid; c < l; c += CHOL_THREADS)
+                W[(j - 1) * l + c] = (c == j - 1) ? psq : W[(j - 1) * l + c] * pisq;
         const double* wj = W + j * l;
-        for (int idx = tid; idx < n1 * n1; idx += SMALL_THREADS) {
-            const int a = j + 1 + idx / n1, b = j + 1 + idx % n1;
-            if (b >= a) W[a * l + b] -= wj[a] * wj[b] * inv_d;
+        for (int a = j + 1 + wave; a < l; a += NW) {
+            const double f = wj[a] * inv_d;
+            double* wa = W + a * l;
+            for (int b = a + lane; b < l; b += 64) wa[b] -= f * wj[b];
         }
-        dprev = d;
+        // thread 0 updated W[j+1][j+1] (wave 0 takes row j+1, lane 0 column j+1)
+        if (tid == 0 && j + 1 < l) chol_pivot(W[(j + 1) * l + j + 1], tol, s_sc[(j + 1) & 1], &s_clamped);
+        psq = csq;
+        pisq = cisq;
         __syncthreads();
     }
-    if (tid == 0) W[(l - 1) * l + (l - 1)] = sqrt(dprev);
-    if (clamped && tid == 0) atomicOr(P.flags, FLAG_RANK_DEF);
+    if (tid == 0) {
+        W[(l - 1) * l + (l - 1)] = psq;
+        if (s_clamped) atomicOr(P.flags, FLAG_RANK_DEF);
+    }
     __syncthreads();
-    for (int e = tid; e < l * l; e += SMALL_THREADS) {
+    for (int e = tid; e < l * l; e += CHOL_THREADS) {
         const int a = e / l, b = e % l;
         if (b < a) W[e] = 0.0;
     }
     __syncthreads();
-    if (in_lds)
-        for (int e = tid; e < l * l; e += SMALL_THREADS) P.R[e] = W[e];
-    if (mode == CHOL_FIRST) {
-        for (int e = tid; e < l * l; e += SMALL_THREADS) P.Racc[e] = W[e];
-        return;
-    }
-    // Racc <- R Racc (both upper triangular), through G as scratch.
-    for (int e = tid; e < l * l; e += SMALL_THREADS) {
-        const int a = e / l, b = e % l;
-        double s = 0.0;
-        if (b >= a)
-            for (int t = a; t <= b; t++) s += W[a * l + t] * P.Racc[t * l + b];
-        P.G[e] = s;
+
+    // ---- inverse: X = R^{-1}; X[i][c] (i < c) stored at W[c][i], diag in s_dinv
+    for (int ib = wave; ib < nb; ib += NW) {
+        const int o = 16 * ib, bs = min(16, l - o);
+        const int c = lane;
+        for (int i = bs - 1; i >= 0; i--) {
+            if (c < bs && c >= i) {
+                const double rii = W[(o + i) * l + o + i];
+                if (c == i) {
+                    s_dinv[o + i] = 1.0 / rii;
+                } else {
+                    double sacc = 0.0;
+                    for (int t = i + 1; t <= c; t++) {
+                        const double xt = (t == c) ? s_dinv[o + c] : W[(o + c) * l + o + t];
+                        sacc += W[(o + i) * l + o + t] * xt;
+                    }
+                    W[(o + c) * l + o + i] = -sacc / rii;
+                }
+            }
+        }
     }
     __syncthreads();
-    for (int e = tid; e < l * l; e += SMALL_THREADS) P.Racc[e] = P.G[e];
+    for (int ib = nb - 2; ib >= 0; ib--) {
+        const int o = 16 * ib;
+        const int nblk = nb - 1 - ib;
+        for (int e = tid; e < nblk * 256; e += CHOL_THREADS) {
+            const int jb = ib + 1 + e / 256, r = (e % 256) / 16, cc = e % 16;
+            const int col = 16 * jb + cc, row = o + r;
+            double s0 = 0.0, s1 = 0.0;
+            if (col < l && row < l) {
+                int t = 16 * (ib + 1);
+                for (; t + 1 < col; t += 2) {
+                    s0 += W[row * l + t] * W[col * l + t];
+                    s1 += W[row * l + t + 1] * W[col * l + t + 1];
+                }
+                for (; t < col; t++) s0 += W[row * l + t] * W[col * l + t];
+                s0 += W[row * l + col] * s_dinv[col];
+            }
+            Tm[e] = s0 + s1;
+        }
+        __syncthreads();
+        const int bs = min(16, l - o);
+        for (int e = tid; e < nblk * 256; e += CHOL_THREADS) {
+            const int jb = ib + 1 + e / 256, r = (e % 256) / 16, cc = e % 16;
+            const int col = 16 * jb + cc, row = o + r;
+            if (col >= l || r >= bs) continue;
+            double sacc = s_dinv[row] * Tm[(e / 256) * 256 + r * 16 + cc];
+            for (int t = r + 1; t < bs; t++) sacc += W[(o + t) * l + row] * Tm[(e / 256) * 256 + t * 16 + cc];
+            W[col * l + row] = -sacc;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < l * l; e += CHOL_THREADS) {
+        const int a = e / l, b = e % l;
+        const double r = b >= a ? W[e] : 0.0;
+        P.Rinv[e] = b > a ? W[b * l + a] : (b == a ? s_dinv[a] : 0.0);
+        if (in_lds) P.R[e] = r;
+        if (mode == CHOL_FIRST) P.Racc[e] = r;
+    }
+    if (!in_lds) {
+        __syncthreads();
+        for (int e = tid; e < l * l; e += CHOL_THREADS) {
+            const int a = e / l, b = e % l;
+            if (b < a) W[e] = 0.0;
+        }
+    }
 }
 
-hipError_t launch_chol(const LaunchGroup& g, int mode, int iter, hipStream_t s) {
-    if (g.blocks <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * CHOL_LDS_MAX * CHOL_LDS_MAX;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_chol,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr = true;
+
+// ---------------------------------------------------------------------------
+// Cholesky and inverse in one register-resident sweep (l <= 128).
+//
+// Symmetric Gaussian elimination on [G | I]: at column j every row a > j
+// subtracts (v_a / d_j) times row j, where v = row j of the current Schur
+// complement and d_j = v_j.  The upper triangle of the l x l work matrix
+// holds the Schur complement, the strict lower triangle accumulates
+// E = L^{-1} (G = L D L^T, L unit lower).  Then
+//   R    = D^{1/2} L^T   : R[j][b]    = v_b / sqrt(d_j)          (b >= j)
+//   R^-1 = L^{-T} D^-1/2 : R^-1[b][j] = E[j][b] / sqrt(d_j)      (b <  j)
+// and row j is final at step j, so its owners write row j of R and column j
+// of R^{-1} straight to global memory.  Each of 1024 threads keeps one 4 x 4
+// tile in registers; row j and the pivot scalars are published through LDS
+// (double-buffered), one barrier per column.  A pivot d_j <= l 2^-52
+// max_i G_ii is clamped to that threshold (numerically rank-deficient sketch)
+// and flagged.  mode FIRST also stores R in Racc (for R2 = R' R).
+// ---------------------------------------------------------------------------
+constexpr int CRT_THREADS = 1024;
+constexpr int CRT_LMAX = 128;
+
+__global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict__ probs,
+                                                        const int32_t* __restrict__ pidx,
+                                                        const int32_t* __restrict__ toff, int cnt,
+                                                        int mode, int iter) {
+    __shared__ __align__(16) double s_row[2][CRT_LMAX];
+    __shared__ double s_sc[2][4];
+    __shared__ double s_sq[CRT_LMAX], s_rsq[CRT_LMAX];  // sqrt(d_j), 1/sqrt(d_j)
+    __shared__ double s_tol;
+    __shared__ int s_clamped;
+    int local;
+    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
+    if (iter >= 0 && iter > P.q) return;
+    if (mode == CHOL_SECOND && !second_pass(P, iter)) return;
+    const int l = P.l;
+    if (l > CRT_LMAX) return;
+    const int tid = threadIdx.x;
+    const int nt4 = (l + 3) / 4;
+    const bool own = tid < nt4 * nt4;
+    const int ta = own ? tid / nt4 : 0, tb = own ? tid % nt4 : 0;
+    const int a0 = 4 * ta, b0 = 4 * tb;
+    const double* __restrict__ G = P.G;
+    double* __restrict__ Rout = P.R;
+    double* __restrict__ Rinv = P.Rinv;
+    double* __restrict__ Racc = P.Racc;
+    const bool first = mode == CHOL_FIRST;
+
+    double x[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const int a = a0 + r, b = b0 + c;
+            x[r][c] = (own && a < l && b < l && a <= b) ? G[a * l + b] : 0.0;
+        }
+    if (tid < 64) {
+        double mx = 0.0;
+        for (int i = tid; i < l; i += 64) mx = fmax(mx, fabs(G[i * l + i]));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if (tid == 0) {
+            const double t = (double)l * 0x1.0p-52 * mx;
+            s_tol = t > 0.0 ? t : 0x1.0p-1000;
+            s_clamped = 0;
+        }
     }
-    hipLaunchKernelGGL(k_chol, dim3(g.blocks), dim3(SMALL_THREADS), lds, s, g.probs, g.pidx,
+    __syncthreads();
+    const double tol = s_tol;
+    // publish row 0 and the first pivot
+    if (own && ta == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            if (b0 + c < l) s_row[0][b0 + c] = x[0][c];
+        if (tb == 0) {
+            chol_pivot(x[0][0], tol, s_sc[0], &s_clamped);
+            s_sq[0] = s_sc[0][2];
+            s_rsq[0] = s_sc[0][3];
+        }
+    }
+    __syncthreads();
+
+    // The loop touches only registers and LDS: a barrier then never waits for
+    // global memory.  Rows are final once their step has passed, so R and
+    // R^{-1} are written from the registers after the loop.
+    for (int j = 0; j < l; j++) {
+        const int sl = j & 1;
+        const double inv_d = s_sc[sl][1];
+        // Elimination of column j from rows a > j.
+        if (own && a0 + 3 > j) {
+            double fa[4], cb[4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) fa[r] = (a0 + r < l) ? s_row[sl][a0 + r] * inv_d : 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int b = b0 + c;
+                cb[c] = b == j ? 1.0 : (b < l ? s_row[sl][b] : 0.0);
+            }
+            if (ta < tb) {  // Schur complement block: every column b > a > j
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                    if (a0 + r > j)
+#pragma unroll
+                        for (int c = 0; c < 4; c++) x[r][c] -= fa[r] * cb[c];
+            } else if (ta > tb) {  // E block: columns b <= j
+                if (b0 <= j) {
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+                        if (a0 + r > j)
+#pragma unroll
+                            for (int c = 0; c < 4; c++)
+                                if (b0 + c <= j) x[r][c] -= fa[r] * cb[c];
+                }
+            } else {  // diagonal block: both kinds
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int a = a0 + r;
+                    if (a > j)
+#pragma unroll
+                        for (int c = 0; c < 4; c++) {
+                            const int b = b0 + c;
+                            if (b >= a || b <= j) x[r][c] -= fa[r] * cb[c];
+                        }
+                }
+            }
+        }
+        // Publish row j + 1 (Schur part for b > j, E part for b <= j) and its pivot.
+        if (own && j + 1 < l && ta == ((j + 1) >> 2)) {
+            const int r = j + 1 - a0;
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int b = b0 + c;
+                if (b >= l) continue;
+                double xv = x[0][c];
+                if (r == 1) xv = x[1][c];
+                else if (r == 2) xv = x[2][c];
+                else if (r == 3) xv = x[3][c];
+                s_row[sl ^ 1][b] = xv;
+                if (b == j + 1) {
+                    chol_pivot(xv, tol, s_sc[sl ^ 1], &s_clamped);
+                    s_sq[j + 1] = s_sc[sl ^ 1][2];
+                    s_rsq[j + 1] = s_sc[sl ^ 1][3];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && s_clamped) atomicOr(P.flags, FLAG_RANK_DEF);
+    // R[a][b] = v_b / sqrt(d_a) (b > a), sqrt(d_a) (b = a), 0 below;
+    // R^{-1}[b][a] = E[a][b] / sqrt(d_a) (b < a), 1/sqrt(d_a) (b = a), 0 above.
+    if (own) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int a = a0 + r;
+            if (a >= l) continue;
+            const double sq = s_sq[a], rsq = s_rsq[a];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int b = b0 + c;
+                if (b >= l) continue;
+                const double xv = x[r][c];
+                const double rv = b > a ? xv * rsq : (b == a ? sq : 0.0);
+                Rout[a * l + b] = rv;
+                if (first) Racc[a * l + b] = rv;
+                Rinv[b * l + a] = b < a ? xv * rsq : (b == a ? rsq : 0.0);
+            }
+        }
+    }
+}
+
+hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chol_rt, dim3(g.blocks), dim3(CRT_THREADS), 0, s, g.probs, g.pidx,
+                       g.toff, g.count, mode, iter);
+    hipError_t er = hipGetLastError();
+    if (er != hipSuccess || lmax <= CRT_LMAX) return er;
+    // l > 128: the variant with the work array in global memory.
+    hipLaunchKernelGGL(k_chol<false>, dim3(g.blocks), dim3(CHOL_THREADS), 0, s, g.probs, g.pidx,
                        g.toff, g.count, mode, iter);
     return hipGetLastError();
 }
 
+// R2 = R' R (both upper triangular): the R factor of Y2 after both
+// CholeskyQR passes.  One block per 16 x 16 output tile.
+__global__ __launch_bounds__(256) void k_r2(const Prob* __restrict__ probs,
+                                            const int32_t* __restrict__ pidx,
+                                            const int32_t* __restrict__ toff, int cnt, int iter) {
+    int local;
+    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
+    if (iter != P.q) return;  // only the R factor of the last Y2 is used
+    const int l = P.l, nt = P.lp / 16;
+    const int ta = local / nt, tb = local % nt;
+    const int a = ta * 16 + (threadIdx.x >> 4), b = tb * 16 + (threadIdx.x & 15);
+    if (a >= l || b >= l) return;
+    const double* __restrict__ Ra = P.R + a * l;
+    const double* __restrict__ Rb = P.Racc + b;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int t = a;
+    for (; t + 3 <= b; t += 4) {
+        s0 += Ra[t] * Rb[t * l];
+        s1 += Ra[t + 1] * Rb[(t + 1) * l];
+        s2 += Ra[t + 2] * Rb[(t + 2) * l];
+        s3 += Ra[t + 3] * Rb[(t + 3) * l];
+    }
+    for (; t <= b; t++) s0 += Ra[t] * Rb[t * l];
+    P.R2[a * l + b] = (s0 + s1) + (s2 + s3);
+}
+
+hipError_t launch_r2(const LaunchGroup& g, int iter, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_r2, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff, g.count, iter);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
-// QRCP of M = Racc^T (l x l).  Wave 0 picks the pivot, swaps and builds the
-// reflector; then every wave updates its trailing columns (one column per
-// wave at a time, rows over lanes) and recomputes their norms over the rows
-// below the diagonal for the next pivot choice.  The reflectors are then
-// accumulated backwards in place into Qt = H_0 H_1 ... H_{l-1}.
+// QRCP of M = R2^T (l x l), one block of 256 threads per problem.
+//   Pivot: during the trailing update each column posts
+//   key = (bits of its squared norm with the 9 low mantissa bits cleared) |
+//   (511 - position) with a 64-bit LDS atomicMax; for non-negative doubles
+//   the bit pattern orders like the value, so the winner is the largest norm
+//   and, among norms equal to 43 bits, the lowest position.
+//   Step j: wave 0 swaps the pivot column into position j and turns it into
+//   the reflector v (v_j = 1 implicit, beta on the diagonal); then every
+//   thread takes a trailing column: w = tau v^T col, col -= w v, and its new
+//   squared norm over the rows below j.  Two barriers per step.
+// Outputs: T (upper, T_jj >= 0), perm, the reflectors VT[j][a] (row j is v_j,
+// zero left of j) in Qt, tau[j] and the column signs sign[j] = tau[LMAX + j].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(SMALL_THREADS) void k_qrcp(const Prob* __restrict__ probs,
-                                                        const int32_t* __restrict__ pidx,
-                                                        const int32_t* __restrict__ toff,
-                                                        int cnt) {
+constexpr int QR_THREADS = 256;
+
+__device__ __forceinline__ unsigned long long qr_key(double nn, int c) {
+    return (__double_as_longlong(nn) & ~0x1FFull) | (unsigned long long)(511 - c);
+}
+
+template <bool IN_LDS>
+__global__ __launch_bounds__(QR_THREADS) void k_qrcp(const Prob* __restrict__ probs,
+                                                     const int32_t* __restrict__ pidx,
+                                                     const int32_t* __restrict__ toff, int cnt) {
     extern __shared__ __align__(16) double sm[];
-    __shared__ double s_v[LMAX];
     __shared__ double s_nrm[LMAX];
     __shared__ double s_tau[LMAX];
-    __shared__ double s_sign[LMAX];
     __shared__ int s_perm[LMAX];
+    __shared__ unsigned long long s_key[2];
     int local;
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
     const int l = P.l;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = SMALL_THREADS / 64;
-    const bool in_lds = l <= QRCP_LDS_MAX;
-    double* W = in_lds ? sm : P.Qt;
+    if (IN_LDS != (l <= QRCP_LDS_MAX)) return;
+    double* W;
+    if constexpr (IN_LDS) W = sm;
+    else W = P.R;  // P.R is free once R2 is formed
 
-    for (int e = tid; e < l * l; e += SMALL_THREADS) {
+#pragma unroll 8
+    for (int e = tid; e < l * l; e += QR_THREADS) {
         const int a = e / l, b = e % l;
-        W[e] = P.Racc[b * l + a];  // M = R2^T
+        W[e] = P.R2[b * l + a];  // M = R2^T
     }
-    for (int c = tid; c < l; c += SMALL_THREADS) s_perm[c] = c;
+    for (int c = tid; c < l; c += QR_THREADS) s_perm[c] = c;
+    if (tid < 2) s_key[tid] = 0ull;
     __syncthreads();
-    for (int c = wave; c < l; c += NW) {
-        double ss = 0.0;
-        for (int i = lane; i < l; i += 64) ss += W[i * l + c] * W[i * l + c];
-        ss = wave_sum(ss);
-        if (lane == 0) s_nrm[c] = ss;
+    for (int c = tid; c < l; c += QR_THREADS) {
+        double n4[4] = {0.0, 0.0, 0.0, 0.0};
+        int i = 0;
+        for (; i + 8 <= l; i += 8) {
+            double wv[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) wv[u] = W[(i + u) * l + c];
+#pragma unroll
+            for (int u = 0; u < 8; u++) n4[u & 3] += wv[u] * wv[u];
+        }
+        for (; i < l; i++) n4[0] += W[i * l + c] * W[i * l + c];
+        const double ss = (n4[0] + n4[1]) + (n4[2] + n4[3]);
+        s_nrm[c] = ss;
+        atomicMax(&s_key[0], qr_key(ss, c));
     }
     __syncthreads();
 
     for (int j = 0; j < l; j++) {
         if (wave == 0) {
-            // pivot: largest squared norm, lowest index on ties
-            double bv = -1.0;
-            int bi = l;
-            for (int c = j + lane; c < l; c += 64) {
-                const double v = s_nrm[c];
-                if (v > bv) { bv = v; bi = c; }
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ov = __shfl_xor(bv, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-            }
-            const int p = bi;
-            if (p != j) {
-                for (int i = lane; i < l; i += 64) {
-                    const double t = W[i * l + j];
-                    W[i * l + j] = W[i * l + p];
-                    W[i * l + p] = t;
-                }
-                if (lane == 0) {
-                    const int t = s_perm[j]; s_perm[j] = s_perm[p]; s_perm[p] = t;
-                    const double tn = s_nrm[j]; s_nrm[j] = s_nrm[p]; s_nrm[p] = tn;
-                }
-            }
-            // Householder reflector of column j, rows j..l-1
-            double ss = 0.0;
-            for (int i = j + lane; i < l; i += 64) ss += W[i * l + j] * W[i * l + j];
-            ss = wave_sum(ss);
-            const double alpha = W[j * l + j];
+            const unsigned long long key = s_key[j & 1];
+            const int p = 511 - (int)(key & 0x1FFull);
+            const double alpha = W[j * l + p];  // becomes W[j][j] after the swap
+            const double ss = s_nrm[p];         // sum_{i >= j} W[i][p]^2
+            __builtin_amdgcn_wave_barrier();
             const double xnorm = sqrt(ss);
             double tau = 0.0, beta = alpha, scale = 0.0;
             if (xnorm != 0.0) {
@@ -196,165 +483,190 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_qrcp(const Prob* __restrict__
                 scale = 1.0 / (alpha - beta);
                 tau = (beta - alpha) / beta;
             }
-            for (int i = j + lane; i < l; i += 64) {
-                double v;
-                if (i == j) v = 1.0;
-                else {
-                    v = W[i * l + j] * scale;
-                    if (xnorm != 0.0) W[i * l + j] = v;
+            for (int i = lane; i < l; i += 64) {  // each lane owns rows i = lane (mod 64)
+                double wj = W[i * l + j];
+                if (p != j) {
+                    const double wp = W[i * l + p];
+                    W[i * l + p] = wj;
+                    wj = wp;
                 }
-                s_v[i] = v;
+                if (i > j) wj = xnorm != 0.0 ? wj * scale : wj;
+                else if (i == j) wj = beta;
+                W[i * l + j] = wj;
             }
             if (lane == 0) {
                 s_tau[j] = tau;
-                W[j * l + j] = beta;
+                s_key[j & 1] = 0ull;
+                if (p != j) {
+                    const int t = s_perm[j]; s_perm[j] = s_perm[p]; s_perm[p] = t;
+                    s_nrm[p] = s_nrm[j];
+                }
             }
         }
         __syncthreads();
         const double tau = s_tau[j];
-        for (int c = j + 1 + wave; c < l; c += NW) {
-            double dot = 0.0;
-            if (tau != 0.0) {
-                for (int i = j + lane; i < l; i += 64) dot += s_v[i] * W[i * l + c];
-                dot = wave_sum(dot) * tau;
-                for (int i = j + lane; i < l; i += 64) W[i * l + c] -= dot * s_v[i];
+        for (int c = j + 1 + tid; c < l; c += QR_THREADS) {
+            // w = tau v^T col (v_j = 1), 16 rows per batch of independent loads
+            double d4[4] = {W[j * l + c], 0.0, 0.0, 0.0};
+            int i = j + 1;
+            for (; i + 16 <= l; i += 16) {
+                double vv[16], wv[16];
+#pragma unroll
+                for (int u = 0; u < 16; u++) {
+                    vv[u] = W[(i + u) * l + j];
+                    wv[u] = W[(i + u) * l + c];
+                }
+#pragma unroll
+                for (int u = 0; u < 16; u++) d4[u & 3] += vv[u] * wv[u];
             }
-            double ss = 0.0;
-            for (int i = j + 1 + lane; i < l; i += 64) ss += W[i * l + c] * W[i * l + c];
-            ss = wave_sum(ss);
-            if (lane == 0) s_nrm[c] = ss;
+            for (; i < l; i++) d4[0] += W[i * l + j] * W[i * l + c];
+            const double w = tau * ((d4[0] + d4[1]) + (d4[2] + d4[3]));
+            W[j * l + c] -= w;
+            double n4[4] = {0.0, 0.0, 0.0, 0.0};
+            i = j + 1;
+            for (; i + 16 <= l; i += 16) {
+                double vv[16], wv[16];
+#pragma unroll
+                for (int u = 0; u < 16; u++) {
+                    vv[u] = W[(i + u) * l + j];
+                    wv[u] = W[(i + u) * l + c];
+                }
+#pragma unroll
+                for (int u = 0; u < 16; u++) {
+                    const double x = wv[u] - w * vv[u];
+                    W[(i + u) * l + c] = x;
+                    n4[u & 3] += x * x;
+                }
+            }
+            for (; i < l; i++) {
+                const double x = W[i * l + c] - w * W[i * l + j];
+                W[i * l + c] = x;
+                n4[0] += x * x;
+            }
+            const double nn = (n4[0] + n4[1]) + (n4[2] + n4[3]);
+            s_nrm[c] = nn;
+            atomicMax(&s_key[(j + 1) & 1], qr_key(nn, c));
         }
         __syncthreads();
     }
 
-    // T (upper, T_jj >= 0) and the permutation.
-    for (int j = tid; j < l; j += SMALL_THREADS) s_sign[j] = W[j * l + j] < 0.0 ? -1.0 : 1.0;
-    __syncthreads();
-    for (int e = tid; e < l * l; e += SMALL_THREADS) {
+    double* tau_out = P.tau;
+    for (int j = tid; j < l; j += QR_THREADS) {
+        tau_out[j] = s_tau[j];
+        tau_out[LMAX + j] = W[j * l + j] < 0.0 ? -1.0 : 1.0;
+        P.perm[j] = s_perm[j];
+    }
+    for (int e = tid; e < l * l; e += QR_THREADS) {
         const int a = e / l, b = e % l;
-        P.T[e] = b >= a ? s_sign[a] * W[e] : 0.0;
+        const double sg = W[a * l + a] < 0.0 ? -1.0 : 1.0;
+        P.T[e] = b >= a ? sg * W[e] : 0.0;
+        // reflector a, component b
+        P.Qt[e] = b < a ? 0.0 : (b == a ? 1.0 : W[b * l + a]);
     }
-    for (int j = tid; j < l; j += SMALL_THREADS) P.perm[j] = s_perm[j];
-    __syncthreads();
-
-    // Qt = H_0 (H_1 (... H_{l-1} I)), in place.
-    for (int j = l - 1; j >= 0; j--) {
-        if (wave == 0) {
-            for (int i = j + lane; i < l; i += 64) {
-                s_v[i] = (i == j) ? 1.0 : W[i * l + j];
-                W[i * l + j] = (i == j) ? 1.0 : 0.0;
-                if (i > j) W[j * l + i] = 0.0;
-            }
-        }
-        __syncthreads();
-        const double tau = s_tau[j];
-        if (tau != 0.0) {
-            for (int c = j + wave; c < l; c += NW) {
-                double dot = 0.0;
-                for (int i = j + lane; i < l; i += 64) dot += s_v[i] * W[i * l + c];
-                dot = wave_sum(dot) * tau;
-                for (int i = j + lane; i < l; i += 64) W[i * l + c] -= dot * s_v[i];
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < l * l; e += SMALL_THREADS) P.Qt[e] = W[e] * s_sign[e % l];
 }
 
-hipError_t launch_qrcp(const LaunchGroup& g, hipStream_t s) {
+hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
     const size_t lds = sizeof(double) * QRCP_LDS_MAX * QRCP_LDS_MAX;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_qrcp,
+        hipError_t e = hipFuncSetAttribute((const void*)k_qrcp<true>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(k_qrcp, dim3(g.blocks), dim3(SMALL_THREADS), lds, s, g.probs, g.pidx,
+    hipLaunchKernelGGL(k_qrcp<true>, dim3(g.blocks), dim3(QR_THREADS), lds, s, g.probs, g.pidx,
+                       g.toff, g.count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || lmax <= QRCP_LDS_MAX) return e;
+    hipLaunchKernelGGL(k_qrcp<false>, dim3(g.blocks), dim3(QR_THREADS), 0, s, g.probs, g.pidx,
                        g.toff, g.count);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// U = Q1 Qt (blocks of 32 rows of U) and V = Q2 P (blocks of 64 rows of V).
-// Per problem: ceil(m/32) U-blocks followed by ceil(n/64) V-blocks.
+// U = Q1 H_0 H_1 ... H_{l-1} diag(sign): the reflectors of the QRCP applied
+// to the rows of Q1 (equal to Q1 Qt without forming Qt).  Eight lanes share a
+// row; lane k holds the entries a = k (mod 8) in registers, so a reflector
+// costs two short dot/axpy loops and a three-step shuffle reduction.  The
+// reflectors stream through LDS in panels of 32.
 // ---------------------------------------------------------------------------
-constexpr int UV_ROWS = 32;
-constexpr int V_ROWS = 64;
+constexpr int FU_ROWS = 32;
+constexpr int FU_PANEL = 32;
 
-__global__ __launch_bounds__(256) void k_form_uv(const Prob* __restrict__ probs,
-                                                 const int32_t* __restrict__ pidx,
-                                                 const int32_t* __restrict__ toff, int cnt) {
-    extern __shared__ __align__(16) double xs[];  // UV_ROWS x l
+template <int TN>
+__global__ __launch_bounds__(256) void k_form_u(const Prob* __restrict__ probs,
+                                                const int32_t* __restrict__ pidx,
+                                                const int32_t* __restrict__ toff, int cnt) {
+    constexpr int LPAD = 8 * TN;                   // reflector rows padded with zeros
+    extern __shared__ __align__(16) double vt[];   // FU_PANEL x LPAD
+    __shared__ double s_tau[FU_PANEL];
     int local;
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
     const int l = P.l;
-    const int ub = (int)((P.m + UV_ROWS - 1) / UV_ROWS);
     const int tid = threadIdx.x;
-    if (local >= ub) {
-        const int64_t r0 = (int64_t)(local - ub) * V_ROWS;
-        for (int e = tid; e < V_ROWS * l; e += 256) {
-            const int64_t r = r0 + e / l;
-            const int c = e % l;
-            if (r < P.n) P.V[r * l + c] = P.Q2[r * l + P.perm[c]];
-        }
-        return;
+    const int rr = tid >> 3, k = tid & 7;
+    const int64_t row = (int64_t)local * FU_ROWS + rr;
+    const bool rv = row < P.m;
+    double u[TN];
+#pragma unroll
+    for (int t = 0; t < TN; t++) {
+        const int a = k + 8 * t;
+        u[t] = (rv && a < l) ? P.Q1[row * l + a] : 0.0;
     }
-    const int64_t r0 = (int64_t)local * UV_ROWS;
-    const int nrows = (int)min((int64_t)UV_ROWS, P.m - r0);
-    for (int e = tid; e < UV_ROWS * l; e += 256) {
-        const int rr = e / l;
-        xs[e] = rr < nrows ? P.Q1[(r0 + rr) * l + e % l] : 0.0;
-    }
-    __syncthreads();
-    const int cg = tid & 63;
-    const int rg = tid >> 6;  // 8 rows per group
-    constexpr int NJ = (LMAX + 63) / 64;
-    double acc[8][NJ];
-#pragma unroll
-    for (int r = 0; r < 8; r++)
-#pragma unroll
-        for (int jj = 0; jj < NJ; jj++) acc[r][jj] = 0.0;
-    for (int a = 0; a < l; a++) {
-        double qt[NJ];
-#pragma unroll
-        for (int jj = 0; jj < NJ; jj++) {
-            const int c = cg + 64 * jj;
-            qt[jj] = c < l ? P.Qt[a * l + c] : 0.0;
+    for (int j0 = 0; j0 < l; j0 += FU_PANEL) {
+        const int pj = min(FU_PANEL, l - j0);
+        __syncthreads();
+#pragma unroll 8
+        for (int e = tid; e < pj * LPAD; e += 256) {
+            const int jj = e / LPAD, a = e % LPAD;
+            vt[e] = a < l ? P.Qt[(int64_t)(j0 + jj) * l + a] : 0.0;
         }
+        if (tid < pj) s_tau[tid] = P.tau[j0 + tid];
+        __syncthreads();
+        for (int jj = 0; jj < pj; jj++) {
+            const double* v = vt + jj * LPAD + k;
+            double vv[TN];
 #pragma unroll
-        for (int r = 0; r < 8; r++) {
-            const double q = xs[(rg * 8 + r) * l + a];
+            for (int t = 0; t < TN; t++) vv[t] = v[8 * t];
+            double d = 0.0;
 #pragma unroll
-            for (int jj = 0; jj < NJ; jj++) acc[r][jj] += q * qt[jj];
+            for (int t = 0; t < TN; t++) d += u[t] * vv[t];
+            d = sum8_dpp(d);
+            const double w = s_tau[jj] * d;
+#pragma unroll
+            for (int t = 0; t < TN; t++) u[t] -= w * vv[t];
         }
     }
+    if (!rv) return;
 #pragma unroll
-    for (int r = 0; r < 8; r++) {
-        const int rr = rg * 8 + r;
-        if (rr >= nrows) continue;
-#pragma unroll
-        for (int jj = 0; jj < NJ; jj++) {
-            const int c = cg + 64 * jj;
-            if (c < l) P.U[(r0 + rr) * l + c] = acc[r][jj];
-        }
+    for (int t = 0; t < TN; t++) {
+        const int a = k + 8 * t;
+        if (a < l) P.U[row * l + a] = u[t] * P.tau[LMAX + a];
     }
 }
 
-hipError_t launch_form_uv(const LaunchGroup& g, hipStream_t s) {
+hipError_t launch_form_u(const LaunchGroup& g, int l, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * UV_ROWS * LMAX;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_form_uv,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr = true;
+    const size_t lds = sizeof(double) * FU_PANEL * 8 * 33;
+    const int tn = (l + 7) / 8;
+#define FU_CASE(N)                                                                              \
+    if (tn <= N) {                                                                              \
+        static bool attr = false;                                                               \
+        if (!attr) {                                                                            \
+            hipError_t e = hipFuncSetAttribute((const void*)k_form_u<N>,                        \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,      \
+                                               (int)lds);                                       \
+            if (e != hipSuccess) return e;                                                      \
+            attr = true;                                                                        \
+        }                                                                                       \
+        hipLaunchKernelGGL(k_form_u<N>, dim3(g.blocks), dim3(256), lds, s, g.probs, g.pidx,     \
+                           g.toff, g.count);                                                    \
+        return hipGetLastError();                                                               \
     }
-    hipLaunchKernelGGL(k_form_uv, dim3(g.blocks), dim3(256), lds, s, g.probs, g.pidx, g.toff,
-                       g.count);
-    return hipGetLastError();
+    FU_CASE(4) FU_CASE(8) FU_CASE(16) FU_CASE(24) FU_CASE(33)
+#undef FU_CASE
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

@@ -27,30 +27,30 @@ int sketch_rows_per_block();
 int sketch_k_tile(int prec);
 
 // Row-block kernels.
-constexpr int ROWS_PER_BLOCK = 64;  // rows per block of the sum / solve / assembly kernels
 hipError_t launch_omega(const LaunchGroup& g, hipStream_t s);          // blocks: ceil(n*l/2/256)
 hipError_t launch_make_op(const LaunchGroup& g, int side, hipStream_t s);  // blocks: ceil(lp*ld/256)
-hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s);
+hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s);  // ceil(rows*lp/4/256)
 // Gram partial sums of a row-major rows x l FP64 matrix picked by `src`.
 enum GramSrc : int32_t { GSRC_Y = 0, GSRC_QA = 1, GSRC_U = 2, GSRC_V = 3 };
 constexpr int GRAM_THREADS = 256;
 hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStream_t s);
-hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int nblk_per_prob, int iter,
+hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int iter,
                               hipStream_t s);
-// dst = src R^{-1} by forward substitution, row by row.
-enum SolveMode : int32_t { SOLVE_Y_TO_QA = 0, SOLVE_Y_TO_Q = 1, SOLVE_QA_TO_Q = 2 };
-hipError_t launch_solve(const LaunchGroup& g, int side, int mode, int iter, hipStream_t s);
+// dst = src R^{-1}, row blocks of 32; nj = ceil(l_max / 64) of the group.
+enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2 };
+hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int nj, int iter, hipStream_t s);
+hipError_t launch_gather_v(const LaunchGroup& g, hipStream_t s);  // blocks: ceil(n*l/256)
 // Column maxima of the FP64 factor and FP8 operand scales.
 hipError_t launch_op_scales(const LaunchGroup& g, int side, int iter, hipStream_t s);
 
 // One block per problem.
 enum CholMode : int32_t { CHOL_FIRST = 0, CHOL_SECOND = 1 };
-hipError_t launch_chol(const LaunchGroup& g, int mode, int iter, hipStream_t s);
-hipError_t launch_qrcp(const LaunchGroup& g, hipStream_t s);
-hipError_t launch_form_uv(const LaunchGroup& g, hipStream_t s);
+hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipStream_t s);
+hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s);
+hipError_t launch_r2(const LaunchGroup& g, int iter, hipStream_t s);  // blocks: nt*nt
+hipError_t launch_form_u(const LaunchGroup& g, int l, hipStream_t s);  // blocks: ceil(m/32)
 hipError_t launch_report(const LaunchGroup& g, int phase, hipStream_t s);
 hipError_t launch_normA(const LaunchGroup& g, hipStream_t s);
-hipError_t launch_explicit_m(const LaunchGroup& g, hipStream_t s);
 hipError_t launch_clear_flags(const LaunchGroup& g, hipStream_t s);
 
 // Stand-alone helpers of the C ABI.

@@ -99,8 +99,8 @@ struct Layout {
 };
 
 enum {
-    O_XOP, O_QOP, O_XSC, O_QSC, O_YPART, O_Y, O_QA, O_Q1, O_Q2, O_GPART, O_G, O_R, O_RACC,
-    O_QT, O_REP, O_FLAGS, O_PERM, O_COUNT
+    O_XOP, O_QOP, O_XSC, O_QSC, O_YPART, O_Y, O_QA, O_Q1, O_Q2, O_GPART, O_G, O_R, O_RINV,
+    O_RACC, O_R2, O_QT, O_TAU, O_REP, O_FLAGS, O_PERM, O_COUNT
 };
 
 static void split_k(int64_t rows, int64_t K, int bk, int target, int32_t* s, int64_t* kc) {
@@ -113,6 +113,8 @@ static void split_k(int64_t rows, int64_t K, int bk, int target, int32_t* s, int
 }
 
 static void gram_chunks(int64_t rows, int lp, int target, int32_t* rb, int32_t* gb) {
+    // Row chunks of the Gram partial sums: about `target` blocks per problem,
+    // at least 64 rows per chunk.
     const int nt = lp / 16;
     const int ntu = nt * (nt + 1) / 2;
     const int ngroups = (ntu + 31) / 32;
@@ -155,7 +157,9 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
     sizes[O_Q1] = (size_t)m * l * 8;
     sizes[O_Q2] = (size_t)n * l * 8;
     sizes[O_GPART] = (size_t)std::max(L.gb_m, L.gb_n) * l * l * 8;
-    sizes[O_G] = sizes[O_R] = sizes[O_RACC] = sizes[O_QT] = (size_t)l * l * 8;
+    sizes[O_G] = sizes[O_R] = sizes[O_RINV] = sizes[O_RACC] = sizes[O_R2] = sizes[O_QT] =
+        (size_t)l * l * 8;
+    sizes[O_TAU] = 2 * LMAX * 8;
     sizes[O_REP] = 128 * 8;
     sizes[O_FLAGS] = 64;
     sizes[O_PERM] = (size_t)l * 4;
@@ -192,6 +196,8 @@ struct Plan {
     int max_q = 0;
     int report = 0;
     int prec_mix = 0;  // bitmask of precisions present
+    int nj = 1;        // ceil(max l / 64): column tiles of the row-block products
+    int lmax = 0;      // largest l of the plan
     std::vector<cor_problem> reqs;
     std::vector<Layout> lay;
     std::vector<Prob> hp;     // host copies of the descriptors
@@ -205,8 +211,9 @@ struct Plan {
         int prec = 0;
         double bytes = 0, flops = 0;  // algorithmic cost of one launch
     };
-    Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, solveM, solveN, uv, norm;
+    Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, applyM, applyN, vg, r2, norm;
     std::vector<Grp> skAX, skATX;  // per (precision, column tiles)
+    std::vector<Grp> formU;        // per register-tile class of l (nt holds l)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     bool async = false;
@@ -247,7 +254,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->report = opts ? opts->report : 0;
     P->reqs.assign(probs, probs + count);
     const int sk_target = std::max(16, 2048 / count);
-    const int gr_target = std::max(2, 256 / count);
+    const int gr_target = std::max(2, 128 / count);
     size_t ws = 0;
     std::vector<size_t> base(count);
     for (int i = 0; i < count; i++) {
@@ -257,6 +264,8 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         ws += P->lay.back().total;
         P->max_q = std::max(P->max_q, (int)q.q);
         P->prec_mix |= 1 << q.prec;
+        P->nj = std::max(P->nj, (int)((q.k + q.p + 63) / 64));
+        P->lmax = std::max(P->lmax, (int)(q.k + q.p));
     }
 
     // Launch tables.
@@ -271,19 +280,37 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     auto R_omega = per([&](int i) { return cdiv(cdiv(probs[i].n * P->lay[i].l, 2), 256); });
     auto R_opM = per([&](int i) { return cdiv(P->lay[i].lp * P->lay[i].ldq, 256); });
     auto R_opN = per([&](int i) { return cdiv(P->lay[i].lp * P->lay[i].ldx, 256); });
-    auto R_sumM = per([&](int i) { return cdiv(probs[i].m, ROWS_PER_BLOCK); });
-    auto R_sumN = per([&](int i) { return cdiv(probs[i].n, ROWS_PER_BLOCK); });
+    auto R_sumM = per([&](int i) { return cdiv(probs[i].m * P->lay[i].lp / 4, 256); });
+    auto R_sumN = per([&](int i) { return cdiv(probs[i].n * P->lay[i].lp / 4, 256); });
     auto R_gramM = per([&](int i) { return (int64_t)P->lay[i].gb_m * gram_groups(P->lay[i].lp); });
     auto R_gramN = per([&](int i) { return (int64_t)P->lay[i].gb_n * gram_groups(P->lay[i].lp); });
-    auto R_red = per([&](int i) { return cdiv((int64_t)P->lay[i].l * P->lay[i].l, 256); });
+    auto R_red = per([&](int i) { return cdiv((int64_t)P->lay[i].l * P->lay[i].l, 64); });
     auto R_small = per([&](int) { return (int64_t)1; });
-    auto R_solveM = per([&](int i) { return cdiv(probs[i].m, 32); });
-    auto R_solveN = per([&](int i) { return cdiv(probs[i].n, 32); });
-    auto R_uv = per([&](int i) { return cdiv(probs[i].m, 32) + cdiv(probs[i].n, 64); });
+    auto R_applyM = per([&](int i) { return cdiv(probs[i].m, 32); });
+    auto R_applyN = per([&](int i) { return cdiv(probs[i].n, 32); });
+    auto R_vg = per([&](int i) { return cdiv(probs[i].n * P->lay[i].l, 256); });
+    auto R_r2 = per([&](int i) { return (int64_t)P->lay[i].nt * P->lay[i].nt; });
     auto R_norm = per([&](int) { return (int64_t)64; });
     // Sketch tables: one per (precision, column-tile count) class.
     std::map<std::pair<int, int>, std::vector<int>> classes;
     for (int i = 0; i < count; i++) classes[{probs[i].prec, P->lay[i].nt}].push_back(i);
+    // U assembly tables: one per class of ceil(l/8).
+    std::map<int, std::vector<int>> uclasses;
+    for (int i = 0; i < count; i++) {
+        const int tn = (P->lay[i].l + 7) / 8;
+        uclasses[tn <= 4 ? 4 : tn <= 8 ? 8 : tn <= 16 ? 16 : tn <= 24 ? 24 : 33].push_back(i);
+    }
+    struct URef { int lmax; TableBuilder::Ref r; };
+    std::vector<URef> urefs;
+    for (auto& kv : uclasses) {
+        std::vector<int64_t> b;
+        int lmax = 0;
+        for (int i : kv.second) {
+            b.push_back(cdiv(probs[i].m, 32));
+            lmax = std::max(lmax, (int)P->lay[i].l);
+        }
+        urefs.push_back({lmax, tb.add(kv.second, b)});
+    }
     struct SkRef { int prec, nt; TableBuilder::Ref ax, atx; double bax, fax, batx, fatx; };
     std::vector<SkRef> skrefs;
     const int64_t bm = sketch_rows_per_block();
@@ -336,6 +363,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         d.k = q.k; d.l = L.l; d.lp = L.lp; d.q = q.q;
         d.prec = q.prec;
         d.report = P->report;
+        d.cholqr2_all = (opts && opts->cholqr2_all) ? 1 : 0;
         const int sz = prec_size(q.prec);
         d.avec = (((uintptr_t)q.A % 16) == 0 && (q.lda * sz) % 16 == 0) ? 1 : 0;
         d.xop = w + L.off[O_XOP];
@@ -353,8 +381,11 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         d.rb_m = L.rb_m; d.rb_n = L.rb_n; d.gb_m = L.gb_m; d.gb_n = L.gb_n;
         d.G = (double*)(w + L.off[O_G]);
         d.R = (double*)(w + L.off[O_R]);
+        d.Rinv = (double*)(w + L.off[O_RINV]);
         d.Racc = (double*)(w + L.off[O_RACC]);
+        d.R2 = (double*)(w + L.off[O_R2]);
         d.Qt = (double*)(w + L.off[O_QT]);
+        d.tau = (double*)(w + L.off[O_TAU]);
         d.rep = (double*)(w + L.off[O_REP]);
         d.flags = (int32_t*)(w + L.off[O_FLAGS]);
         d.U = q.U; d.T = q.T; d.V = q.V;
@@ -398,8 +429,13 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->gramM = mk(R_gramM); P->gramN = mk(R_gramN);
     P->redM = mk(R_red); P->redN = P->redM;
     P->small = mk(R_small);
-    P->solveM = mk(R_solveM); P->solveN = mk(R_solveN);
-    P->uv = mk(R_uv); P->norm = mk(R_norm);
+    P->applyM = mk(R_applyM); P->applyN = mk(R_applyN);
+    P->vg = mk(R_vg); P->r2 = mk(R_r2); P->norm = mk(R_norm);
+    for (auto& u : urefs) {
+        Plan::Grp g = mk(u.r);
+        g.nt = u.lmax;
+        P->formU.push_back(g);
+    }
     for (auto& r : skrefs) {
         Plan::Grp a = mk(r.ax), b = mk(r.atx);
         a.nt = b.nt = r.nt;
@@ -444,12 +480,12 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_sum(P->sumM.g, SIDE_M, it, s));
         E(launch_gram(P->gramM.g, SIDE_M, GSRC_Y, it, s));
         E(launch_gram_reduce(P->redM.g, SIDE_M, 0, it, s));
-        E(launch_chol(P->small.g, CHOL_FIRST, it, s));
-        E(launch_solve(P->solveM.g, SIDE_M, SOLVE_Y_TO_QA, it, s));
+        E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
+        E(launch_apply(P->applyM.g, SIDE_M, AP_Y_RINV_QA, P->nj, it, s));
         E(launch_gram(P->gramM.g, SIDE_M, GSRC_QA, it, s));
-        E(launch_gram_reduce(P->redM.g, SIDE_M, 0, it, s));
-        E(launch_chol(P->small.g, CHOL_SECOND, it, s));
-        E(launch_solve(P->solveM.g, SIDE_M, SOLVE_QA_TO_Q, it, s));
+        E(launch_gram_reduce(P->redM.g, SIDE_M, 1, it, s));
+        E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
+        E(launch_apply(P->applyM.g, SIDE_M, AP_QA_RINV_Q, P->nj, it, s));
         if (fp8) {
             E(launch_op_scales(P->small.g, SIDE_M, it, s));
             E(launch_make_op(P->opM.g, SIDE_M, s));
@@ -459,20 +495,22 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_sum(P->sumN.g, SIDE_N, it, s));
         E(launch_gram(P->gramN.g, SIDE_N, GSRC_Y, it, s));
         E(launch_gram_reduce(P->redN.g, SIDE_N, 0, it, s));
-        E(launch_chol(P->small.g, CHOL_FIRST, it, s));
-        E(launch_solve(P->solveN.g, SIDE_N, SOLVE_Y_TO_QA, it, s));
+        E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
+        E(launch_apply(P->applyN.g, SIDE_N, AP_Y_RINV_QA, P->nj, it, s));
         E(launch_gram(P->gramN.g, SIDE_N, GSRC_QA, it, s));
-        E(launch_gram_reduce(P->redN.g, SIDE_N, 0, it, s));
-        E(launch_chol(P->small.g, CHOL_SECOND, it, s));
-        E(launch_solve(P->solveN.g, SIDE_N, SOLVE_QA_TO_Q, it, s));
+        E(launch_gram_reduce(P->redN.g, SIDE_N, 1, it, s));
+        E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
+        E(launch_r2(P->r2.g, it, s));
+        E(launch_apply(P->applyN.g, SIDE_N, AP_QA_RINV_Q, P->nj, it, s));
         if (fp8 && it < P->max_q) {
             E(launch_op_scales(P->small.g, SIDE_N, it, s));
             E(launch_make_op(P->opN.g, SIDE_N, s));
         }
     }
     // M = Q1^T A Q2 = R2^T; M P = Qt T; U = Q1 Qt, V = Q2 P.
-    E(launch_qrcp(P->small.g, s));
-    E(launch_form_uv(P->uv.g, s));
+    E(launch_qrcp(P->small.g, P->lmax, s));
+    for (const auto& ug : P->formU) E(launch_form_u(ug.g, ug.nt, s));
+    E(launch_gather_v(P->vg.g, s));
     if (P->report) {
         E(launch_gram(P->gramM.g, SIDE_M, GSRC_U, -1, s));
         E(launch_gram_reduce(P->redM.g, SIDE_M, 0, -1, s));
@@ -560,7 +598,7 @@ int plan_report(const Plan* P) { return P->report; }
 size_t plan_bytes(const Plan* P) { return P->mem_bytes; }
 
 size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec) {
-    Layout L = make_layout(m, n, l, prec, 2048, 256);
+    Layout L = make_layout(m, n, l, prec, 2048, 128);
     return L.total + 256 + 1024;
 }
 
@@ -790,3 +828,4 @@ cor_status cor_release(void) {
 }
 
 }  // extern "C"
+
