@@ -110,6 +110,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates the "
+                         "HBM byte counters against a kernel of known traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: multi-GPU runs are not part of this build "
@@ -120,6 +123,17 @@ def main():
     import torch
 
     import paper_1810_07323_amd as cu
+
+    if args.copy_calib:
+        nbytes = args.copy_calib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read": nbytes, "copy_calib_bytes_written": nbytes,
+                          "launches": 5}))
+        return
 
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")

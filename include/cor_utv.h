@@ -3,21 +3,21 @@
  *
  * Compressed Randomized UTV with power iteration (Kaloorazi & de Lamare,
  * "Compressed Randomized UTV Decompositions for Low-Rank Approximations and
- * Big Data Applications", Sec. III, Alg. 1 and Alg. 3).  Given A (m x n) and
+ * Big Data Applications", Sec. III, Alg. 2 and Alg. 3).  Given A (m x n) and
  * integers k <= l = k + p < min(m, n) and q >= 0, the library returns a
  * rank-l approximation A ~ U T V^T with U (m x l) and V (n x l) orthonormal
  * and T (l x l) upper triangular whose diagonal tracks the leading singular
- * values of A (the URV form of eq. (eq_T_basic)).
+ * values of A (the URV form of eq. (16)).
  *
  * What runs, per decomposition (all on the GPU):
  *   X = Omega (i.i.d. N(0,1), n x l)                      [Alg. 3, step 1]
  *   repeat q+1 times:                                      [Alg. 3, loop]
- *     Y1 = A X          -> Q1 R1 = Y1 (CholeskyQR2, FP64)  [eq. (eq_C1_1st)]
- *     Y2 = A^T Q1       -> Q2 R2 = Y2 (CholeskyQR2, FP64)  [eq. (eqAC1)]
+ *     Y1 = A X          -> Q1 R1 = Y1 (CholeskyQR2, FP64)  [eq. (11)]
+ *     Y2 = A^T Q1       -> Q2 R2 = Y2 (CholeskyQR2, FP64)  [eq. (12)]
  *     X  = Q2
- *   M = Q1^T A Q2 = R2^T                                   [eq. (eqM)]
- *   M P = Qt T  (column-pivoted QR, FP64)                  [eq. (eq_Drrqr)]
- *   U = Q1 Qt,  V = Q2 P                                   [eq. (eq_T_basic)]
+ *   M = Q1^T A Q2 = R2^T                                   [eq. (14)]
+ *   M P = Qt T  (column-pivoted QR, FP64)                  [eq. (15)]
+ *   U = Q1 Qt,  V = Q2 P                                   [eq. (16)]
  * The second sketch uses Q1 instead of the paper's un-normalised C1 and every
  * product with A is orthonormalised before the next one; both leave Q1, Q2 and
  * M unchanged in exact arithmetic.  M = R2^T holds because

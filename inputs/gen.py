@@ -15,7 +15,7 @@ import numpy as np
 # ---------------------------------------------------------------------------
 # Workload table.  Sizes follow the paper's problem statement (A is m x n,
 # k <= l < min(m, n), l = k + p, q power steps) at the shapes of the
-# benchmark workloads named in the design doc.
+# benchmark workloads (1000^2 FP64, 8000^2 FP32, 20000x10000 BF16).
 # ---------------------------------------------------------------------------
 CONFIGS = {
     # 1000x1000 FP64, Haar U,V, sigma_i = 1 (i<=10), 1e-3*0.9^(i-10) after,

@@ -1,11 +1,11 @@
 /*
  * CoR-UTV FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
- * Follows Sec. III of the paper: Alg. 1 (no power iteration) and Alg. 3
- * (power method), the compression D = Q1^T A Q2 of eq. (eqM), the QRCP
- * D = Q~ R~ P~^T of eq. (eq_Drrqr) and the assembly U = Q1 Q~, T = R~,
- * V = Q2 P~ of eq. (eq_T_basic).  Accuracy measures follow the rank-l error
- * (eq. AppErrorCoR, here in the Frobenius norm) and the rank-k truncation
+ * Follows Sec. III of the paper: Alg. 2 (no power iteration) and Alg. 3
+ * (power method), the compression D = Q1^T A Q2 of eq. (14), the QRCP
+ * D = Q~ R~ P~^T of eq. (15) and the assembly U = Q1 Q~, T = R~,
+ * V = Q2 P~ of eq. (16).  Accuracy measures follow the rank-l error
+ * (eq. (43), here in the Frobenius norm) and the rank-k truncation
  * U(:,1:k) T(1:k,:) V^T of Sec. VI-B.
  */
 #include "oracle.h"
@@ -17,7 +17,7 @@
 #define IDX(i, j, ld) ((int64_t)(i) * (int64_t)(ld) + (int64_t)(j))
 
 /* ------------------------------------------------------------------------ */
-/* Gaussian test matrix Psi (Alg. 1 / Alg. 3, first step).                   */
+/* Gaussian test matrix Psi (Alg. 2 / Alg. 3, first step).                   */
 /* ------------------------------------------------------------------------ */
 uint64_t orc_splitmix64(uint64_t seed, uint64_t index) {
     /* Output `index` (0-based) of SplitMix64: state advances by the golden
@@ -153,7 +153,7 @@ int orc_qr(const double* Y, int64_t r, int32_t c, int64_t ldy, double* Q, double
 }
 
 /* ------------------------------------------------------------------------ */
-/* QRCP of the compressed matrix, eq. (eq_Drrqr): D P~ = Q~ R~.               */
+/* QRCP of the compressed matrix, eq. (15): D P~ = Q~ R~.               */
 /* ------------------------------------------------------------------------ */
 int orc_qrcp(const double* M, int32_t l, double* Qt, double* T, int32_t* perm, double* min_gap) {
     if (l < 1) return ORC_EINVAL;
@@ -232,7 +232,7 @@ static double orth_loss(const double* Q, int64_t r, int32_t c) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Alg. 3 (Alg. 1 when q = 0).                                               */
+/* Alg. 3 (Alg. 2 when q = 0).                                               */
 /* ------------------------------------------------------------------------ */
 int orc_cor_utv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t k, int32_t p,
                 int32_t q, const double* omega, double* U, double* T, double* V,
@@ -273,7 +273,7 @@ int orc_cor_utv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t k, i
         memcpy(X, Q2, sz_n);
     }
 
-    /* Compression D = Q1^T A Q2, eq. (eqM), by its definition. */
+    /* Compression D = Q1^T A Q2, eq. (14), by its definition. */
     orc_gemm_nn(A, m, n, lda, Q2, l, l, Z);
     orc_gemm_tn(Q1, m, l, l, Z, l, l, M);
 

@@ -4,7 +4,7 @@
  * A plain, slow, single-threaded implementation of Compressed Randomized UTV
  * with power iteration (Kaloorazi & de Lamare, "Compressed Randomized UTV
  * Decompositions for Low-Rank Approximations and Big Data Applications",
- * Sec. III, Alg. 1 and Alg. 3).  It exists to check the GPU library; only the
+ * Sec. III, Alg. 2 and Alg. 3).  It exists to check the GPU library; only the
  * test suite, the smoke check and the CPU baseline leg of the benchmark may
  * load it.  It shares no code, header, table or constant with the GPU path.
  *

@@ -2,9 +2,9 @@
 //   - Cholesky of the Gram matrix (CholeskyQR of C1, C2 in Alg. 3) and the
 //     accumulated R factor of the orthonormalisation;
 //   - the column-pivoted QR of the compressed matrix M = Q1^T A Q2 = R2^T,
-//     eq. (eq_Drrqr): Businger-Golub pivoting on exactly recomputed trailing
+//     eq. (15): Businger-Golub pivoting on exactly recomputed trailing
 //     column norms (lowest index on ties), Householder reflections, T_jj >= 0;
-//   - U = Q1 Qt and V = Q2 P of eq. (eq_T_basic);
+//   - U = Q1 Qt and V = Q2 P of eq. (16);
 //   - the accuracy report and the stand-alone format conversion.
 #include "common.h"
 #include "kernels.h"

@@ -28,7 +28,7 @@ def _signfix_qr(y):
 
 
 # --------------------------------------------------------------------------
-# Gaussian test matrix (Alg. 1 / Alg. 3 first step)
+# Gaussian test matrix (Alg. 2 / Alg. 3 first step)
 # --------------------------------------------------------------------------
 def test_splitmix64_reference_output(orc):
     # First output of SplitMix64 started from state 0, as produced by the
@@ -189,7 +189,7 @@ def test_metrics_identity_with_exact_compression(orc):
 
 
 def test_compression_equals_r2_transpose_and_d_approx(orc):
-    # Alg. 1 as printed (q = 0): C1 = A Psi, C2 = A^T C1, QR of both, explicit
+    # Alg. 2 as printed (q = 0): C1 = A Psi, C2 = A^T C1, QR of both, explicit
     # D = Q1^T A Q2 and the single-pass D_approx = Q1^T C1 (Q2^T Psi)^+.
     # The oracle instead forms C2 = A^T Q1.  Closed forms: Q2 is the same,
     # D = D_approx = R1^-T R2'^T and D = R2^T (R2 of A^T Q1).
