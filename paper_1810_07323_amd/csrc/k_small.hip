@@ -9,10 +9,14 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace cor {
 
 constexpr int CHOL_LDS_MAX = 128;  // l*l + 16*l doubles + scratch fit in 160 KB of LDS
 constexpr int QRCP_LDS_MAX = 136;  // l*l doubles + scratch
+constexpr int QRT_LMAX = 128;      // register-resident QRCP: 4 lanes per column
+constexpr int QRT_THREADS = 4 * QRT_LMAX;
 
 __device__ __forceinline__ const Prob& group_prob2(const Prob* probs, const int32_t* pidx,
                                                    const int32_t* toff, int cnt, int& local) {
@@ -204,23 +208,122 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol(const Prob* __restrict__ 
 // E = L^{-1} (G = L D L^T, L unit lower).  Then
 //   R    = D^{1/2} L^T   : R[j][b]    = v_b / sqrt(d_j)          (b >= j)
 //   R^-1 = L^{-T} D^-1/2 : R^-1[b][j] = E[j][b] / sqrt(d_j)      (b <  j)
-// and row j is final at step j, so its owners write row j of R and column j
-// of R^{-1} straight to global memory.  Each of 1024 threads keeps one 4 x 4
-// tile in registers; row j and the pivot scalars are published through LDS
-// (double-buffered), one barrier per column.  A pivot d_j <= l 2^-52
-// max_i G_ii is clamped to that threshold (numerically rank-deficient sketch)
-// and flagged.  mode FIRST also stores R in Racc (for R2 = R' R).
+//
+// Each thread keeps one 4 x 4 tile in registers (ceil(l/4)^2 threads).  The
+// owners of row j publish it in LDS (double-buffered) as three vectors, so
+// that the column step needs no per-element selects:
+//   fa[a] = v_a for a > j, else 0          (row multipliers, times 1/d_j)
+//   rU[b] = v_b                            (Schur part, read by b >= a)
+//   rL[b] = E[j][b] for b < j, 1 at b = j, 0 after   (E part, read by b < a)
+// and the owner of the diagonal tile publishes 1/d_j.  The column loop is
+// unrolled by four, so the published row's place inside its tile is a
+// compile-time index.  Dependent FP64 operations are slow (tens of cycles
+// each), so the only arithmetic on the serial path of a column is one
+// update, the reciprocal of the next pivot (hardware estimate refined by two
+// Newton steps) and the LDS exchange; square roots for R and R^{-1} are
+// taken after the loop.  Tiles are numbered strictly-upper (row-major),
+// diagonal, strictly-lower (column-major), so a wave holds one kind of tile
+// (but for the two waves at the seams), and the waves whose rows are done,
+// or whose E columns have not started, skip the step as a whole.  A pivot
+// d_j <= l 2^-52 max_i G_ii is clamped to that threshold (numerically
+// rank-deficient sketch) and flagged.  mode FIRST also stores R in Racc (for
+// R2 = R' R).
 // ---------------------------------------------------------------------------
 constexpr int CRT_THREADS = 1024;
 constexpr int CRT_LMAX = 128;
+
+// 1/d from the hardware estimate and two Newton steps y <- y + y (1 - d y).
+__device__ __forceinline__ double recip_nr(double d) {
+    double y = __builtin_amdgcn_rcp(d);
+#pragma unroll
+    for (int it = 0; it < 2; it++) y = fma(y, fma(-d, y, 1.0), y);
+    return y;
+}
+
+// Publication of row jr by the owners of its tile row (local row R inside
+// the tile): this thread's four entries (columns b0..b0+3) into the three
+// row vectors; the owner of the diagonal tile also publishes d and 1/d.
+template <int R>
+__device__ __forceinline__ void chol_publish(const double (&x)[4][4], int jr, int b0, bool diag,
+                                             double tol, double* fa, double* ru, double* rl,
+                                             double* s_d, double* s_inv, int slot,
+                                             int* clamped) {
+    double f[4], lv[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const int b = b0 + c;
+        f[c] = b > jr ? x[R][c] : 0.0;
+        lv[c] = b < jr ? x[R][c] : (b == jr ? 1.0 : 0.0);
+    }
+    if (diag) {
+        double d = x[R][R];
+        if (!(d > tol)) {
+            d = tol;
+            *clamped = 1;
+        }
+        s_inv[slot] = recip_nr(d);
+        s_d[jr] = d;
+    }
+    *reinterpret_cast<double2*>(&fa[b0]) = make_double2(f[0], f[1]);
+    *reinterpret_cast<double2*>(&fa[b0 + 2]) = make_double2(f[2], f[3]);
+    *reinterpret_cast<double2*>(&ru[b0]) = make_double2(x[R][0], x[R][1]);
+    *reinterpret_cast<double2*>(&ru[b0 + 2]) = make_double2(x[R][2], x[R][3]);
+    *reinterpret_cast<double2*>(&rl[b0]) = make_double2(lv[0], lv[1]);
+    *reinterpret_cast<double2*>(&rl[b0 + 2]) = make_double2(lv[2], lv[3]);
+}
+
+// One column step j: eliminate column j (published in slot sl) from this
+// thread's tile.
+__device__ __forceinline__ void chol_step(double (&x)[4][4], int j, int kind, int a0, int b0,
+                                          const double* fa_s, const double* ru_s,
+                                          const double* rl_s, double inv_d) {
+    if (!(a0 + 3 > j) || (kind == 2 && b0 > j)) return;
+    const double2 f01 = *reinterpret_cast<const double2*>(&fa_s[a0]);
+    const double2 f23 = *reinterpret_cast<const double2*>(&fa_s[a0 + 2]);
+    const double fa[4] = {f01.x * inv_d, f01.y * inv_d, f23.x * inv_d, f23.y * inv_d};
+    if (kind == 0) {
+        const double2 u01 = *reinterpret_cast<const double2*>(&ru_s[b0]);
+        const double2 u23 = *reinterpret_cast<const double2*>(&ru_s[b0 + 2]);
+        const double cb[4] = {u01.x, u01.y, u23.x, u23.y};
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) x[r][c] = fma(-fa[r], cb[c], x[r][c]);
+    } else if (kind == 2) {
+        const double2 l01 = *reinterpret_cast<const double2*>(&rl_s[b0]);
+        const double2 l23 = *reinterpret_cast<const double2*>(&rl_s[b0 + 2]);
+        const double cb[4] = {l01.x, l01.y, l23.x, l23.y};
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) x[r][c] = fma(-fa[r], cb[c], x[r][c]);
+    } else {
+        const double2 u01 = *reinterpret_cast<const double2*>(&ru_s[b0]);
+        const double2 u23 = *reinterpret_cast<const double2*>(&ru_s[b0 + 2]);
+        const double2 l01 = *reinterpret_cast<const double2*>(&rl_s[b0]);
+        const double2 l23 = *reinterpret_cast<const double2*>(&rl_s[b0 + 2]);
+        const double cu[4] = {u01.x, u01.y, u23.x, u23.y};
+        const double cl[4] = {l01.x, l01.y, l23.x, l23.y};
+        // the diagonal element first: it feeds the next pivot
+#pragma unroll
+        for (int r = 0; r < 4; r++) x[r][r] = fma(-fa[r], cu[r], x[r][r]);
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++)
+                if (c != r) x[r][c] = fma(-fa[r], c > r ? cu[c] : cl[c], x[r][c]);
+    }
+}
 
 __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict__ probs,
                                                         const int32_t* __restrict__ pidx,
                                                         const int32_t* __restrict__ toff, int cnt,
                                                         int mode, int iter) {
-    __shared__ __align__(16) double s_row[2][CRT_LMAX];
-    __shared__ double s_sc[2][4];
-    __shared__ double s_sq[CRT_LMAX], s_rsq[CRT_LMAX];  // sqrt(d_j), 1/sqrt(d_j)
+    __shared__ __align__(16) double s_fa[2][CRT_LMAX];
+    __shared__ __align__(16) double s_ru[2][CRT_LMAX];
+    __shared__ __align__(16) double s_rl[2][CRT_LMAX];
+    __shared__ double s_inv[2];
+    __shared__ double s_d[CRT_LMAX];  // pivots d_j
     __shared__ double s_tol;
     __shared__ int s_clamped;
     int local;
@@ -231,15 +334,35 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
     if (l > CRT_LMAX) return;
     const int tid = threadIdx.x;
     const int nt4 = (l + 3) / 4;
+    const int nup = nt4 * (nt4 - 1) / 2;  // strictly upper tiles
     const bool own = tid < nt4 * nt4;
-    const int ta = own ? tid / nt4 : 0, tb = own ? tid % nt4 : 0;
+    // tile of this thread: kind 0 strictly upper, 1 diagonal, 2 strictly lower
+    int ta = 0, tb = 0, kind = 1;
+    if (own) {
+        if (tid < nup) {  // row-major over ta < tb
+            int r = 0, rem = tid;
+            while (rem >= nt4 - 1 - r) { rem -= nt4 - 1 - r; r++; }
+            ta = r; tb = r + 1 + rem; kind = 0;
+        } else if (tid < nup + nt4) {
+            ta = tb = tid - nup; kind = 1;
+        } else {  // column-major over tb < ta
+            int c = 0, rem = tid - nup - nt4;
+            while (rem >= nt4 - 1 - c) { rem -= nt4 - 1 - c; c++; }
+            tb = c; ta = c + 1 + rem; kind = 2;
+        }
+    } else {
+        ta = tb = -1;  // no tile: never active, never publishes
+    }
     const int a0 = 4 * ta, b0 = 4 * tb;
+    const bool diag = own && kind == 1;
     const double* __restrict__ G = P.G;
-    double* __restrict__ Rout = P.R;
-    double* __restrict__ Rinv = P.Rinv;
-    double* __restrict__ Racc = P.Racc;
     const bool first = mode == CHOL_FIRST;
 
+    for (int e = tid; e < 2 * CRT_LMAX; e += blockDim.x) {
+        (&s_fa[0][0])[e] = 0.0;
+        (&s_ru[0][0])[e] = 0.0;
+        (&s_rl[0][0])[e] = 0.0;
+    }
     double x[4][4];
 #pragma unroll
     for (int r = 0; r < 4; r++)
@@ -261,93 +384,56 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
     }
     __syncthreads();
     const double tol = s_tol;
-    // publish row 0 and the first pivot
-    if (own && ta == 0) {
-#pragma unroll
-        for (int c = 0; c < 4; c++)
-            if (b0 + c < l) s_row[0][b0 + c] = x[0][c];
-        if (tb == 0) {
-            chol_pivot(x[0][0], tol, s_sc[0], &s_clamped);
-            s_sq[0] = s_sc[0][2];
-            s_rsq[0] = s_sc[0][3];
-        }
-    }
+    if (own && ta == 0)
+        chol_publish<0>(x, 0, b0, diag, tol, s_fa[0], s_ru[0], s_rl[0], s_d, s_inv, 0, &s_clamped);
     __syncthreads();
 
     // The loop touches only registers and LDS: a barrier then never waits for
     // global memory.  Rows are final once their step has passed, so R and
-    // R^{-1} are written from the registers after the loop.
-    for (int j = 0; j < l; j++) {
-        const int sl = j & 1;
-        const double inv_d = s_sc[sl][1];
-        // Elimination of column j from rows a > j.
-        if (own && a0 + 3 > j) {
-            double fa[4], cb[4];
+    // R^{-1} are written from the registers after the loop.  Column j = 4 jb + jj.
+    for (int jb = 0; 4 * jb < l; jb++) {
 #pragma unroll
-            for (int r = 0; r < 4; r++) fa[r] = (a0 + r < l) ? s_row[sl][a0 + r] * inv_d : 0.0;
-#pragma unroll
-            for (int c = 0; c < 4; c++) {
-                const int b = b0 + c;
-                cb[c] = b == j ? 1.0 : (b < l ? s_row[sl][b] : 0.0);
-            }
-            if (ta < tb) {  // Schur complement block: every column b > a > j
-#pragma unroll
-                for (int r = 0; r < 4; r++)
-                    if (a0 + r > j)
-#pragma unroll
-                        for (int c = 0; c < 4; c++) x[r][c] -= fa[r] * cb[c];
-            } else if (ta > tb) {  // E block: columns b <= j
-                if (b0 <= j) {
-#pragma unroll
-                    for (int r = 0; r < 4; r++)
-                        if (a0 + r > j)
-#pragma unroll
-                            for (int c = 0; c < 4; c++)
-                                if (b0 + c <= j) x[r][c] -= fa[r] * cb[c];
-                }
-            } else {  // diagonal block: both kinds
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int a = a0 + r;
-                    if (a > j)
-#pragma unroll
-                        for (int c = 0; c < 4; c++) {
-                            const int b = b0 + c;
-                            if (b >= a || b <= j) x[r][c] -= fa[r] * cb[c];
+        for (int jj = 0; jj < 4; jj++) {
+            const int j = 4 * jb + jj;
+            if (j < l) {
+                const int sl = jj & 1;
+                chol_step(x, j, kind, a0, b0, s_fa[sl], s_ru[sl], s_rl[sl], s_inv[sl]);
+                // publish row j + 1: local row jj + 1 of tile row jb, or row 0 of tile row jb + 1
+                if (j + 1 < l) {
+                    if (jj < 3) {
+                        if (ta == jb) {
+                            if (jj == 0)
+                                chol_publish<1>(x, j + 1, b0, diag, tol, s_fa[sl ^ 1], s_ru[sl ^ 1],
+                                                s_rl[sl ^ 1], s_d, s_inv, sl ^ 1, &s_clamped);
+                            else if (jj == 1)
+                                chol_publish<2>(x, j + 1, b0, diag, tol, s_fa[sl ^ 1], s_ru[sl ^ 1],
+                                                s_rl[sl ^ 1], s_d, s_inv, sl ^ 1, &s_clamped);
+                            else
+                                chol_publish<3>(x, j + 1, b0, diag, tol, s_fa[sl ^ 1], s_ru[sl ^ 1],
+                                                s_rl[sl ^ 1], s_d, s_inv, sl ^ 1, &s_clamped);
                         }
+                    } else if (ta == jb + 1) {
+                        chol_publish<0>(x, j + 1, b0, diag, tol, s_fa[sl ^ 1], s_ru[sl ^ 1],
+                                        s_rl[sl ^ 1], s_d, s_inv, sl ^ 1, &s_clamped);
+                    }
                 }
+                __syncthreads();
             }
         }
-        // Publish row j + 1 (Schur part for b > j, E part for b <= j) and its pivot.
-        if (own && j + 1 < l && ta == ((j + 1) >> 2)) {
-            const int r = j + 1 - a0;
-#pragma unroll
-            for (int c = 0; c < 4; c++) {
-                const int b = b0 + c;
-                if (b >= l) continue;
-                double xv = x[0][c];
-                if (r == 1) xv = x[1][c];
-                else if (r == 2) xv = x[2][c];
-                else if (r == 3) xv = x[3][c];
-                s_row[sl ^ 1][b] = xv;
-                if (b == j + 1) {
-                    chol_pivot(xv, tol, s_sc[sl ^ 1], &s_clamped);
-                    s_sq[j + 1] = s_sc[sl ^ 1][2];
-                    s_rsq[j + 1] = s_sc[sl ^ 1][3];
-                }
-            }
-        }
-        __syncthreads();
     }
     if (tid == 0 && s_clamped) atomicOr(P.flags, FLAG_RANK_DEF);
     // R[a][b] = v_b / sqrt(d_a) (b > a), sqrt(d_a) (b = a), 0 below;
     // R^{-1}[b][a] = E[a][b] / sqrt(d_a) (b < a), 1/sqrt(d_a) (b = a), 0 above.
     if (own) {
+        double* __restrict__ Rout = P.R;
+        double* __restrict__ Rinv = P.Rinv;
+        double* __restrict__ Racc = P.Racc;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int a = a0 + r;
             if (a >= l) continue;
-            const double sq = s_sq[a], rsq = s_rsq[a];
+            const double sq = sqrt(s_d[a]);
+            const double rsq = 1.0 / sq;
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 const int b = b0 + c;
@@ -364,7 +450,10 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
 
 hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chol_rt, dim3(g.blocks), dim3(CRT_THREADS), 0, s, g.probs, g.pidx,
+    // ceil(l/4)^2 tile owners, rounded up to whole waves
+    const int nt4 = (std::min(lmax, CRT_LMAX) + 3) / 4;
+    const int threads = std::min(CRT_THREADS, (nt4 * nt4 + 63) / 64 * 64);
+    hipLaunchKernelGGL(k_chol_rt, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx,
                        g.toff, g.count, mode, iter);
     hipError_t er = hipGetLastError();
     if (er != hipSuccess || lmax <= CRT_LMAX) return er;
@@ -439,6 +528,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_qrcp(const Prob* __restrict__ pr
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
     const int l = P.l;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (l <= QRT_LMAX) return;  // k_qrcp_rt
     if (IN_LDS != (l <= QRCP_LDS_MAX)) return;
     double* W;
     if constexpr (IN_LDS) W = sm;
@@ -565,8 +655,220 @@ __global__ __launch_bounds__(QR_THREADS) void k_qrcp(const Prob* __restrict__ pr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident QRCP of M = R2^T for l <= 128 (one block per problem).
+//   Four adjacent lanes own one column of M; lane t of the quad keeps rows
+//   i = 4u + t (u < RPT) in registers, so the trailing matrix never leaves
+//   the register file and per-column dot products and norms are quad sums
+//   (two DPP steps).  Columns stay in place; the pivot column of step j is
+//   found with the 64-bit key above and retired after the step.  Step j:
+//     1. the pivot quad copies its raw column into slot j of an LDS archive
+//        (laid out [t][u] so that a lane moves 16 bytes at a time), reads
+//        alpha = M[j][p] back and forms beta, tau and scale = 1/(alpha-beta)
+//        (reflector v_i = scale*M[i][p] below j, v_j = 1, zero above);
+//     2. every remaining column reads the archived pivot column:
+//        w = tau (col_j + scale sum_{i>j} raw_i col_i), col_j -= w,
+//        col_i -= (w scale) raw_i below j, and posts the squared norm of its
+//        rows below j as the next step's key.
+//   Rows above j are skipped in blocks of 4*CH rows (uniform branches); only
+//   the block holding row j needs per-element selects.  Two barriers per
+//   step and no global memory access inside the loop: T, the reflectors,
+//   tau, the signs of T_jj and perm are written from the archive at the end.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_mov<0xB1>(v);  // quad_perm 1,0,3,2
+    v += dpp_mov<0x4E>(v);  // quad_perm 2,3,0,1
+    return v;
+}
+
+template <int RPT>
+__host__ __device__ constexpr int qrt_stride() { return RPT + 2; }  // doubles per archived lane row
+
+template <int RPT>
+__host__ __device__ constexpr size_t qrt_lds_bytes() {
+    return sizeof(double) * (size_t)(4 * RPT) * 4 * qrt_stride<RPT>();
+}
+
+template <int RPT>
+__global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict__ probs,
+                                                         const int32_t* __restrict__ pidx,
+                                                         const int32_t* __restrict__ toff,
+                                                         int cnt) {
+    constexpr int LR = 4 * RPT;   // rows covered
+    constexpr int ST = qrt_stride<RPT>();
+    constexpr int CH = RPT < 8 ? RPT : 8;  // u per row block
+    constexpr int NCH = RPT / CH;
+    extern __shared__ __align__(16) double s_arc[];  // [LR steps][4 lanes][ST]
+    __shared__ double s_nrm[LR];
+    __shared__ double s_tau[LR], s_scale[LR], s_beta[LR];
+    __shared__ int s_perm[LR];
+    __shared__ unsigned long long s_key[2];
+    int local;
+    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
+    const int l = P.l;
+    if (l > LR) return;
+    const int tid = threadIdx.x;
+    const int c = tid >> 2, t = tid & 3;
+    const bool incol = c < l;
+    const double* __restrict__ R2 = P.R2;
+
+    double col[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; u++) {
+        const int i = 4 * u + t;
+        col[u] = (incol && i < l) ? R2[c * l + i] : 0.0;  // M[i][c] = R2[c][i]
+    }
+    double nn = 0.0;
+#pragma unroll
+    for (int u = 0; u < RPT; u++) nn = fma(col[u], col[u], nn);
+    nn = quad_sum(nn);
+    if (tid < 2) s_key[tid] = 0ull;
+    __syncthreads();
+    if (incol && t == 0) {
+        s_nrm[c] = nn;
+        atomicMax(&s_key[0], qr_key(nn, c));
+    }
+    bool active = incol;
+    __syncthreads();
+
+    for (int j = 0; j < l; j++) {
+        const unsigned long long key = s_key[j & 1];
+        const int p = 511 - (int)(key & 0x1FFull);
+        double* arc = s_arc + j * 4 * ST;
+        if (c == p) {
+#pragma unroll
+            for (int u = 0; u < RPT; u += 2)
+                *reinterpret_cast<double2*>(arc + t * ST + u) = make_double2(col[u], col[u + 1]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double alpha = arc[(j & 3) * ST + (j >> 2)];
+            const double ss = s_nrm[p];  // sum over rows >= j of column p squared
+            const double xnorm = sqrt(ss);
+            double tau = 0.0, beta = alpha, scale = 1.0;
+            if (xnorm != 0.0) {
+                beta = alpha >= 0.0 ? -xnorm : xnorm;
+                scale = 1.0 / (alpha - beta);
+                tau = (beta - alpha) / beta;
+            }
+            if (t == 0) {
+                s_tau[j] = tau;
+                s_scale[j] = scale;
+                s_beta[j] = beta;
+                s_perm[j] = p;
+                s_key[(j + 1) & 1] = 0ull;
+            }
+            active = false;
+        }
+        __syncthreads();
+        if (active) {
+            const double tau = s_tau[j], scale = s_scale[j];
+            const double* arct = arc + t * ST;
+            double raw[RPT];
+            double dm = 0.0, du = 0.0;  // masked block / blocks below row j
+#pragma unroll
+            for (int q = 0; q < NCH; q++) {
+                const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
+                if (hi < j) continue;
+#pragma unroll
+                for (int u = q * CH; u < q * CH + CH; u += 2) {
+                    const double2 r2 = *reinterpret_cast<const double2*>(arct + u);
+                    raw[u] = r2.x;
+                    raw[u + 1] = r2.y;
+                }
+                if (lo > j) {
+#pragma unroll
+                    for (int u = q * CH; u < q * CH + CH; u++) du = fma(raw[u], col[u], du);
+                } else {
+#pragma unroll
+                    for (int u = q * CH; u < q * CH + CH; u++) {
+                        const int i = 4 * u + t;
+                        const double vv = i > j ? raw[u] * scale : (i == j ? 1.0 : 0.0);
+                        dm = fma(vv, col[u], dm);
+                    }
+                }
+            }
+            const double w = tau * quad_sum(fma(scale, du, dm));
+            const double ws = w * scale;
+            double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < NCH; q++) {
+                const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
+                if (hi < j) continue;
+                if (lo > j) {
+#pragma unroll
+                    for (int u = q * CH; u < q * CH + CH; u++) {
+                        col[u] = fma(-ws, raw[u], col[u]);
+                        if (u & 1) n1 = fma(col[u], col[u], n1);
+                        else n0 = fma(col[u], col[u], n0);
+                    }
+                } else {
+#pragma unroll
+                    for (int u = q * CH; u < q * CH + CH; u++) {
+                        const int i = 4 * u + t;
+                        const double vv = i > j ? raw[u] * scale : (i == j ? 1.0 : 0.0);
+                        col[u] = fma(-w, vv, col[u]);
+                        if (i > j) n0 = fma(col[u], col[u], n0);
+                    }
+                }
+            }
+            const double n = quad_sum(n0 + n1);
+            if (t == 0) {
+                s_nrm[c] = n;
+                atomicMax(&s_key[(j + 1) & 1], qr_key(n, c));
+            }
+        }
+        __syncthreads();
+    }
+
+    // Outputs from the archive: raw_j[i] = M[i][perm j] after step j - 1.
+    for (int e = tid; e < l * l; e += blockDim.x) {
+        const int a = e / l, b = e % l;
+        // T[a][b] (row a, column b): rows above b hold the archived column b.
+        double tv = 0.0;
+        if (a < b) tv = s_arc[b * 4 * ST + (a & 3) * ST + (a >> 2)] * (s_beta[a] < 0.0 ? -1.0 : 1.0);
+        else if (a == b) tv = fabs(s_beta[a]);
+        P.T[e] = tv;
+        // reflector a, component b
+        double vv = 0.0;
+        if (b == a) vv = 1.0;
+        else if (b > a) vv = s_arc[a * 4 * ST + (b & 3) * ST + (b >> 2)] * s_scale[a];
+        P.Qt[e] = vv;
+    }
+    for (int j = tid; j < l; j += blockDim.x) {
+        P.tau[j] = s_tau[j];
+        P.tau[LMAX + j] = s_beta[j] < 0.0 ? -1.0 : 1.0;
+        P.perm[j] = s_perm[j];
+    }
+}
+
+template <int RPT>
+static hipError_t launch_qrcp_rt(const LaunchGroup& g, int threads, hipStream_t s) {
+    constexpr size_t lds = qrt_lds_bytes<RPT>();
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_qrcp_rt<RPT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_qrcp_rt<RPT>, dim3(g.blocks), dim3(threads), lds, s, g.probs, g.pidx,
+                       g.toff, g.count);
+    return hipGetLastError();
+}
+
 hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
+    {
+        const int lr = std::min(lmax, QRT_LMAX);
+        const int threads = 4 * ((lr + 15) / 16 * 16);
+        hipError_t e = lr <= 16   ? launch_qrcp_rt<4>(g, threads, s)
+                       : lr <= 32 ? launch_qrcp_rt<8>(g, threads, s)
+                       : lr <= 64 ? launch_qrcp_rt<16>(g, threads, s)
+                                  : launch_qrcp_rt<32>(g, threads, s);
+        if (e != hipSuccess || lmax <= QRT_LMAX) return e;
+    }
+    // l > 128: M in LDS (l <= 136) or in global memory.
     const size_t lds = sizeof(double) * QRCP_LDS_MAX * QRCP_LDS_MAX;
     static bool attr = false;
     if (!attr) {

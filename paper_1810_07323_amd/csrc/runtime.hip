@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -103,9 +104,11 @@ enum {
     O_RACC, O_R2, O_QT, O_TAU, O_REP, O_FLAGS, O_PERM, O_COUNT
 };
 
+// K splits of a pass: about `target` blocks in all (row blocks x splits, never
+// more), each split at least 4 K tiles long.
 static void split_k(int64_t rows, int64_t K, int bk, int target, int32_t* s, int64_t* kc) {
     const int64_t nrb = cdiv(rows, sketch_rows_per_block());
-    int64_t sp = std::max<int64_t>(1, cdiv(target, nrb));
+    int64_t sp = std::max<int64_t>(1, target / nrb);
     sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / (4 * bk)));
     int64_t c = roundup(cdiv(K, sp), bk);
     *kc = c;
@@ -128,6 +131,18 @@ static void gram_chunks(int64_t rows, int lp, int target, int32_t* rb, int32_t* 
 static int gram_groups(int lp) {
     const int nt = lp / 16;
     return (nt * (nt + 1) / 2 + 31) / 32;
+}
+
+// Blocks per pass of a single decomposition: one resident set of the sketch
+// kernel (256 CUs x 2 blocks) by default; COR_SPLIT_TARGET overrides it for
+// tuning.
+static int sketch_block_target() {
+    static int t = [] {
+        const char* e = getenv("COR_SPLIT_TARGET");
+        const int v = e ? atoi(e) : 0;
+        return v >= 16 ? v : 512;
+    }();
+    return t;
 }
 
 static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_target,
@@ -253,7 +268,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->count = count;
     P->report = opts ? opts->report : 0;
     P->reqs.assign(probs, probs + count);
-    const int sk_target = std::max(16, 2048 / count);
+    const int sk_target = std::max(16, sketch_block_target() / count);
     const int gr_target = std::max(2, 128 / count);
     size_t ws = 0;
     std::vector<size_t> base(count);
@@ -598,7 +613,7 @@ int plan_report(const Plan* P) { return P->report; }
 size_t plan_bytes(const Plan* P) { return P->mem_bytes; }
 
 size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec) {
-    Layout L = make_layout(m, n, l, prec, 2048, 128);
+    Layout L = make_layout(m, n, l, prec, sketch_block_target(), 128);
     return L.total + 256 + 1024;
 }
 
