@@ -105,10 +105,12 @@ enum {
 };
 
 // K splits of a pass: about `target` blocks in all (row blocks x splits, never
-// more), each split at least 4 K tiles long.
+// more), at most 8 splits, each split at least 4 K tiles long.  The layout of
+// a problem depends on its own shape only, never on what it is batched with,
+// so a decomposition gives bitwise the same result alone, batched or served.
 static void split_k(int64_t rows, int64_t K, int bk, int target, int32_t* s, int64_t* kc) {
     const int64_t nrb = cdiv(rows, sketch_rows_per_block());
-    int64_t sp = std::max<int64_t>(1, target / nrb);
+    int64_t sp = std::min<int64_t>(8, std::max<int64_t>(1, target / nrb));
     sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / (4 * bk)));
     int64_t c = roundup(cdiv(K, sp), bk);
     *kc = c;
@@ -268,8 +270,8 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->count = count;
     P->report = opts ? opts->report : 0;
     P->reqs.assign(probs, probs + count);
-    const int sk_target = std::max(16, sketch_block_target() / count);
-    const int gr_target = std::max(2, 128 / count);
+    const int sk_target = sketch_block_target();
+    const int gr_target = 128;
     size_t ws = 0;
     std::vector<size_t> base(count);
     for (int i = 0; i < count; i++) {

@@ -133,6 +133,7 @@ static void launch_round(Server* S, std::vector<Request*>& adm) {
     }
     cor_opts o{};
     for (Request* r : ok) o.report = std::max(o.report, r->opts.report);
+    o.cholqr2_all = ok.empty() ? 0 : ok[0]->opts.cholqr2_all;  // uniform within a round
     cor_status st = COR_OK;
     if (!ok.empty()) st = plan_create(probs.data(), (int32_t)probs.size(), &o, &R->plan, s, true);
     if (st == COR_OK && R->plan) st = plan_run(R->plan, s);
@@ -208,7 +209,14 @@ static void server_loop(Server* S) {
             }
             S->high_water = std::max(S->high_water, S->in_use);
         }
-        if (!adm.empty()) launch_round(S, adm);
+        if (!adm.empty()) {
+            // one round per orthonormalisation option (the other options do
+            // not change the results)
+            std::vector<Request*> part[2];
+            for (Request* r : adm) part[r->opts.cholqr2_all ? 1 : 0].push_back(r);
+            for (auto& v : part)
+                if (!v.empty()) launch_round(S, v);
+        }
         bool progressed = !adm.empty();
         for (size_t i = 0; i < S->active.size();) {
             Round* R = S->active[i];
