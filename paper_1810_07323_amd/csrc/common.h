@@ -101,6 +101,11 @@ template <> struct PrecT<P_F32> { typedef float T; typedef float Acc; static con
 template <> struct PrecT<P_BF16> { typedef uint16_t T; typedef float Acc; static constexpr int SZ = 2; };
 template <> struct PrecT<P_FP8> { typedef uint8_t T; typedef float Acc; static constexpr int SZ = 1; };
 
+// Global-memory view of a device pointer: loads through it are global (not
+// flat) instructions, which the compiler counts without involving LDS.
+typedef const __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ gdouble* as_global(const double* p) { return (gdouble*)p; }
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

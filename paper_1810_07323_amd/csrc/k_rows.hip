@@ -235,14 +235,20 @@ hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Gram partial sums G_b = Z_b^T Z_b of a row chunk Z_b of an FP64 rows x l
-// matrix, on FP64 MFMA 16x16x4.  A block is (row chunk, group of upper
-// 16x16 tiles); each wave holds GT_PER_WAVE tile accumulators across the
-// chunk, whose rows are staged through LDS 32 at a time.  Partials:
-// gpart[chunk][l][l], upper tiles only (every entry with a <= b is written).
+// matrix, on FP64 MFMA 16x16x4.  A block is (row chunk, group of four upper
+// 16x16 tiles); each wave owns one tile and streams the chunk's rows from
+// memory straight into MFMA operands (16 lanes read 128 contiguous bytes of
+// a row), eight K steps per batch with the next batch's loads in flight, so
+// the kernel has no LDS staging and no barrier.  Partials: gpart[chunk][l][l],
+// upper tiles only (every entry with a <= b is written).
 // ---------------------------------------------------------------------------
-constexpr int GT_PER_WAVE = 8;
-constexpr int GT_PER_BLOCK = 4 * GT_PER_WAVE;
-constexpr int GR_ROWS = 32;
+// A zero in global memory: operands outside a matrix are loaded from here (an
+// address select instead of a branch or a mask on the loaded value).  Never
+// written.
+__device__ double g_zero_word[2] = {0.0, 0.0};
+
+constexpr int GT_PER_BLOCK = GRAM_TILES_PER_BLOCK;
+static_assert(GT_PER_BLOCK == 4, "one Gram tile per wave");
 
 __device__ __forceinline__ void tile_of(int t, int nt, int& ta, int& tb) {
     // t-th upper tile (ta <= tb) in row-major order over ta.
@@ -257,7 +263,6 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
                                                       const int32_t* __restrict__ pidx,
                                                       const int32_t* __restrict__ toff, int cnt,
                                                       int side, int iter) {
-    extern __shared__ __align__(16) double zs[];  // GR_ROWS x lp
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter >= 0 && iter > P.q) return;
@@ -267,69 +272,68 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     const int ntu = nt * (nt + 1) / 2;
     const int ngroups = (ntu + GT_PER_BLOCK - 1) / GT_PER_BLOCK;
     const int chunk = local / ngroups;
-    const int grp = local % ngroups;
+    const int grp = local - chunk * ngroups;
     const int64_t rows = side == SIDE_M ? P.m : P.n;
     const int rb = side == SIDE_M ? P.rb_m : P.rb_n;
     const int64_t r0 = (int64_t)chunk * rb;
     const int64_t r1 = min(rows, r0 + rb);
-    const double* Z = SRC == GSRC_Y ? P.Y : SRC == GSRC_QA ? P.Qa : SRC == GSRC_U ? P.U : P.V;
+    const double* __restrict__ Z = SRC == GSRC_Y ? P.Y : SRC == GSRC_QA ? P.Qa : SRC == GSRC_U ? P.U : P.V;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    int ta[GT_PER_WAVE], tb[GT_PER_WAVE];
-    bool act[GT_PER_WAVE];
-    f64x4 acc[GT_PER_WAVE];
+    const int tt = grp * GT_PER_BLOCK + wave;
+    if (tt >= ntu) return;  // no barrier below: idle waves may leave
+    int ta, tb;
+    tile_of(tt, nt, ta, tb);
+    const int ca = 16 * ta + li, cb = 16 * tb + li;
+    const bool oka = ca < l, okb = cb < l;
+    // MFMA K slot g of step s is row rs + 4 s + g; U steps per batch, the next
+    // batch's loads in flight while this batch's MFMAs run.
+    constexpr int U = 8;
+    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+    double xa[U], xb[U], ya[U], yb[U];
+    // Loads are unconditional (clamped addresses, masked values): straight-line
+    // code lets the compiler wait for one batch while the next is in flight.
+    // Columns past l are read at column l - 1 (their tile entries are never
+    // written); rows past the chunk are read from a zero word.  The loads are
+    // unconditional, so straight-line code waits for one batch while the next
+    // is in flight.
+    const int cac = min(ca, l - 1), cbc = min(cb, l - 1);
+    gdouble* Zg = as_global(Z);
+    gdouble* zw = as_global(g_zero_word);
+    auto load = [&](int64_t rs, double (&va)[U], double (&vb)[U]) {
 #pragma unroll
-    for (int t = 0; t < GT_PER_WAVE; t++) {
-        const int tt = grp * GT_PER_BLOCK + wave * GT_PER_WAVE + t;
-        act[t] = tt < ntu;
-        tile_of(act[t] ? tt : 0, nt, ta[t], tb[t]);
-        acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-    }
-    for (int64_t rs = r0; rs < r1; rs += GR_ROWS) {
-        __syncthreads();
-#pragma unroll 8
-        for (int e = threadIdx.x; e < GR_ROWS * lp; e += GRAM_THREADS) {
-            const int rr = e / lp, c = e % lp;
-            const int64_t r = rs + rr;
-            zs[e] = (r < r1 && c < l) ? Z[r * l + c] : 0.0;
+        for (int u = 0; u < U; u++) {
+            const int64_t r = rs + 4 * u + lg;
+            const bool okr = r < r1;
+            gdouble* zr = Zg + r * l;
+            va[u] = *(okr ? zr + cac : zw);
+            vb[u] = *(okr ? zr + cbc : zw);
         }
-        __syncthreads();
+    };
+    // Two register buffers in turn, every prefetch unconditional (rows past
+    // the chunk read the zero word): the compiler then waits exactly for the
+    // older batch while the newer one is in flight.
+    load(r0, xa, xb);
+    for (int64_t rs = r0; rs < r1; rs += 8 * U) {
+        load(rs + 4 * U, ya, yb);
 #pragma unroll
-        for (int kk = 0; kk < GR_ROWS; kk += 4) {
-            const double* zr = zs + (kk + lg) * lp;
+        for (int u = 0; u < U; u++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], acc, 0, 0, 0);
+        load(rs + 8 * U, xa, xb);
 #pragma unroll
-            for (int t = 0; t < GT_PER_WAVE; t++) {
-                if (!act[t]) continue;
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(zr[ta[t] * 16 + li], zr[tb[t] * 16 + li],
-                                                             acc[t], 0, 0, 0);
-            }
-        }
+        for (int u = 0; u < U; u++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[u], yb[u], acc, 0, 0, 0);
     }
     double* out = P.gpart + (int64_t)chunk * l * l;
 #pragma unroll
-    for (int t = 0; t < GT_PER_WAVE; t++) {
-        if (!act[t]) continue;
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int ga = ta[t] * 16 + lg + 4 * e;  // f64 MFMA output row
-            const int gb = tb[t] * 16 + li;
-            if (ga < l && gb < l) out[(int64_t)ga * l + gb] = acc[t][e];
-        }
+    for (int e = 0; e < 4; e++) {
+        const int ga = 16 * ta + lg + 4 * e;  // f64 MFMA output row
+        if (ga < l && okb) out[(int64_t)ga * l + cb] = acc[e];
     }
 }
 
 template <int SRC>
 static hipError_t launch_gram_t(const LaunchGroup& g, int side, int iter, hipStream_t s) {
-    const size_t lds = sizeof(double) * GR_ROWS * LPMAX;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gram<SRC>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    hipLaunchKernelGGL(k_gram<SRC>, dim3(g.blocks), dim3(GRAM_THREADS), lds, s, g.probs, g.pidx,
+    hipLaunchKernelGGL(k_gram<SRC>, dim3(g.blocks), dim3(GRAM_THREADS), 0, s, g.probs, g.pidx,
                        g.toff, g.count, side, iter);
     return hipGetLastError();
 }
@@ -394,160 +398,165 @@ hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int it
 }
 
 // ---------------------------------------------------------------------------
-// dst = src S for a block of AP_ROWS rows, S l x l FP64 (R^{-1} of a
-// CholeskyQR pass).  The rows sit in LDS; S streams through LDS in panels as
-// large as the remaining LDS allows (all of S at l <= 122); each thread
-// accumulates 8 rows x NJ columns (columns cg + 64 j).  Optionally writes
-// the transposed operand copy of dst in the pass format.
-// The stage (source, destination, right factor) is a template parameter: a
-// run-time switch over these pointers was mis-compiled by the gfx950 backend
-// (the default branch kept the source of another case).
+// dst = src S for a block of AP_ROWS = 32 rows, S = R^{-1} (l x l, FP64) of a
+// CholeskyQR pass, on the FP64 MFMA (16x16x4).  Wave w owns row tile w & 1
+// and half w >> 1 of the column tiles.  Lane group g of a wave takes the K
+// slots g KQ + s (KQ = lp / 4, s < KQ): both operands stream from memory into
+// registers (S is small and stays in cache), four K steps per batch with the
+// next batch's loads in flight.  The finished 32 x l tile goes through LDS so
+// that dst (row-major) and the transposed operand copy in the pass format
+// are both written with contiguous runs.  H = column tiles per half (compile
+// time bound of the accumulator array).
+// The stage (source, destination) is a template parameter: a run-time switch
+// over these pointers was mis-compiled by the gfx950 backend (the default
+// branch kept the source of another case).
 // ---------------------------------------------------------------------------
 constexpr int AP_ROWS = 32;
-constexpr int AP_LDS_DOUBLES = 19456;  // 152 KB
 
 template <typename T>
-__device__ void write_op_rows(const Prob& P, int side, int64_t r0, int nrows, const double* xs) {
+__device__ void write_op_rows(const Prob& P, int side, int64_t r0, int nrows, const double* xs,
+                              int ldx) {
+    // op[c][r0 + rr] for c < l, rr < nrows: two columns per wave pass, lane & 31 = row
     const int l = P.l;
     T* op = reinterpret_cast<T*>(side == SIDE_M ? P.qop : P.xop);
     const int64_t ld = side == SIDE_M ? P.ldq : P.ldx;
-    for (int e = threadIdx.x; e < l * AP_ROWS; e += 256) {
-        const int c = e / AP_ROWS, rr = e % AP_ROWS;
-        if (rr < nrows) op[(int64_t)c * ld + r0 + rr] = conv_op<T>(xs[rr * l + c], 1.0f);
-    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rr = lane & 31;
+    for (int c = 2 * wave + (lane >> 5); c < l; c += 8)
+        if (rr < nrows) op[(int64_t)c * ld + r0 + rr] = conv_op<T>(xs[rr * ldx + c], 1.0f);
 }
 
-template <int MODE, int NJ>
+template <int MODE, int H>
 __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
                                                const int32_t* __restrict__ pidx,
                                                const int32_t* __restrict__ toff, int cnt,
                                                int side, int iter) {
-    extern __shared__ __align__(16) double lds[];
+    extern __shared__ __align__(16) double lds[];  // 32 x lp output tile
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter >= 0 && iter > P.q) return;
     const bool two = second_pass(P, iter);
     if (MODE == AP_QA_RINV_Q && !two) return;
-    const int l = P.l;
-    constexpr int SPW = 64 * NJ;
-    double* xs = lds;                 // AP_ROWS x l
-    double* sp = lds + AP_ROWS * l;   // PR x SPW
-    const int PR = min(l, (AP_LDS_DOUBLES - AP_ROWS * l) / SPW);
+    const int l = P.l, lp = P.lp;
+    const int nt = lp / 16;
+    const int hn = (nt + 1) / 2;  // column tiles per half
+    const int kq = lp / 4;        // K steps
     const int64_t rows = side == SIDE_M ? P.m : P.n;
     const int64_t r0 = (int64_t)local * AP_ROWS;
     const int nrows = (int)min((int64_t)AP_ROWS, rows - r0);
-    const double* src = (MODE == AP_QA_RINV_Q) ? P.Qa : P.Y;
-    const double* S = P.Rinv;
+    const double* __restrict__ src = (MODE == AP_QA_RINV_Q) ? P.Qa : P.Y;
+    const double* __restrict__ S = P.Rinv;
     // First pass: into Qa when a second pass follows, else straight into Q.
     double* const qdst = side == SIDE_M ? P.Q1 : P.Q2;
     double* const dst = (MODE == AP_Y_RINV_QA && two) ? P.Qa : qdst;
     const bool op = !(MODE == AP_Y_RINV_QA && two);
     const int tid = threadIdx.x;
-#pragma unroll 8
-    for (int e = tid; e < AP_ROWS * l; e += 256) {
-        const int rr = e / l;
-        xs[e] = rr < nrows ? src[(r0 + rr) * l + (e % l)] : 0.0;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int rt = wave & 1, half = wave >> 1;
+    const int ct0 = half * hn;
+    const int nct = min(hn, nt - ct0);  // column tiles of this wave
+    const int64_t arow = r0 + 16 * rt + li;  // row of src this lane feeds
+    const bool arow_ok = arow < rows;
+    const double* __restrict__ arp = src + min(arow, rows - 1) * l;  // clamped: loads are unconditional
+    const int kbase = lg * kq;
+
+    f64x4 acc[H];
+#pragma unroll
+    for (int t = 0; t < H; t++) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    constexpr int U = 4;
+    double a0[U], a1[U], b0[U][H], b1[U][H];
+    // Loads are unconditional (clamped addresses, masked values) and every
+    // wave runs H tiles (zero operands past its last tile): straight-line code
+    // lets the compiler wait for one batch while the next is in flight.
+    // Operands past the matrices come from clamped addresses (junk rows and
+    // columns of the tile are never written) except the K slots past l, whose
+    // A operand is read from a zero word: the loads are unconditional, so
+    // straight-line code waits for one batch while the next is in flight.
+    gdouble* ag = as_global(arp);
+    gdouble* Sg = as_global(S);
+    gdouble* zw = as_global(g_zero_word);
+    int cc[H];
+#pragma unroll
+    for (int t = 0; t < H; t++) cc[t] = min(16 * (ct0 + t) + li, l - 1);
+    auto load = [&](int s0, double (&a)[U], double (&b)[U][H]) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int k = kbase + s0 + u;  // slots past this group's kq belong to the next group
+            const int kc = min(k, l - 1);
+            a[u] = *((s0 + u < kq && k < l) ? ag + k : zw);
+            gdouble* srow = Sg + (int64_t)kc * l;
+#pragma unroll
+            for (int t = 0; t < H; t++) b[u][t] = srow[cc[t]];
+        }
+    };
+    // Two register buffers in turn, every prefetch unconditional (K slots past
+    // l or past the group's kq read the zero word): the compiler then waits
+    // exactly for the older batch while the newer one is in flight.
+    load(0, a0, b0);
+    for (int s0 = 0; s0 < kq; s0 += 2 * U) {
+        load(s0 + U, a1, b1);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int t = 0; t < H; t++)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u][t], acc[t], 0, 0, 0);
+        load(s0 + 2 * U, a0, b0);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int t = 0; t < H; t++)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u][t], acc[t], 0, 0, 0);
     }
-    const int cg = tid & 63, rg = tid >> 6;
-    double acc[8][NJ];
+    // f64 MFMA output: lane (i, g), entry e -> row g + 4e, column i of the tile.
+    double* xs = lds;  // 32 x lp
 #pragma unroll
-    for (int r = 0; r < 8; r++)
+    for (int t = 0; t < H; t++)
+        if (t < nct)
 #pragma unroll
-        for (int j = 0; j < NJ; j++) acc[r][j] = 0.0;
-    for (int a0 = 0; a0 < l; a0 += PR) {
-        const int pt = min(PR, l - a0);
-        __syncthreads();
-#pragma unroll 8
-        for (int e = tid; e < pt * SPW; e += 256) {
-            const int t = e / SPW, c = e % SPW;
-            sp[e] = c < l ? S[(int64_t)(a0 + t) * l + c] : 0.0;
-        }
-        __syncthreads();
-        int t = 0;
-        for (; t + 4 <= pt; t += 4) {  // four rows of S per batch of LDS loads
-            double sv[4][NJ], xv[4][8];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-#pragma unroll
-                for (int j = 0; j < NJ; j++) sv[u][j] = sp[(t + u) * SPW + cg + 64 * j];
-#pragma unroll
-                for (int r = 0; r < 8; r++) xv[u][r] = xs[(rg * 8 + r) * l + a0 + t + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-#pragma unroll
-                for (int r = 0; r < 8; r++)
-#pragma unroll
-                    for (int j = 0; j < NJ; j++) acc[r][j] += xv[u][r] * sv[u][j];
-        }
-        for (; t < pt; t++) {
-            double sv[NJ];
-#pragma unroll
-            for (int j = 0; j < NJ; j++) sv[j] = sp[t * SPW + cg + 64 * j];
-#pragma unroll
-            for (int r = 0; r < 8; r++) {
-                const double x = xs[(rg * 8 + r) * l + a0 + t];
-#pragma unroll
-                for (int j = 0; j < NJ; j++) acc[r][j] += x * sv[j];
-            }
-        }
-    }
+            for (int e = 0; e < 4; e++)
+                xs[(16 * rt + lg + 4 * e) * lp + 16 * (ct0 + t) + li] = acc[t][e];
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 8; r++) {
-        const int rr = rg * 8 + r;
-#pragma unroll
-        for (int j = 0; j < NJ; j++) {
-            const int c = cg + 64 * j;
-            if (c < l) xs[rr * l + c] = acc[r][j];
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < AP_ROWS * l; e += 256) {
-        const int r = e / l;
-        if (r < nrows) dst[(r0 + r) * l + (e % l)] = xs[e];
-    }
+    for (int r = wave; r < nrows; r += 4)
+        for (int c = lane; c < l; c += 64) dst[(r0 + r) * l + c] = xs[r * lp + c];
     if (op && P.prec != P_FP8) {
         switch (P.prec) {
-            case P_F64: write_op_rows<double>(P, side, r0, nrows, xs); break;
-            case P_F32: write_op_rows<float>(P, side, r0, nrows, xs); break;
-            default: write_op_rows<uint16_t>(P, side, r0, nrows, xs); break;
+            case P_F64: write_op_rows<double>(P, side, r0, nrows, xs, lp); break;
+            case P_F32: write_op_rows<float>(P, side, r0, nrows, xs, lp); break;
+            default: write_op_rows<uint16_t>(P, side, r0, nrows, xs, lp); break;
         }
     }
 }
 
-template <int MODE, int NJ>
-static hipError_t launch_apply_t(const LaunchGroup& g, int side, int iter, hipStream_t s) {
-    const size_t lds = sizeof(double) * AP_LDS_DOUBLES;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_apply<MODE, NJ>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    hipLaunchKernelGGL((k_apply<MODE, NJ>), dim3(g.blocks), dim3(256), lds, s, g.probs, g.pidx,
+template <int MODE, int H>
+static hipError_t launch_apply_t(const LaunchGroup& g, int side, int lmax, int iter,
+                                 hipStream_t s) {
+    const int lp = (lmax + 15) / 16 * 16;
+    const size_t lds = sizeof(double) * (size_t)AP_ROWS * lp;
+    hipLaunchKernelGGL((k_apply<MODE, H>), dim3(g.blocks), dim3(256), lds, s, g.probs, g.pidx,
                        g.toff, g.count, side, iter);
     return hipGetLastError();
 }
 
 template <int MODE>
-static hipError_t launch_apply_m(const LaunchGroup& g, int side, int nj, int iter, hipStream_t s) {
-    switch (nj) {
-        case 1: return launch_apply_t<MODE, 1>(g, side, iter, s);
-        case 2: return launch_apply_t<MODE, 2>(g, side, iter, s);
-        case 3: return launch_apply_t<MODE, 3>(g, side, iter, s);
-        case 4: return launch_apply_t<MODE, 4>(g, side, iter, s);
-        default: return launch_apply_t<MODE, 5>(g, side, iter, s);
-    }
+static hipError_t launch_apply_m(const LaunchGroup& g, int side, int lmax, int iter,
+                                 hipStream_t s) {
+    const int nt = (lmax + 15) / 16;
+    const int hn = (nt + 1) / 2;
+    if (hn <= 1) return launch_apply_t<MODE, 1>(g, side, lmax, iter, s);
+    if (hn <= 2) return launch_apply_t<MODE, 2>(g, side, lmax, iter, s);
+    if (hn <= 4) return launch_apply_t<MODE, 4>(g, side, lmax, iter, s);
+    if (hn <= 6) return launch_apply_t<MODE, 6>(g, side, lmax, iter, s);
+    return launch_apply_t<MODE, 9>(g, side, lmax, iter, s);
 }
 
-hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int nj, int iter, hipStream_t s) {
+hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int iter,
+                        hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
     switch (mode) {
-        case AP_Y_RINV_QA: return launch_apply_m<AP_Y_RINV_QA>(g, side, nj, iter, s);
-        case AP_QA_RINV_Q: return launch_apply_m<AP_QA_RINV_Q>(g, side, nj, iter, s);
-        case AP_Y_RINV_Q: return launch_apply_m<AP_Y_RINV_Q>(g, side, nj, iter, s);
+        case AP_Y_RINV_QA: return launch_apply_m<AP_Y_RINV_QA>(g, side, lmax, iter, s);
+        case AP_QA_RINV_Q: return launch_apply_m<AP_QA_RINV_Q>(g, side, lmax, iter, s);
+        case AP_Y_RINV_Q: return launch_apply_m<AP_Y_RINV_Q>(g, side, lmax, iter, s);
     }
     return hipErrorInvalidValue;
 }

@@ -33,12 +33,16 @@ hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s); 
 // Gram partial sums of a row-major rows x l FP64 matrix picked by `src`.
 enum GramSrc : int32_t { GSRC_Y = 0, GSRC_QA = 1, GSRC_U = 2, GSRC_V = 3 };
 constexpr int GRAM_THREADS = 256;
+// Upper 16 x 16 tiles of the l x l Gram matrix per block (one per wave); a
+// launch covers (row chunks) x ceil(tiles / GRAM_TILES_PER_BLOCK) blocks.
+constexpr int GRAM_TILES_PER_BLOCK = 4;
 hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStream_t s);
 hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int iter,
                               hipStream_t s);
-// dst = src R^{-1}, row blocks of 32; nj = ceil(l_max / 64) of the group.
+// dst = src R^{-1}, row blocks of 32; lmax = largest l of the group.
 enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2 };
-hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int nj, int iter, hipStream_t s);
+hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int iter,
+                        hipStream_t s);
 hipError_t launch_gather_v(const LaunchGroup& g, hipStream_t s);  // blocks: ceil(n*l/256)
 // Column maxima of the FP64 factor and FP8 operand scales.
 hipError_t launch_op_scales(const LaunchGroup& g, int side, int iter, hipStream_t s);

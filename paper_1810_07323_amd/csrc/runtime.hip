@@ -117,22 +117,21 @@ static void split_k(int64_t rows, int64_t K, int bk, int target, int32_t* s, int
     *s = (int32_t)cdiv(K, c);
 }
 
-static void gram_chunks(int64_t rows, int lp, int target, int32_t* rb, int32_t* gb) {
-    // Row chunks of the Gram partial sums: about `target` blocks per problem,
-    // at least 64 rows per chunk.
+static int gram_groups(int lp) {
     const int nt = lp / 16;
-    const int ntu = nt * (nt + 1) / 2;
-    const int ngroups = (ntu + 31) / 32;
+    return (nt * (nt + 1) / 2 + GRAM_TILES_PER_BLOCK - 1) / GRAM_TILES_PER_BLOCK;
+}
+
+static void gram_chunks(int64_t rows, int lp, int target, int32_t* rb, int32_t* gb) {
+    // Row chunks of the Gram partial sums: about `target` blocks per problem
+    // (chunks x tile groups), at least 64 rows per chunk.  Fewer chunks mean
+    // fewer l x l partials to write and reduce.
+    const int ngroups = gram_groups(lp);
     int64_t g = std::max<int64_t>(1, cdiv(target, ngroups));
     g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(rows, 64)));
     int64_t r = roundup(cdiv(rows, g), 4);
     *rb = (int32_t)r;
     *gb = (int32_t)cdiv(rows, r);
-}
-
-static int gram_groups(int lp) {
-    const int nt = lp / 16;
-    return (nt * (nt + 1) / 2 + 31) / 32;
 }
 
 // Blocks per pass of a single decomposition: one resident set of the sketch
@@ -271,7 +270,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->report = opts ? opts->report : 0;
     P->reqs.assign(probs, probs + count);
     const int sk_target = sketch_block_target();
-    const int gr_target = 128;
+    const int gr_target = 256;
     size_t ws = 0;
     std::vector<size_t> base(count);
     for (int i = 0; i < count; i++) {
@@ -498,11 +497,11 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_gram(P->gramM.g, SIDE_M, GSRC_Y, it, s));
         E(launch_gram_reduce(P->redM.g, SIDE_M, 0, it, s));
         E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
-        E(launch_apply(P->applyM.g, SIDE_M, AP_Y_RINV_QA, P->nj, it, s));
+        E(launch_apply(P->applyM.g, SIDE_M, AP_Y_RINV_QA, P->lmax, it, s));
         E(launch_gram(P->gramM.g, SIDE_M, GSRC_QA, it, s));
         E(launch_gram_reduce(P->redM.g, SIDE_M, 1, it, s));
         E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
-        E(launch_apply(P->applyM.g, SIDE_M, AP_QA_RINV_Q, P->nj, it, s));
+        E(launch_apply(P->applyM.g, SIDE_M, AP_QA_RINV_Q, P->lmax, it, s));
         if (fp8) {
             E(launch_op_scales(P->small.g, SIDE_M, it, s));
             E(launch_make_op(P->opM.g, SIDE_M, s));
@@ -513,12 +512,12 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_gram(P->gramN.g, SIDE_N, GSRC_Y, it, s));
         E(launch_gram_reduce(P->redN.g, SIDE_N, 0, it, s));
         E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
-        E(launch_apply(P->applyN.g, SIDE_N, AP_Y_RINV_QA, P->nj, it, s));
+        E(launch_apply(P->applyN.g, SIDE_N, AP_Y_RINV_QA, P->lmax, it, s));
         E(launch_gram(P->gramN.g, SIDE_N, GSRC_QA, it, s));
         E(launch_gram_reduce(P->redN.g, SIDE_N, 1, it, s));
         E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
         E(launch_r2(P->r2.g, it, s));
-        E(launch_apply(P->applyN.g, SIDE_N, AP_QA_RINV_Q, P->nj, it, s));
+        E(launch_apply(P->applyN.g, SIDE_N, AP_QA_RINV_Q, P->lmax, it, s));
         if (fp8 && it < P->max_q) {
             E(launch_op_scales(P->small.g, SIDE_N, it, s));
             E(launch_make_op(P->opN.g, SIDE_N, s));
@@ -615,7 +614,7 @@ int plan_report(const Plan* P) { return P->report; }
 size_t plan_bytes(const Plan* P) { return P->mem_bytes; }
 
 size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec) {
-    Layout L = make_layout(m, n, l, prec, sketch_block_target(), 128);
+    Layout L = make_layout(m, n, l, prec, sketch_block_target(), 256);
     return L.total + 256 + 1024;
 }
 
