@@ -50,6 +50,12 @@ __host__ __device__ constexpr int sk_lds_bytes() {
     return 2 * (sk_a_bytes<PREC, TRANS>() + NT * 16 * ROWB);
 }
 
+// Sixteen zero bytes in global memory: out-of-range rows of a full tile are
+// loaded from here (an address select, not a branch).  Never written.
+__device__ __align__(16) uint32_t g_zero16[4] = {0u, 0u, 0u, 0u};
+
+typedef const __attribute__((address_space(1))) i32x4 gi32x4;
+
 // 16-byte global load with element-wise bounds (zero fill) when needed.
 template <typename T, int VEC>
 __device__ __forceinline__ i32x4 load16(const T* p, int64_t valid, bool vec_ok) {
@@ -77,8 +83,6 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch(const Prob* __restrict__ 
     constexpr int VEC = SkCfg<PREC>::VEC;
     constexpr int ABYTES = sk_a_bytes<PREC, TRANS>();
     constexpr int XBYTES = NT * 16 * ROWB;
-    constexpr bool ATRANS_SCALAR = TRANS && (PREC == P_F32 || PREC == P_F64);
-    constexpr int AROWB = SK_BM * SZ + 16;  // row stride of a transposed F32/F64 tile
 
     extern __shared__ __align__(16) unsigned char smem[];
 
@@ -109,6 +113,8 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch(const Prob* __restrict__ 
     const int wave = tid >> 6;
     const int li = lane & 15;
     const int lg = lane >> 4;
+    constexpr bool ATRANS_SCALAR = TRANS && (PREC == P_F32 || PREC == P_F64);
+    constexpr int AROWB = SK_BM * SZ + 16;  // row stride of a transposed F32/F64 tile
 
     // ---------------- global -> register staging ----------------
     // A tile: non-transposed: SK_BM rows x 8 chunks;  transposed: BK rows x
@@ -120,7 +126,49 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch(const Prob* __restrict__ 
     i32x4 ra[A_LD];
     i32x4 rx[X_LD];
 
+    // Full tiles (every K of the tile inside the split, 16-byte aligned rows,
+    // and for the transposed pass every output row inside the matrix) load
+    // with unconditional 16-byte global loads; rows past the matrix read the
+    // zero block.  Straight-line loads let the compiler keep them all in
+    // flight while the previous tile's MFMAs run.  Other tiles take the
+    // element-wise path below.
+    const bool rows_full = !TRANS || row0 + SK_BM <= rows;
+    auto load_tile_full = [&](int64_t k0) {
+        gi32x4* z16 = (gi32x4*)g_zero16;
+        if constexpr (!TRANS) {
+#pragma unroll
+            for (int t = 0; t < A_LD; t++) {
+                const int c = tid + t * SK_THREADS;
+                const int r = c >> 3, ch = c & 7;
+                const int64_t gr = row0 + r;
+                const T* a = A + min(gr, rows - 1) * lda + k0 + ch * VEC;
+                ra[t] = *(gr < rows ? (gi32x4*)a : z16);
+            }
+        } else {
+            constexpr int CPR = SK_BM * SZ / 16;  // chunks per A row segment
+#pragma unroll
+            for (int t = 0; t < A_LD; t++) {
+                const int c = tid + t * SK_THREADS;
+                const int kr = c / CPR, ch = c % CPR;
+                const T* a = A + (k0 + kr) * lda + row0 + ch * VEC;
+                ra[t] = *(gi32x4*)a;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < X_LD; t++) {
+            // chunks past X_CHUNKS repeat the last one (their LDS store is skipped)
+            const int c = min(tid + t * SK_THREADS, X_CHUNKS - 1);
+            const int r = c >> 3, ch = c & 7;
+            // X is [lp][ldx] with zeros past the factor: every K < ldx is readable.
+            const T* x = X + (int64_t)min(r, lp - 1) * ldx + k0 + ch * VEC;
+            rx[t] = *(gi32x4*)x;
+        }
+    };
     auto load_tile = [&](int64_t k0) {
+        if (avec && rows_full && k0 + BK <= kend) {
+            load_tile_full(k0);
+            return;
+        }
         if constexpr (!TRANS) {
 #pragma unroll
             for (int t = 0; t < A_LD; t++) {
@@ -232,6 +280,8 @@ __global__ __launch_bounds__(SK_THREADS) void k_sketch(const Prob* __restrict__ 
 #pragma unroll
                         for (int e = 0; e < VEC; e++) av[r][e] = u.e[e];
                     } else {
+                        // F32/F64 tiles stay [K][row] in LDS (a transposing
+                        // store of 4-byte elements costs more than these reads)
 #pragma unroll
                         for (int e = 0; e < VEC; e++)
                             av[r][e] = *reinterpret_cast<const T*>(As + (kk + e) * AROWB + orow * SZ);

@@ -201,33 +201,32 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol(const Prob* __restrict__ 
 // ---------------------------------------------------------------------------
 // Cholesky and inverse in one register-resident sweep (l <= 128).
 //
-// Symmetric Gaussian elimination on [G | I]: at column j every row a > j
-// subtracts (v_a / d_j) times row j, where v = row j of the current Schur
-// complement and d_j = v_j.  The upper triangle of the l x l work matrix
-// holds the Schur complement, the strict lower triangle accumulates
-// E = L^{-1} (G = L D L^T, L unit lower).  Then
-//   R    = D^{1/2} L^T   : R[j][b]    = v_b / sqrt(d_j)          (b >= j)
-//   R^-1 = L^{-T} D^-1/2 : R^-1[b][j] = E[j][b] / sqrt(d_j)      (b <  j)
-//
-// Each thread keeps one 4 x 4 tile in registers (ceil(l/4)^2 threads).  The
-// owners of row j publish it in LDS (double-buffered) as three vectors, so
-// that the column step needs no per-element selects:
-//   fa[a] = v_a for a > j, else 0          (row multipliers, times 1/d_j)
-//   rU[b] = v_b                            (Schur part, read by b >= a)
-//   rL[b] = E[j][b] for b < j, 1 at b = j, 0 after   (E part, read by b < a)
-// and the owner of the diagonal tile publishes 1/d_j.  The column loop is
-// unrolled by four, so the published row's place inside its tile is a
-// compile-time index.  Dependent FP64 operations are slow (tens of cycles
-// each), so the only arithmetic on the serial path of a column is one
-// update, the reciprocal of the next pivot (hardware estimate refined by two
-// Newton steps) and the LDS exchange; square roots for R and R^{-1} are
-// taken after the loop.  Tiles are numbered strictly-upper (row-major),
-// diagonal, strictly-lower (column-major), so a wave holds one kind of tile
-// (but for the two waves at the seams), and the waves whose rows are done,
-// or whose E columns have not started, skip the step as a whole.  A pivot
-// d_j <= l 2^-52 max_i G_ii is clamped to that threshold (numerically
-// rank-deficient sketch) and flagged.  mode FIRST also stores R in Racc (for
-// R2 = R' R).
+// Symmetric Gaussian elimination on [G | I], four columns at a time.  The
+// upper triangle of the l x l work matrix holds the Schur complement, the
+// strict lower triangle accumulates E = L^{-1} (G = L D L^T, L unit lower);
+// row j is final once its column has been eliminated and then holds
+// v_j = (row j of the Schur complement at step j), so that
+//   R    = D^{1/2} L^T   : R[j][b]    = v_j[b] / sqrt(d_j)          (b >= j)
+//   R^-1 = L^{-T} D^-1/2 : R^-1[b][j] = E[j][b] / sqrt(d_j)         (b <  j)
+// Each thread keeps one 4 x 4 tile in registers (ceil(l/4)^2 threads).  For
+// the block P of columns 4kb .. 4kb + 3:
+//   A. the owner of the diagonal tile factors it, B = L1 D1 L1^T, in
+//      registers (its upper part becomes the rows v_j, its lower part
+//      L1^{-1}) and publishes L1, 1/D1 and the E rows of P inside the block;
+//   B. the other owners of block row P apply L1^{-1} to their tile (the
+//      four pivot rows, Schur or E part, now final) and publish them;
+//   C. every tile below the block subtracts the rank-4 product
+//      sum_k (v_k[a] / d_k) w_k[b], with w = v (Schur part, b >= a) or the
+//      E rows (b < a).
+// Two barriers per four columns; dependent FP64 operations are slow (tens of
+// cycles each), so the serial path is the in-register factor of a 4 x 4
+// block, one triangular solve and one exchange.  Tiles are numbered
+// strictly-upper (row-major), diagonal, strictly-lower (column-major), so a
+// wave holds one kind of tile (but for the two waves at the seams) and waves
+// whose rows are done, or whose E columns have not started, skip the update.
+// A pivot d_j <= l 2^-52 max_i G_ii is clamped to that threshold
+// (numerically rank-deficient sketch) and flagged.  mode FIRST also stores R
+// in Racc (for R2 = R' R).
 // ---------------------------------------------------------------------------
 constexpr int CRT_THREADS = 1024;
 constexpr int CRT_LMAX = 128;
@@ -240,90 +239,24 @@ __device__ __forceinline__ double recip_nr(double d) {
     return y;
 }
 
-// Publication of row jr by the owners of its tile row (local row R inside
-// the tile): this thread's four entries (columns b0..b0+3) into the three
-// row vectors; the owner of the diagonal tile also publishes d and 1/d.
-template <int R>
-__device__ __forceinline__ void chol_publish(const double (&x)[4][4], int jr, int b0, bool diag,
-                                             double tol, double* fa, double* ru, double* rl,
-                                             double* s_d, double* s_inv, int slot,
-                                             int* clamped) {
-    double f[4], lv[4];
-#pragma unroll
-    for (int c = 0; c < 4; c++) {
-        const int b = b0 + c;
-        f[c] = b > jr ? x[R][c] : 0.0;
-        lv[c] = b < jr ? x[R][c] : (b == jr ? 1.0 : 0.0);
-    }
-    if (diag) {
-        double d = x[R][R];
-        if (!(d > tol)) {
-            d = tol;
-            *clamped = 1;
-        }
-        s_inv[slot] = recip_nr(d);
-        s_d[jr] = d;
-    }
-    *reinterpret_cast<double2*>(&fa[b0]) = make_double2(f[0], f[1]);
-    *reinterpret_cast<double2*>(&fa[b0 + 2]) = make_double2(f[2], f[3]);
-    *reinterpret_cast<double2*>(&ru[b0]) = make_double2(x[R][0], x[R][1]);
-    *reinterpret_cast<double2*>(&ru[b0 + 2]) = make_double2(x[R][2], x[R][3]);
-    *reinterpret_cast<double2*>(&rl[b0]) = make_double2(lv[0], lv[1]);
-    *reinterpret_cast<double2*>(&rl[b0 + 2]) = make_double2(lv[2], lv[3]);
+__device__ __forceinline__ void st2(double* p, double a, double b) {
+    *reinterpret_cast<double2*>(p) = make_double2(a, b);
 }
-
-// One column step j: eliminate column j (published in slot sl) from this
-// thread's tile.
-__device__ __forceinline__ void chol_step(double (&x)[4][4], int j, int kind, int a0, int b0,
-                                          const double* fa_s, const double* ru_s,
-                                          const double* rl_s, double inv_d) {
-    if (!(a0 + 3 > j) || (kind == 2 && b0 > j)) return;
-    const double2 f01 = *reinterpret_cast<const double2*>(&fa_s[a0]);
-    const double2 f23 = *reinterpret_cast<const double2*>(&fa_s[a0 + 2]);
-    const double fa[4] = {f01.x * inv_d, f01.y * inv_d, f23.x * inv_d, f23.y * inv_d};
-    if (kind == 0) {
-        const double2 u01 = *reinterpret_cast<const double2*>(&ru_s[b0]);
-        const double2 u23 = *reinterpret_cast<const double2*>(&ru_s[b0 + 2]);
-        const double cb[4] = {u01.x, u01.y, u23.x, u23.y};
-#pragma unroll
-        for (int r = 0; r < 4; r++)
-#pragma unroll
-            for (int c = 0; c < 4; c++) x[r][c] = fma(-fa[r], cb[c], x[r][c]);
-    } else if (kind == 2) {
-        const double2 l01 = *reinterpret_cast<const double2*>(&rl_s[b0]);
-        const double2 l23 = *reinterpret_cast<const double2*>(&rl_s[b0 + 2]);
-        const double cb[4] = {l01.x, l01.y, l23.x, l23.y};
-#pragma unroll
-        for (int r = 0; r < 4; r++)
-#pragma unroll
-            for (int c = 0; c < 4; c++) x[r][c] = fma(-fa[r], cb[c], x[r][c]);
-    } else {
-        const double2 u01 = *reinterpret_cast<const double2*>(&ru_s[b0]);
-        const double2 u23 = *reinterpret_cast<const double2*>(&ru_s[b0 + 2]);
-        const double2 l01 = *reinterpret_cast<const double2*>(&rl_s[b0]);
-        const double2 l23 = *reinterpret_cast<const double2*>(&rl_s[b0 + 2]);
-        const double cu[4] = {u01.x, u01.y, u23.x, u23.y};
-        const double cl[4] = {l01.x, l01.y, l23.x, l23.y};
-        // the diagonal element first: it feeds the next pivot
-#pragma unroll
-        for (int r = 0; r < 4; r++) x[r][r] = fma(-fa[r], cu[r], x[r][r]);
-#pragma unroll
-        for (int r = 0; r < 4; r++)
-#pragma unroll
-            for (int c = 0; c < 4; c++)
-                if (c != r) x[r][c] = fma(-fa[r], c > r ? cu[c] : cl[c], x[r][c]);
-    }
+__device__ __forceinline__ void ld4(const double* p, double (&v)[4]) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 
 __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict__ probs,
                                                         const int32_t* __restrict__ pidx,
                                                         const int32_t* __restrict__ toff, int cnt,
                                                         int mode, int iter) {
-    __shared__ __align__(16) double s_fa[2][CRT_LMAX];
-    __shared__ __align__(16) double s_ru[2][CRT_LMAX];
-    __shared__ __align__(16) double s_rl[2][CRT_LMAX];
-    __shared__ double s_inv[2];
-    __shared__ double s_d[CRT_LMAX];  // pivots d_j
+    __shared__ __align__(16) double s_ru[2][4][CRT_LMAX];  // v rows of the block (Schur part)
+    __shared__ __align__(16) double s_rl[2][4][CRT_LMAX];  // E rows of the block
+    __shared__ double s_lm[2][8];                           // L1 below its diagonal
+    __shared__ __align__(16) double s_inv[2][4];            // 1 / d of the block
+    __shared__ double s_d[CRT_LMAX];                        // pivots d_j
     __shared__ double s_tol;
     __shared__ int s_clamped;
     int local;
@@ -337,7 +270,7 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
     const int nup = nt4 * (nt4 - 1) / 2;  // strictly upper tiles
     const bool own = tid < nt4 * nt4;
     // tile of this thread: kind 0 strictly upper, 1 diagonal, 2 strictly lower
-    int ta = 0, tb = 0, kind = 1;
+    int ta = -1, tb = -1, kind = 1;
     if (own) {
         if (tid < nup) {  // row-major over ta < tb
             int r = 0, rem = tid;
@@ -350,19 +283,11 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
             while (rem >= nt4 - 1 - c) { rem -= nt4 - 1 - c; c++; }
             tb = c; ta = c + 1 + rem; kind = 2;
         }
-    } else {
-        ta = tb = -1;  // no tile: never active, never publishes
     }
     const int a0 = 4 * ta, b0 = 4 * tb;
-    const bool diag = own && kind == 1;
     const double* __restrict__ G = P.G;
     const bool first = mode == CHOL_FIRST;
 
-    for (int e = tid; e < 2 * CRT_LMAX; e += blockDim.x) {
-        (&s_fa[0][0])[e] = 0.0;
-        (&s_ru[0][0])[e] = 0.0;
-        (&s_rl[0][0])[e] = 0.0;
-    }
     double x[4][4];
 #pragma unroll
     for (int r = 0; r < 4; r++)
@@ -384,45 +309,143 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
     }
     __syncthreads();
     const double tol = s_tol;
-    if (own && ta == 0)
-        chol_publish<0>(x, 0, b0, diag, tol, s_fa[0], s_ru[0], s_rl[0], s_d, s_inv, 0, &s_clamped);
-    __syncthreads();
 
-    // The loop touches only registers and LDS: a barrier then never waits for
-    // global memory.  Rows are final once their step has passed, so R and
-    // R^{-1} are written from the registers after the loop.  Column j = 4 jb + jj.
-    for (int jb = 0; 4 * jb < l; jb++) {
+    // The loop touches only registers and LDS: a barrier never waits for
+    // global memory.  R and R^{-1} are written from the registers at the end.
+    for (int kb = 0; kb < nt4; kb++) {
+        const int pb = kb & 1;
+        // A. factor the diagonal block in registers
+        if (own && kind == 1 && ta == kb) {
+            double inv[4], L[4][4];
 #pragma unroll
-        for (int jj = 0; jj < 4; jj++) {
-            const int j = 4 * jb + jj;
-            if (j < l) {
-                const int sl = jj & 1;
-                chol_step(x, j, kind, a0, b0, s_fa[sl], s_ru[sl], s_rl[sl], s_inv[sl]);
-                // publish row j + 1: local row jj + 1 of tile row jb, or row 0 of tile row jb + 1
-                if (j + 1 < l) {
-                    if (jj < 3) {
-                        if (ta == jb) {
-                            if (jj == 0)
-                                chol_publish<1>(x, j + 1, b0, diag, tol, s_fa[sl ^ 1], s_ru[sl ^ 1],
-                                                s_rl[sl ^ 1], s_d, s_inv, sl ^ 1, &s_clamped);
-                            else if (jj == 1)
-                                chol_publish<2>(x, j + 1, b0, diag, tol, s_fa[sl ^ 1], s_ru[sl ^ 1],
-                                                s_rl[sl ^ 1], s_d, s_inv, sl ^ 1, &s_clamped);
-                            else
-                                chol_publish<3>(x, j + 1, b0, diag, tol, s_fa[sl ^ 1], s_ru[sl ^ 1],
-                                                s_rl[sl ^ 1], s_d, s_inv, sl ^ 1, &s_clamped);
-                        }
-                    } else if (ta == jb + 1) {
-                        chol_publish<0>(x, j + 1, b0, diag, tol, s_fa[sl ^ 1], s_ru[sl ^ 1],
-                                        s_rl[sl ^ 1], s_d, s_inv, sl ^ 1, &s_clamped);
-                    }
+            for (int k = 0; k < 4; k++) {
+                double d = x[k][k];
+                if (4 * kb + k >= l) {
+                    d = 1.0;  // padding rows: a unit pivot, nothing to eliminate
+                } else if (!(d > tol)) {
+                    d = tol;
+                    s_clamped = 1;
                 }
-                __syncthreads();
+                inv[k] = recip_nr(d);
+                s_d[4 * kb + k] = d;
+#pragma unroll
+                for (int r = k + 1; r < 4; r++) {
+                    const double m = x[k][r] * inv[k];
+                    L[r][k] = m;
+#pragma unroll
+                    for (int c = r; c < 4; c++) x[r][c] = fma(-m, x[k][c], x[r][c]);
+                }
+            }
+            // L1^{-1} (unit lower) into the lower part of the tile
+            double Li[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < i; j++) {
+                    double t = -L[i][j];
+#pragma unroll
+                    for (int k = j + 1; k < i; k++) t = fma(-L[i][k], Li[k][j], t);
+                    Li[i][j] = t;
+                }
+#pragma unroll
+            for (int i = 1; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < i; j++) x[i][j] = Li[i][j];
+            s_lm[pb][0] = L[1][0];
+            s_lm[pb][1] = L[2][0];
+            s_lm[pb][2] = L[2][1];
+            s_lm[pb][3] = L[3][0];
+            s_lm[pb][4] = L[3][1];
+            s_lm[pb][5] = L[3][2];
+            st2(&s_inv[pb][0], inv[0], inv[1]);
+            st2(&s_inv[pb][2], inv[2], inv[3]);
+            // E rows of P inside the block: L1^{-1} with its unit diagonal
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                double e[4];
+#pragma unroll
+                for (int c = 0; c < 4; c++) e[c] = c < k ? Li[k][c] : (c == k ? 1.0 : 0.0);
+                st2(&s_rl[pb][k][b0], e[0], e[1]);
+                st2(&s_rl[pb][k][b0 + 2], e[2], e[3]);
+            }
+        }
+        __syncthreads();
+        // B. the rest of block row P: rows of L1^{-1} X, final
+        if (own && kind != 1 && ta == kb) {
+            const double l10 = s_lm[pb][0], l20 = s_lm[pb][1], l21 = s_lm[pb][2];
+            const double l30 = s_lm[pb][3], l31 = s_lm[pb][4], l32 = s_lm[pb][5];
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                x[1][c] = fma(-l10, x[0][c], x[1][c]);
+                x[2][c] = fma(-l21, x[1][c], fma(-l20, x[0][c], x[2][c]));
+                x[3][c] = fma(-l32, x[2][c], fma(-l31, x[1][c], fma(-l30, x[0][c], x[3][c])));
+            }
+            if (kind == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    st2(&s_ru[pb][k][b0], x[k][0], x[k][1]);
+                    st2(&s_ru[pb][k][b0 + 2], x[k][2], x[k][3]);
+                    st2(&s_rl[pb][k][b0], 0.0, 0.0);  // no E entries past the block
+                    st2(&s_rl[pb][k][b0 + 2], 0.0, 0.0);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    st2(&s_rl[pb][k][b0], x[k][0], x[k][1]);
+                    st2(&s_rl[pb][k][b0 + 2], x[k][2], x[k][3]);
+                }
+            }
+        }
+        __syncthreads();
+        // C. rank-4 update of the tiles below the block
+        if (own && ta > kb && (kind != 2 || tb <= kb)) {
+            double inv[4], fa[4][4];
+            ld4(&s_inv[pb][0], inv);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                double v[4];
+                ld4(&s_ru[pb][k][a0], v);
+#pragma unroll
+                for (int r = 0; r < 4; r++) fa[k][r] = v[r] * inv[k];
+            }
+            if (kind == 0) {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    double cb[4];
+                    ld4(&s_ru[pb][k][b0], cb);
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+#pragma unroll
+                        for (int c = 0; c < 4; c++) x[r][c] = fma(-fa[k][r], cb[c], x[r][c]);
+                }
+            } else if (kind == 2) {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    double cb[4];
+                    ld4(&s_rl[pb][k][b0], cb);
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+#pragma unroll
+                        for (int c = 0; c < 4; c++) x[r][c] = fma(-fa[k][r], cb[c], x[r][c]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    double cu[4], cl[4];
+                    ld4(&s_ru[pb][k][b0], cu);
+                    ld4(&s_rl[pb][k][b0], cl);
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+#pragma unroll
+                        for (int c = 0; c < 4; c++)
+                            x[r][c] = fma(-fa[k][r], c >= r ? cu[c] : cl[c], x[r][c]);
+                }
             }
         }
     }
+    __syncthreads();
     if (tid == 0 && s_clamped) atomicOr(P.flags, FLAG_RANK_DEF);
-    // R[a][b] = v_b / sqrt(d_a) (b > a), sqrt(d_a) (b = a), 0 below;
+    // R[a][b] = v_a[b] / sqrt(d_a) (b > a), sqrt(d_a) (b = a), 0 below;
     // R^{-1}[b][a] = E[a][b] / sqrt(d_a) (b < a), 1/sqrt(d_a) (b = a), 0 above.
     if (own) {
         double* __restrict__ Rout = P.R;
