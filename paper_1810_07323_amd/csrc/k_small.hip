@@ -767,12 +767,19 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const double alpha = arc[(j & 3) * ST + (j >> 2)];
             const double ss = s_nrm[p];  // sum over rows >= j of column p squared
-            const double xnorm = sqrt(ss);
             double tau = 0.0, beta = alpha, scale = 1.0;
-            if (xnorm != 0.0) {
-                beta = alpha >= 0.0 ? -xnorm : xnorm;
-                scale = 1.0 / (alpha - beta);
-                tau = (beta - alpha) / beta;
+            if (ss > 0.0) {
+                // ||x|| = ss y with y = 1/sqrt(ss) (estimate + two Newton
+                // steps); 1/beta = -+y, so tau needs no division.
+                const double h = 0.5 * ss;
+                double y = __builtin_amdgcn_rsq(ss);
+#pragma unroll
+                for (int it = 0; it < 2; it++) y = fma(y, fma(-h * y, y, 0.5), y);
+                const double xnorm = ss * y;
+                const double sg = alpha >= 0.0 ? -1.0 : 1.0;
+                beta = sg * xnorm;
+                scale = recip_nr(alpha - beta);
+                tau = (beta - alpha) * (sg * y);
             }
             if (t == 0) {
                 s_tau[j] = tau;
@@ -787,8 +794,11 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
         if (active) {
             const double tau = s_tau[j], scale = s_scale[j];
             const double* arct = arc + t * ST;
-            double raw[RPT];
-            double dm = 0.0, du = 0.0;  // masked block / blocks below row j
+            // v_i = scale raw_i below row j, 1 at row j, 0 above.  Eight
+            // partial sums per lane keep the dependent FP64 chains short.
+            double vv[RPT], d8[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) d8[e] = 0.0;
 #pragma unroll
             for (int q = 0; q < NCH; q++) {
                 const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
@@ -796,24 +806,24 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
 #pragma unroll
                 for (int u = q * CH; u < q * CH + CH; u += 2) {
                     const double2 r2 = *reinterpret_cast<const double2*>(arct + u);
-                    raw[u] = r2.x;
-                    raw[u + 1] = r2.y;
+                    vv[u] = r2.x * scale;
+                    vv[u + 1] = r2.y * scale;
                 }
-                if (lo > j) {
-#pragma unroll
-                    for (int u = q * CH; u < q * CH + CH; u++) du = fma(raw[u], col[u], du);
-                } else {
+                if (lo <= j) {
 #pragma unroll
                     for (int u = q * CH; u < q * CH + CH; u++) {
                         const int i = 4 * u + t;
-                        const double vv = i > j ? raw[u] * scale : (i == j ? 1.0 : 0.0);
-                        dm = fma(vv, col[u], dm);
+                        vv[u] = i > j ? vv[u] : (i == j ? 1.0 : 0.0);
                     }
                 }
+#pragma unroll
+                for (int u = q * CH; u < q * CH + CH; u++) d8[u & 7] = fma(vv[u], col[u], d8[u & 7]);
             }
-            const double w = tau * quad_sum(fma(scale, du, dm));
-            const double ws = w * scale;
-            double n0 = 0.0, n1 = 0.0;
+            const double dsum = ((d8[0] + d8[1]) + (d8[2] + d8[3])) + ((d8[4] + d8[5]) + (d8[6] + d8[7]));
+            const double w = tau * quad_sum(dsum);
+            double n8[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) n8[e] = 0.0;
 #pragma unroll
             for (int q = 0; q < NCH; q++) {
                 const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
@@ -821,20 +831,20 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
                 if (lo > j) {
 #pragma unroll
                     for (int u = q * CH; u < q * CH + CH; u++) {
-                        col[u] = fma(-ws, raw[u], col[u]);
-                        if (u & 1) n1 = fma(col[u], col[u], n1);
-                        else n0 = fma(col[u], col[u], n0);
+                        col[u] = fma(-w, vv[u], col[u]);
+                        n8[u & 7] = fma(col[u], col[u], n8[u & 7]);
                     }
                 } else {
 #pragma unroll
                     for (int u = q * CH; u < q * CH + CH; u++) {
                         const int i = 4 * u + t;
-                        const double vv = i > j ? raw[u] * scale : (i == j ? 1.0 : 0.0);
-                        col[u] = fma(-w, vv, col[u]);
-                        if (i > j) n0 = fma(col[u], col[u], n0);
+                        col[u] = fma(-w, vv[u], col[u]);
+                        if (i > j) n8[u & 7] = fma(col[u], col[u], n8[u & 7]);
                     }
                 }
             }
+            const double n0 = (n8[0] + n8[1]) + (n8[2] + n8[3]);
+            const double n1 = (n8[4] + n8[5]) + (n8[6] + n8[7]);
             const double n = quad_sum(n0 + n1);
             if (t == 0) {
                 s_nrm[c] = n;
