@@ -13,7 +13,6 @@
 
 namespace cor {
 
-constexpr int CHOL_LDS_MAX = 128;  // l*l + 16*l doubles + scratch fit in 160 KB of LDS
 constexpr int QRCP_LDS_MAX = 136;  // l*l doubles + scratch
 constexpr int QRT_LMAX = 128;      // register-resident QRCP: 4 lanes per column
 constexpr int QRT_THREADS = 4 * QRT_LMAX;
@@ -24,179 +23,6 @@ __device__ __forceinline__ const Prob& group_prob2(const Prob* probs, const int3
     local = blockIdx.x - toff[j];
     return probs[pidx[j]];
 }
-
-// ---------------------------------------------------------------------------
-// Cholesky G = R^T R and R^{-1} (one block of 256 threads per problem).
-//   Factorisation: right-looking, one barrier per column.  The thread that
-//   updates the next diagonal entry also derives that pivot's scalars
-//   (d, 1/d, sqrt d, 1/sqrt d) into a double-buffered LDS slot, so no other
-//   thread computes a division or a square root.  Row j is scaled one step
-//   later, so no thread reads a row while it is being rescaled.  A pivot
-//   d_j <= l 2^-52 max_i G_ii is clamped to that threshold (numerically
-//   rank-deficient sketch) and flagged.
-//   Inverse: 16 x 16 blocks.  Each wave inverts diagonal blocks by back
-//   substitution (lane = column, so a lane only reads values it wrote); the
-//   off-diagonal blocks follow block row by block row from the bottom:
-//   X_ij = -X_ii sum_{i<k<=j} R_ik X_kj.  The strict upper part of R^{-1} is
-//   kept transposed in the free lower triangle of the work array.
-// Outputs: R, Rinv; mode FIRST also keeps R in Racc (for R2 = R' R).
-// ---------------------------------------------------------------------------
-constexpr int CHOL_THREADS = 256;
-
-__device__ __forceinline__ void chol_pivot(double d, double tol, double* sc, int* clamped) {
-    if (!(d > tol)) {
-        d = tol;
-        *clamped = 1;
-    }
-    const double sq = sqrt(d);
-    sc[0] = d;
-    sc[1] = 1.0 / d;
-    sc[2] = sq;
-    sc[3] = 1.0 / sq;
-}
-
-// IN_LDS selects where the l x l work array lives; a pointer that may point
-// to either LDS or global memory would force flat (global-latency) accesses.
-template <bool IN_LDS>
-__global__ __launch_bounds__(CHOL_THREADS) void k_chol(const Prob* __restrict__ probs,
-                                                       const int32_t* __restrict__ pidx,
-                                                       const int32_t* __restrict__ toff, int cnt,
-                                                       int mode, int iter) {
-    extern __shared__ __align__(16) double sm[];
-    __shared__ double s_tol;
-    __shared__ double s_sc[2][4];
-    __shared__ double s_dinv[LMAX];
-    __shared__ int s_clamped;
-    int local;
-    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
-    if (iter >= 0 && iter > P.q) return;
-    if (mode == CHOL_SECOND && !second_pass(P, iter)) return;
-    const int l = P.l;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NW = CHOL_THREADS / 64;
-    constexpr bool in_lds = IN_LDS;
-    if (IN_LDS != (l <= CHOL_LDS_MAX)) return;
-    double* W;
-    double* Tm;  // (nb - 1) * 256 <= 16 l doubles
-    if constexpr (IN_LDS) { W = sm; Tm = sm + l * l; }
-    else { W = P.R; Tm = P.G; }
-    const int nb = (l + 15) / 16;
-
-#pragma unroll 8
-    for (int e = tid; e < l * l; e += CHOL_THREADS) W[e] = P.G[e];
-    if (tid < 64) {
-        double mx = 0.0;
-        for (int i = tid; i < l; i += 64) mx = fmax(mx, fabs(P.G[i * l + i]));
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if (tid == 0) {
-            const double t = (double)l * 0x1.0p-52 * mx;
-            s_tol = t > 0.0 ? t : 0x1.0p-1000;
-            s_clamped = 0;
-        }
-    }
-    __syncthreads();
-    const double tol = s_tol;
-    if (tid == 0) chol_pivot(W[0], tol, s_sc[0], &s_clamped);
-    __syncthreads();
-
-    double psq = 1.0, pisq = 1.0;  // scalars of the previous pivot
-    for (int j = 0; j < l; j++) {
-        const double inv_d = s_sc[j & 1][1];
-        const double csq = s_sc[j & 1][2], cisq = s_sc[j & 1][3];
-        if (j > 0)
-            for (int c = j - 1 + tid; c < l; c += CHOL_THREADS)
-                W[(j - 1) * l + c] = (c == j - 1) ? psq : W[(j - 1) * l + c] * pisq;
-        const double* wj = W + j * l;
-        for (int a = j + 1 + wave; a < l; a += NW) {
-            const double f = wj[a] * inv_d;
-            double* wa = W + a * l;
-            for (int b = a + lane; b < l; b += 64) wa[b] -= f * wj[b];
-        }
-        // thread 0 updated W[j+1][j+1] (wave 0 takes row j+1, lane 0 column j+1)
-        if (tid == 0 && j + 1 < l) chol_pivot(W[(j + 1) * l + j + 1], tol, s_sc[(j + 1) & 1], &s_clamped);
-        psq = csq;
-        pisq = cisq;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        W[(l - 1) * l + (l - 1)] = psq;
-        if (s_clamped) atomicOr(P.flags, FLAG_RANK_DEF);
-    }
-    __syncthreads();
-    for (int e = tid; e < l * l; e += CHOL_THREADS) {
-        const int a = e / l, b = e % l;
-        if (b < a) W[e] = 0.0;
-    }
-    __syncthreads();
-
-    // ---- inverse: X = R^{-1}; X[i][c] (i < c) stored at W[c][i], diag in s_dinv
-    for (int ib = wave; ib < nb; ib += NW) {
-        const int o = 16 * ib, bs = min(16, l - o);
-        const int c = lane;
-        for (int i = bs - 1; i >= 0; i--) {
-            if (c < bs && c >= i) {
-                const double rii = W[(o + i) * l + o + i];
-                if (c == i) {
-                    s_dinv[o + i] = 1.0 / rii;
-                } else {
-                    double sacc = 0.0;
-                    for (int t = i + 1; t <= c; t++) {
-                        const double xt = (t == c) ? s_dinv[o + c] : W[(o + c) * l + o + t];
-                        sacc += W[(o + i) * l + o + t] * xt;
-                    }
-                    W[(o + c) * l + o + i] = -sacc / rii;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    for (int ib = nb - 2; ib >= 0; ib--) {
-        const int o = 16 * ib;
-        const int nblk = nb - 1 - ib;
-        for (int e = tid; e < nblk * 256; e += CHOL_THREADS) {
-            const int jb = ib + 1 + e / 256, r = (e % 256) / 16, cc = e % 16;
-            const int col = 16 * jb + cc, row = o + r;
-            double s0 = 0.0, s1 = 0.0;
-            if (col < l && row < l) {
-                int t = 16 * (ib + 1);
-                for (; t + 1 < col; t += 2) {
-                    s0 += W[row * l + t] * W[col * l + t];
-                    s1 += W[row * l + t + 1] * W[col * l + t + 1];
-                }
-                for (; t < col; t++) s0 += W[row * l + t] * W[col * l + t];
-                s0 += W[row * l + col] * s_dinv[col];
-            }
-            Tm[e] = s0 + s1;
-        }
-        __syncthreads();
-        const int bs = min(16, l - o);
-        for (int e = tid; e < nblk * 256; e += CHOL_THREADS) {
-            const int jb = ib + 1 + e / 256, r = (e % 256) / 16, cc = e % 16;
-            const int col = 16 * jb + cc, row = o + r;
-            if (col >= l || r >= bs) continue;
-            double sacc = s_dinv[row] * Tm[(e / 256) * 256 + r * 16 + cc];
-            for (int t = r + 1; t < bs; t++) sacc += W[(o + t) * l + row] * Tm[(e / 256) * 256 + t * 16 + cc];
-            W[col * l + row] = -sacc;
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < l * l; e += CHOL_THREADS) {
-        const int a = e / l, b = e % l;
-        const double r = b >= a ? W[e] : 0.0;
-        P.Rinv[e] = b > a ? W[b * l + a] : (b == a ? s_dinv[a] : 0.0);
-        if (in_lds) P.R[e] = r;
-        if (mode == CHOL_FIRST) P.Racc[e] = r;
-    }
-    if (!in_lds) {
-        __syncthreads();
-        for (int e = tid; e < l * l; e += CHOL_THREADS) {
-            const int a = e / l, b = e % l;
-            if (b < a) W[e] = 0.0;
-        }
-    }
-}
-
 
 // ---------------------------------------------------------------------------
 // Cholesky and inverse in one register-resident sweep (l <= 128).
@@ -248,23 +74,18 @@ __device__ __forceinline__ void ld4(const double* p, double (&v)[4]) {
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 
-__global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict__ probs,
-                                                        const int32_t* __restrict__ pidx,
-                                                        const int32_t* __restrict__ toff, int cnt,
-                                                        int mode, int iter) {
+// Factor the n x n block (n <= 128) whose upper triangle is Gs (leading
+// dimension ld): R and R^{-1} of the block into R and Rinv (same leading
+// dimension), pivots clamped at tol.  Every thread of the block calls it.
+__device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n, double* __restrict__ Rout,
+                           double* __restrict__ Rinv, int ld, double tol, int* clamped) {
     __shared__ __align__(16) double s_ru[2][4][CRT_LMAX];  // v rows of the block (Schur part)
     __shared__ __align__(16) double s_rl[2][4][CRT_LMAX];  // E rows of the block
     __shared__ double s_lm[2][8];                           // L1 below its diagonal
     __shared__ __align__(16) double s_inv[2][4];            // 1 / d of the block
     __shared__ double s_d[CRT_LMAX];                        // pivots d_j
-    __shared__ double s_tol;
     __shared__ int s_clamped;
-    int local;
-    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
-    if (iter >= 0 && iter > P.q) return;
-    if (mode == CHOL_SECOND && !second_pass(P, iter)) return;
-    const int l = P.l;
-    if (l > CRT_LMAX) return;
+    const int l = n;
     const int tid = threadIdx.x;
     const int nt4 = (l + 3) / 4;
     const int nup = nt4 * (nt4 - 1) / 2;  // strictly upper tiles
@@ -285,8 +106,6 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
         }
     }
     const int a0 = 4 * ta, b0 = 4 * tb;
-    const double* __restrict__ G = P.G;
-    const bool first = mode == CHOL_FIRST;
 
     double x[4][4];
 #pragma unroll
@@ -294,21 +113,10 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
 #pragma unroll
         for (int c = 0; c < 4; c++) {
             const int a = a0 + r, b = b0 + c;
-            x[r][c] = (own && a < l && b < l && a <= b) ? G[a * l + b] : 0.0;
+            x[r][c] = (own && a < l && b < l && a <= b) ? Gs[a * ld + b] : 0.0;
         }
-    if (tid < 64) {
-        double mx = 0.0;
-        for (int i = tid; i < l; i += 64) mx = fmax(mx, fabs(G[i * l + i]));
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if (tid == 0) {
-            const double t = (double)l * 0x1.0p-52 * mx;
-            s_tol = t > 0.0 ? t : 0x1.0p-1000;
-            s_clamped = 0;
-        }
-    }
+    if (tid == 0) s_clamped = 0;
     __syncthreads();
-    const double tol = s_tol;
 
     // The loop touches only registers and LDS: a barrier never waits for
     // global memory.  R and R^{-1} are written from the registers at the end.
@@ -444,13 +252,10 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
         }
     }
     __syncthreads();
-    if (tid == 0 && s_clamped) atomicOr(P.flags, FLAG_RANK_DEF);
+    if (tid == 0 && s_clamped) *clamped = 1;
     // R[a][b] = v_a[b] / sqrt(d_a) (b > a), sqrt(d_a) (b = a), 0 below;
     // R^{-1}[b][a] = E[a][b] / sqrt(d_a) (b < a), 1/sqrt(d_a) (b = a), 0 above.
     if (own) {
-        double* __restrict__ Rout = P.R;
-        double* __restrict__ Rinv = P.Rinv;
-        double* __restrict__ Racc = P.Racc;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int a = a0 + r;
@@ -462,26 +267,142 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
                 const int b = b0 + c;
                 if (b >= l) continue;
                 const double xv = x[r][c];
-                const double rv = b > a ? xv * rsq : (b == a ? sq : 0.0);
-                Rout[a * l + b] = rv;
-                if (first) Racc[a * l + b] = rv;
-                Rinv[b * l + a] = b < a ? xv * rsq : (b == a ? rsq : 0.0);
+                Rout[a * ld + b] = b > a ? xv * rsq : (b == a ? sq : 0.0);
+                Rinv[b * ld + a] = b < a ? xv * rsq : (b == a ? rsq : 0.0);
             }
         }
     }
 }
 
+
+// C = alpha op(A) op(B) + beta C for the small blocks of the large-l
+// Cholesky (M, N, K <= 136), on FP64 MFMA 16x16x4: the waves of the work-group
+// take the 16 x 16 output tiles in turn; operands are read from (cache
+// resident) global memory, zero outside the matrices.  op(A)[i][k] is
+// A[k * lda + i] when ta, else A[i * lda + k]; likewise op(B) with tb.
+__device__ void blk_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
+                         bool ta, const double* __restrict__ B, int ldb, bool tb, double beta,
+                         double* __restrict__ C, int ldc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int mt = (M + 15) / 16, ntl = (N + 15) / 16;
+    for (int tile = wave; tile < mt * ntl; tile += nw) {
+        const int ti = tile / ntl, tj = tile - ti * ntl;
+        const int ar = 16 * ti + li, bc = 16 * tj + li;
+        f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+                const int k = k0 + 4 * s + lg;
+                const bool ok = k < K;
+                av[s] = (ok && ar < M) ? (ta ? A[k * lda + ar] : A[ar * lda + k]) : 0.0;
+                bv[s] = (ok && bc < N) ? (tb ? B[bc * ldb + k] : B[k * ldb + bc]) : 0.0;
+            }
+#pragma unroll
+            for (int s = 0; s < 4; s++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int r = 16 * ti + lg + 4 * e;
+            if (r < M && bc < N) {
+                double* c = C + r * ldc + bc;
+                *c = beta == 0.0 ? alpha * acc[e] : fma(alpha, acc[e], beta * *c);
+            }
+        }
+    }
+}
+
+// The Cholesky stage: G = R^T R, R^{-1}, for l <= 264.  l <= 128: one block
+// factor in registers.  Larger l: nb = ceil(l / 128) diagonal blocks, right
+// looking: factor block k, form its block row R_kj = R_kk^{-T} G_kj, subtract
+// R_kj^T R_kj from the trailing blocks of G (in place); then the blocks of
+// R^{-1} above the diagonal, last block column first:
+// R^{-1}_ij = -R^{-1}_ii sum_{i<m<=j} R_im R^{-1}_mj.  All phases run in this
+// one work-group, separated by barriers; the block products read and write
+// cache-resident global memory (Qt serves as the l x l temporary).
+__global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict__ probs,
+                                                        const int32_t* __restrict__ pidx,
+                                                        const int32_t* __restrict__ toff, int cnt,
+                                                        int mode, int iter) {
+    __shared__ double s_tol;
+    __shared__ int s_clamped_any;
+    int local;
+    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
+    if (iter >= 0 && iter > P.q) return;
+    if (mode == CHOL_SECOND && !second_pass(P, iter)) return;
+    const int l = P.l;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    double* __restrict__ G = P.G;
+    double* __restrict__ R = P.R;
+    double* __restrict__ Ri = P.Rinv;
+    if (tid < 64) {
+        double mx = 0.0;
+        for (int i = tid; i < l; i += 64) mx = fmax(mx, fabs(G[i * l + i]));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        if (tid == 0) {
+            const double t = (double)l * 0x1.0p-52 * mx;
+            s_tol = t > 0.0 ? t : 0x1.0p-1000;
+            s_clamped_any = 0;
+        }
+    }
+    __syncthreads();
+    const double tol = s_tol;
+    {
+        const int nb = (l + CRT_LMAX - 1) / CRT_LMAX;
+        const int bs = ((l + nb - 1) / nb + 3) / 4 * 4;
+        // blocks of R and R^{-1} below the diagonal blocks are zero
+        if (nb > 1)
+            for (int e = tid; e < l * l; e += nth) {
+                const int a = e / l, b = e - (e / l) * l;
+                if (a / bs != b / bs && b < a) { R[e] = 0.0; Ri[e] = 0.0; }
+            }
+        for (int k = 0; k < nb; k++) {
+            const int o = k * bs, n = min(bs, l - o), o2 = o + n, rest = l - o2;
+            chol_block(G + o * l + o, n, R + o * l + o, Ri + o * l + o, l, tol, &s_clamped_any);
+            __syncthreads();
+            if (rest <= 0) break;
+            // block row: R_kj = (R^{-1}_kk)^T G_kj
+            blk_gemm(n, rest, n, 1.0, Ri + o * l + o, l, true, G + o * l + o2, l, false, 0.0,
+                     R + o * l + o2, l);
+            __syncthreads();
+            // trailing update: G_jj -= R_kj^T R_kj (the lower triangle is never read)
+            blk_gemm(rest, rest, n, -1.0, R + o * l + o2, l, true, R + o * l + o2, l, false, 1.0,
+                     G + o2 * l + o2, l);
+            __syncthreads();
+        }
+        // R^{-1} above the diagonal blocks
+        double* __restrict__ Tm = P.Qt;
+        for (int j = 1; j < nb; j++) {
+            const int oj = j * bs, nj = min(bs, l - oj);
+            for (int i = j - 1; i >= 0; i--) {
+                const int oi = i * bs, ni = bs;
+                // Tm = sum_{i<m<=j} R_im R^{-1}_mj  (ni x nj)
+                const int kk = oj + nj - (oi + ni);
+                blk_gemm(ni, nj, kk, 1.0, R + oi * l + oi + ni, l, false, Ri + (oi + ni) * l + oj, l,
+                         false, 0.0, Tm, l);
+                __syncthreads();
+                // R^{-1}_ij = -R^{-1}_ii Tm
+                blk_gemm(ni, nj, ni, -1.0, Ri + oi * l + oi, l, false, Tm, l, false, 0.0,
+                         Ri + oi * l + oj, l);
+                __syncthreads();
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && s_clamped_any) atomicOr(P.flags, FLAG_RANK_DEF);
+    if (mode == CHOL_FIRST)
+        for (int e = tid; e < l * l; e += nth) P.Racc[e] = R[e];
+}
+
 hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
-    // ceil(l/4)^2 tile owners, rounded up to whole waves
+    // ceil(l/4)^2 tile owners of a diagonal block, rounded up to whole waves
     const int nt4 = (std::min(lmax, CRT_LMAX) + 3) / 4;
-    const int threads = std::min(CRT_THREADS, (nt4 * nt4 + 63) / 64 * 64);
+    const int threads = lmax > CRT_LMAX ? CRT_THREADS
+                                        : std::min(CRT_THREADS, (nt4 * nt4 + 63) / 64 * 64);
     hipLaunchKernelGGL(k_chol_rt, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx,
-                       g.toff, g.count, mode, iter);
-    hipError_t er = hipGetLastError();
-    if (er != hipSuccess || lmax <= CRT_LMAX) return er;
-    // l > 128: the variant with the work array in global memory.
-    hipLaunchKernelGGL(k_chol<false>, dim3(g.blocks), dim3(CHOL_THREADS), 0, s, g.probs, g.pidx,
                        g.toff, g.count, mode, iter);
     return hipGetLastError();
 }
