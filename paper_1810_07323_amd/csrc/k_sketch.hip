@@ -31,9 +31,13 @@ template <> struct SkCfg<P_F32> { static constexpr int BK = 32, VEC = 4; };
 template <> struct SkCfg<P_BF16> { static constexpr int BK = 64, VEC = 8; };
 template <> struct SkCfg<P_FP8> { static constexpr int BK = 128, VEC = 16; };
 
-constexpr int SK_THREADS = 256;
 constexpr int SK_RT = 2;                      // row tiles of 16 per wave
-constexpr int SK_BM = 4 * SK_RT * 16;         // output rows per block (128)
+// A X blocks: 4 waves, 128 output rows (each A row contributes a long
+// contiguous K run).  A^T X blocks: 8 waves, 256 output rows, so that every
+// row of A a block reads is a 1 KB (FP32) contiguous run rather than 512 B.
+template <bool TRANS> __host__ __device__ constexpr int sk_waves() { return TRANS ? 8 : 4; }
+template <bool TRANS> __host__ __device__ constexpr int sk_threads() { return 64 * sk_waves<TRANS>(); }
+template <bool TRANS> __host__ __device__ constexpr int sk_bm() { return 32 * sk_waves<TRANS>(); }
 constexpr int ROWB = 144;                     // LDS bytes per 128-byte K row (+16 pad)
 
 template <int PREC, bool TRANS>
@@ -41,8 +45,8 @@ __host__ __device__ constexpr int sk_a_bytes() {
     // Non-transposed (and 1/2-byte transposed) tiles: BM rows of 128 (+16) bytes.
     // F32/F64 transposed tiles: BK rows of BM elements (+16 bytes).
     return (TRANS && (PREC == P_F32 || PREC == P_F64))
-               ? SkCfg<PREC>::BK * (SK_BM * PrecT<PREC>::SZ + 16)
-               : SK_BM * ROWB;
+               ? SkCfg<PREC>::BK * (sk_bm<TRANS>() * PrecT<PREC>::SZ + 16)
+               : sk_bm<TRANS>() * ROWB;
 }
 
 template <int PREC, int NT, bool TRANS>
@@ -72,12 +76,14 @@ __device__ __forceinline__ i32x4 load16(const T* p, int64_t valid, bool vec_ok) 
 }
 
 template <int PREC, int NT, bool TRANS>
-__global__ __launch_bounds__(SK_THREADS) void k_sketch(const Prob* __restrict__ probs,
+__global__ __launch_bounds__(sk_threads<TRANS>()) void k_sketch(const Prob* __restrict__ probs,
                                                        const int32_t* __restrict__ pidx,
                                                        const int32_t* __restrict__ toff, int cnt,
                                                        int iter) {
     typedef typename PrecT<PREC>::T T;
     typedef typename PrecT<PREC>::Acc Acc;
+    constexpr int SK_THREADS = sk_threads<TRANS>();
+    constexpr int SK_BM = sk_bm<TRANS>();
     constexpr int SZ = PrecT<PREC>::SZ;
     constexpr int BK = SkCfg<PREC>::BK;
     constexpr int VEC = SkCfg<PREC>::VEC;
@@ -393,7 +399,7 @@ static hipError_t launch_nt(const LaunchGroup& g, int iter, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sketch<PREC, NT, TRANS>), dim3(g.blocks), dim3(SK_THREADS), lds, s,
+    hipLaunchKernelGGL((k_sketch<PREC, NT, TRANS>), dim3(g.blocks), dim3(sk_threads<TRANS>()), lds, s,
                        g.probs, g.pidx, g.toff, g.count, iter);
     return hipGetLastError();
 }
@@ -422,7 +428,7 @@ hipError_t launch_sketch(int prec, bool trans, int nt, const LaunchGroup& g, int
     return hipErrorInvalidValue;
 }
 
-int sketch_rows_per_block() { return SK_BM; }
+int sketch_rows_per_block(bool trans) { return trans ? sk_bm<true>() : sk_bm<false>(); }
 int sketch_k_tile(int prec) {
     switch (prec) {
         case P_F64: return SkCfg<P_F64>::BK;

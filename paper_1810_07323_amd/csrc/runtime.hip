@@ -108,8 +108,9 @@ enum {
 // more), at most 8 splits, each split at least 4 K tiles long.  The layout of
 // a problem depends on its own shape only, never on what it is batched with,
 // so a decomposition gives bitwise the same result alone, batched or served.
-static void split_k(int64_t rows, int64_t K, int bk, int target, int32_t* s, int64_t* kc) {
-    const int64_t nrb = cdiv(rows, sketch_rows_per_block());
+static void split_k(int64_t rows, int64_t K, int bk, int target, bool trans, int32_t* s,
+                    int64_t* kc) {
+    const int64_t nrb = cdiv(rows, sketch_rows_per_block(trans));
     int64_t sp = std::min<int64_t>(8, std::max<int64_t>(1, target / nrb));
     sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / (4 * bk)));
     int64_t c = roundup(cdiv(K, sp), bk);
@@ -155,8 +156,9 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
     L.ldx = roundup(n, 64);
     L.ldq = roundup(m, 64);
     const int bk = sketch_k_tile(prec);
-    split_k(m, n, bk, sketch_target, &L.s_ax, &L.kc_ax);
-    split_k(n, m, bk, sketch_target, &L.s_atx, &L.kc_atx);
+    // A^T X blocks are twice as large (one per CU at a time): half the target
+    split_k(m, n, bk, sketch_target, false, &L.s_ax, &L.kc_ax);
+    split_k(n, m, bk, sketch_target / 2, true, &L.s_atx, &L.kc_atx);
     gram_chunks(m, L.lp, gram_target, &L.rb_m, &L.gb_m);
     gram_chunks(n, L.lp, gram_target, &L.rb_n, &L.gb_n);
     const int sz = prec_size(prec);
@@ -329,7 +331,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     }
     struct SkRef { int prec, nt; TableBuilder::Ref ax, atx; double bax, fax, batx, fatx; };
     std::vector<SkRef> skrefs;
-    const int64_t bm = sketch_rows_per_block();
+    const int64_t bm = sketch_rows_per_block(false), bmt = sketch_rows_per_block(true);
     for (auto& kv : classes) {
         std::vector<int64_t> bax, batx;
         double bytes_ax = 0, fl = 0, bytes_atx = 0;
@@ -337,7 +339,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
             const cor_problem& q = probs[i];
             const Layout& L = P->lay[i];
             bax.push_back(cdiv(q.m, bm) * L.s_ax);
-            batx.push_back(cdiv(q.n, bm) * L.s_atx);
+            batx.push_back(cdiv(q.n, bmt) * L.s_atx);
             const double sz = prec_size(q.prec);
             const double abytes = (double)q.m * q.n * sz;
             bytes_ax += abytes + (double)q.n * L.l * sz + (double)q.m * L.l * 4.0;
