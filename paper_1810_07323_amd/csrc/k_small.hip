@@ -14,8 +14,8 @@
 namespace cor {
 
 constexpr int QRCP_LDS_MAX = 136;  // l*l doubles + scratch
-constexpr int QRT_LMAX = 128;      // register-resident QRCP: 4 lanes per column
-constexpr int QRT_THREADS = 4 * QRT_LMAX;
+constexpr int QRT_LMAX = 128;      // register-resident QRCP: up to 8 lanes per column
+constexpr int QRT_THREADS = 8 * QRT_LMAX;
 
 __device__ __forceinline__ const Prob& group_prob2(const Prob* probs, const int32_t* pidx,
                                                    const int32_t* toff, int cnt, int& local) {
@@ -25,37 +25,39 @@ __device__ __forceinline__ const Prob& group_prob2(const Prob* probs, const int3
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky and inverse in one register-resident sweep (l <= 128).
+// Cholesky and inverse in one sweep over an n x n block (n <= 128), with the
+// work matrix held in FP64 MFMA accumulator tiles.
 //
 // Symmetric Gaussian elimination on [G | I], four columns at a time.  The
-// upper triangle of the l x l work matrix holds the Schur complement, the
-// strict lower triangle accumulates E = L^{-1} (G = L D L^T, L unit lower);
-// row j is final once its column has been eliminated and then holds
-// v_j = (row j of the Schur complement at step j), so that
+// upper triangle of the np x np work matrix X (np = n rounded up to 16) holds
+// the Schur complement, the strict lower triangle accumulates E = L^{-1}
+// (G = L D L^T, L unit lower).  Row j is final once its column block has been
+// eliminated and then holds v_j (row j of the Schur complement at step j) and
+// E[j][0..j), so that
 //   R    = D^{1/2} L^T   : R[j][b]    = v_j[b] / sqrt(d_j)          (b >= j)
 //   R^-1 = L^{-T} D^-1/2 : R^-1[b][j] = E[j][b] / sqrt(d_j)         (b <  j)
-// Each thread keeps one 4 x 4 tile in registers (ceil(l/4)^2 threads).  For
-// the block P of columns 4kb .. 4kb + 3:
-//   A. the owner of the diagonal tile factors it, B = L1 D1 L1^T, in
-//      registers (its upper part becomes the rows v_j, its lower part
-//      L1^{-1}) and publishes L1, 1/D1 and the E rows of P inside the block;
-//   B. the other owners of block row P apply L1^{-1} to their tile (the
-//      four pivot rows, Schur or E part, now final) and publish them;
-//   C. every tile below the block subtracts the rank-4 product
-//      sum_k (v_k[a] / d_k) w_k[b], with w = v (Schur part, b >= a) or the
-//      E rows (b < a).
-// Two barriers per four columns; dependent FP64 operations are slow (tens of
-// cycles each), so the serial path is the in-register factor of a 4 x 4
-// block, one triangular solve and one exchange.  Tiles are numbered
-// strictly-upper (row-major), diagonal, strictly-lower (column-major), so a
-// wave holds one kind of tile (but for the two waves at the seams) and waves
-// whose rows are done, or whose E columns have not started, skip the update.
-// A pivot d_j <= l 2^-52 max_i G_ii is clamped to that threshold
-// (numerically rank-deficient sketch) and flagged.  mode FIRST also stores R
-// in Racc (for R2 = R' R).
+// X is cut into 16 x 16 tiles kept in the registers of the work-group in the
+// layout of the f64 16x16x4 MFMA result (lane 16 g + i, register r holds row
+// g + 4 r, column i).  The four rows of column block kb are register kb & 3
+// of tile row kb >> 2.  Diagonal tile t sits in slot 0 of wave t.  Per block:
+//   A. the wave owning the diagonal tile reads the 4 x 4 diagonal block with
+//      lane reads, factors it (B = L1 D1 L1^T) with the same scalar chain in
+//      every lane, writes the rows v (upper part) and L1^{-1} (lower part)
+//      back, and publishes them with 1/d and d;
+//   B. every tile of the block's tile row applies L1^{-1} to the four rows
+//      (one MFMA with K = 4), then publishes the rows;
+//   C. every tile with rows below the block subtracts the rank-4 product
+//      sum_k (v_k[a] / d_k) w_k[b] (one MFMA), w = v in the upper triangle
+//      and the E rows (1 on the diagonal, 0 right of it) in the lower one.
+// The owner of the next diagonal tile updates it first and factors the next
+// 4 x 4 block while the other tiles are updated, so the serial path per block
+// is one exchange, one MFMA and the 4 x 4 factor.  Two barriers per block.
+// A pivot d_j <= tol (l 2^-52 max_i G_ii) is clamped to tol (numerically
+// rank-deficient sketch) and flagged; padding rows get a pivot above tol.
 // ---------------------------------------------------------------------------
 constexpr int CRT_THREADS = 1024;
 constexpr int CRT_LMAX = 128;
+constexpr int CH_SLOTS = 4;  // 16 x 16 tiles per wave (64 tiles on 16 waves)
 
 // 1/d from the hardware estimate and two Newton steps y <- y + y (1 - d y).
 __device__ __forceinline__ double recip_nr(double d) {
@@ -65,215 +67,243 @@ __device__ __forceinline__ double recip_nr(double d) {
     return y;
 }
 
-__device__ __forceinline__ void st2(double* p, double a, double b) {
-    *reinterpret_cast<double2*>(p) = make_double2(a, b);
-}
-__device__ __forceinline__ void ld4(const double* p, double (&v)[4]) {
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    const double2 b = *reinterpret_cast<const double2*>(p + 2);
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+// 1/d with one third-order correction of the hardware estimate y0 (relative
+// error e of order 2^-23): y0 (1 + e + e^2) has relative error e^3.
+__device__ __forceinline__ double recip3(double d) {
+    const double y = __builtin_amdgcn_rcp(d);
+    const double e = fma(-d, y, 1.0);
+    return fma(y, fma(e, e, e), y);
 }
 
-// Factor the n x n block (n <= 128) whose upper triangle is Gs (leading
-// dimension ld): R and R^{-1} of the block into R and Rinv (same leading
-// dimension), pivots clamped at tol.  Every thread of the block calls it.
-__device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n, double* __restrict__ Rout,
-                           double* __restrict__ Rinv, int ld, double tol, int* clamped) {
-    __shared__ __align__(16) double s_ru[2][4][CRT_LMAX];  // v rows of the block (Schur part)
-    __shared__ __align__(16) double s_rl[2][4][CRT_LMAX];  // E rows of the block
-    __shared__ double s_lm[2][8];                           // L1 below its diagonal
-    __shared__ __align__(16) double s_inv[2][4];            // 1 / d of the block
-    __shared__ double s_d[CRT_LMAX];                        // pivots d_j
-    __shared__ int s_clamped;
-    const int l = n;
-    const int tid = threadIdx.x;
-    const int nt4 = (l + 3) / 4;
-    const int nup = nt4 * (nt4 - 1) / 2;  // strictly upper tiles
-    const bool own = tid < nt4 * nt4;
-    // tile of this thread: kind 0 strictly upper, 1 diagonal, 2 strictly lower
-    int ta = -1, tb = -1, kind = 1;
-    if (own) {
-        if (tid < nup) {  // row-major over ta < tb
-            int r = 0, rem = tid;
-            while (rem >= nt4 - 1 - r) { rem -= nt4 - 1 - r; r++; }
-            ta = r; tb = r + 1 + rem; kind = 0;
-        } else if (tid < nup + nt4) {
-            ta = tb = tid - nup; kind = 1;
-        } else {  // column-major over tb < ta
-            int c = 0, rem = tid - nup - nt4;
-            while (rem >= nt4 - 1 - c) { rem -= nt4 - 1 - c; c++; }
-            tb = c; ta = c + 1 + rem; kind = 2;
-        }
-    }
-    const int a0 = 4 * ta, b0 = 4 * tb;
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
 
-    double x[4][4];
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double sel4(const f64x4& x, int h) {
+    return h == 0 ? x[0] : h == 1 ? x[1] : h == 2 ? x[2] : x[3];
+}
+__device__ __forceinline__ void set4(f64x4& x, int h, double v) {
+    x[0] = h == 0 ? v : x[0];
+    x[1] = h == 1 ? v : x[1];
+    x[2] = h == 2 ? v : x[2];
+    x[3] = h == 3 ? v : x[3];
+}
+
+struct CholShared {
+    double w[4][CRT_LMAX];  // the four rows of the current block (after B)
+    double blk[16];         // the factored 4 x 4 block: rows v and L1^{-1}
+    double inv[2][4];       // 1 / d of the block, by block parity
+    double d[CRT_LMAX];     // pivots
+    double sq[CRT_LMAX];    // sqrt(d)
+    double rs[CRT_LMAX];    // 1 / sqrt(d)
+    int clamped;
+};
+
+// A: factor the 4 x 4 diagonal block kb held in register kb & 3 of the
+// wave's diagonal tile x (element (r, c) in lane 16 r + 4 (kb & 3) + c).
+__device__ __forceinline__ void chol_factor4(f64x4& x, int kb, int n, double tol, int g, int i,
+                                             CholShared& sh) {
+    const int lane = threadIdx.x & 63, h = kb & 3;
+    const double xh = sel4(x, h);
+    double s[4][4];
 #pragma unroll
     for (int r = 0; r < 4; r++)
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
-            const int a = a0 + r, b = b0 + c;
-            x[r][c] = (own && a < l && b < l && a <= b) ? Gs[a * ld + b] : 0.0;
+        for (int c = r; c < 4; c++) s[r][c] = readlane_d(xh, 16 * r + 4 * h + c);
+    // Every lane runs the same chain; lane 0 publishes each value once it is
+    // final: blk[4 r + c] = v_r[c] (c >= r) or L1^{-1}[r][c] (c < r).
+    double m[4][4];
+    bool clamp = false;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const double raw = s[k][k];
+        const double d = fmax(raw, tol);
+        clamp |= !(raw > tol) && 4 * kb + k < n;
+        const double y = recip3(d);
+        if (lane == 0) {
+#pragma unroll
+            for (int c = k; c < 4; c++) sh.blk[4 * k + c] = s[k][c];
+            sh.inv[kb & 1][k] = y;
+            sh.d[4 * kb + k] = d;
         }
-    if (tid == 0) s_clamped = 0;
-    __syncthreads();
-
-    // The loop touches only registers and LDS: a barrier never waits for
-    // global memory.  R and R^{-1} are written from the registers at the end.
-    for (int kb = 0; kb < nt4; kb++) {
-        const int pb = kb & 1;
-        // A. factor the diagonal block in registers
-        if (own && kind == 1 && ta == kb) {
-            double inv[4], L[4][4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                double d = x[k][k];
-                if (4 * kb + k >= l) {
-                    d = 1.0;  // padding rows: a unit pivot, nothing to eliminate
-                } else if (!(d > tol)) {
-                    d = tol;
-                    s_clamped = 1;
-                }
-                inv[k] = recip_nr(d);
-                s_d[4 * kb + k] = d;
+        for (int r = k + 1; r < 4; r++) {
+            m[r][k] = s[k][r] * y;
+            // the next pivot first: one FMA after y
+            s[r][r] = fma(-(s[k][r] * s[k][r]), y, s[r][r]);
 #pragma unroll
-                for (int r = k + 1; r < 4; r++) {
-                    const double m = x[k][r] * inv[k];
-                    L[r][k] = m;
-#pragma unroll
-                    for (int c = r; c < 4; c++) x[r][c] = fma(-m, x[k][c], x[r][c]);
-                }
-            }
-            // L1^{-1} (unit lower) into the lower part of the tile
-            double Li[4][4];
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-#pragma unroll
-                for (int j = 0; j < i; j++) {
-                    double t = -L[i][j];
-#pragma unroll
-                    for (int k = j + 1; k < i; k++) t = fma(-L[i][k], Li[k][j], t);
-                    Li[i][j] = t;
-                }
-#pragma unroll
-            for (int i = 1; i < 4; i++)
-#pragma unroll
-                for (int j = 0; j < i; j++) x[i][j] = Li[i][j];
-            s_lm[pb][0] = L[1][0];
-            s_lm[pb][1] = L[2][0];
-            s_lm[pb][2] = L[2][1];
-            s_lm[pb][3] = L[3][0];
-            s_lm[pb][4] = L[3][1];
-            s_lm[pb][5] = L[3][2];
-            st2(&s_inv[pb][0], inv[0], inv[1]);
-            st2(&s_inv[pb][2], inv[2], inv[3]);
-            // E rows of P inside the block: L1^{-1} with its unit diagonal
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                double e[4];
-#pragma unroll
-                for (int c = 0; c < 4; c++) e[c] = c < k ? Li[k][c] : (c == k ? 1.0 : 0.0);
-                st2(&s_rl[pb][k][b0], e[0], e[1]);
-                st2(&s_rl[pb][k][b0 + 2], e[2], e[3]);
-            }
-        }
-        __syncthreads();
-        // B. the rest of block row P: rows of L1^{-1} X, final
-        if (own && kind != 1 && ta == kb) {
-            const double l10 = s_lm[pb][0], l20 = s_lm[pb][1], l21 = s_lm[pb][2];
-            const double l30 = s_lm[pb][3], l31 = s_lm[pb][4], l32 = s_lm[pb][5];
-#pragma unroll
-            for (int c = 0; c < 4; c++) {
-                x[1][c] = fma(-l10, x[0][c], x[1][c]);
-                x[2][c] = fma(-l21, x[1][c], fma(-l20, x[0][c], x[2][c]));
-                x[3][c] = fma(-l32, x[2][c], fma(-l31, x[1][c], fma(-l30, x[0][c], x[3][c])));
-            }
-            if (kind == 0) {
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    st2(&s_ru[pb][k][b0], x[k][0], x[k][1]);
-                    st2(&s_ru[pb][k][b0 + 2], x[k][2], x[k][3]);
-                    st2(&s_rl[pb][k][b0], 0.0, 0.0);  // no E entries past the block
-                    st2(&s_rl[pb][k][b0 + 2], 0.0, 0.0);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    st2(&s_rl[pb][k][b0], x[k][0], x[k][1]);
-                    st2(&s_rl[pb][k][b0 + 2], x[k][2], x[k][3]);
-                }
-            }
-        }
-        __syncthreads();
-        // C. rank-4 update of the tiles below the block
-        if (own && ta > kb && (kind != 2 || tb <= kb)) {
-            double inv[4], fa[4][4];
-            ld4(&s_inv[pb][0], inv);
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                double v[4];
-                ld4(&s_ru[pb][k][a0], v);
-#pragma unroll
-                for (int r = 0; r < 4; r++) fa[k][r] = v[r] * inv[k];
-            }
-            if (kind == 0) {
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    double cb[4];
-                    ld4(&s_ru[pb][k][b0], cb);
-#pragma unroll
-                    for (int r = 0; r < 4; r++)
-#pragma unroll
-                        for (int c = 0; c < 4; c++) x[r][c] = fma(-fa[k][r], cb[c], x[r][c]);
-                }
-            } else if (kind == 2) {
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    double cb[4];
-                    ld4(&s_rl[pb][k][b0], cb);
-#pragma unroll
-                    for (int r = 0; r < 4; r++)
-#pragma unroll
-                        for (int c = 0; c < 4; c++) x[r][c] = fma(-fa[k][r], cb[c], x[r][c]);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    double cu[4], cl[4];
-                    ld4(&s_ru[pb][k][b0], cu);
-                    ld4(&s_rl[pb][k][b0], cl);
-#pragma unroll
-                    for (int r = 0; r < 4; r++)
-#pragma unroll
-                        for (int c = 0; c < 4; c++)
-                            x[r][c] = fma(-fa[k][r], c >= r ? cu[c] : cl[c], x[r][c]);
-                }
-            }
+            for (int c = r + 1; c < 4; c++) s[r][c] = fma(-m[r][k], s[k][c], s[r][c]);
         }
     }
-    __syncthreads();
-    if (tid == 0 && s_clamped) *clamped = 1;
-    // R[a][b] = v_a[b] / sqrt(d_a) (b > a), sqrt(d_a) (b = a), 0 below;
-    // R^{-1}[b][a] = E[a][b] / sqrt(d_a) (b < a), 1/sqrt(d_a) (b = a), 0 above.
-    if (own) {
+    // L1^{-1} (unit lower)
+    double li[4][4];
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int a = a0 + r;
-            if (a >= l) continue;
-            const double sq = sqrt(s_d[a]);
-            const double rsq = 1.0 / sq;
+    for (int r = 1; r < 4; r++)
 #pragma unroll
-            for (int c = 0; c < 4; c++) {
-                const int b = b0 + c;
-                if (b >= l) continue;
-                const double xv = x[r][c];
-                Rout[a * ld + b] = b > a ? xv * rsq : (b == a ? sq : 0.0);
-                Rinv[b * ld + a] = b < a ? xv * rsq : (b == a ? rsq : 0.0);
-            }
+        for (int c = 0; c < r; c++) {
+            double t = -m[r][c];
+#pragma unroll
+            for (int k = c + 1; k < r; k++) t = fma(-m[r][k], li[k][c], t);
+            li[r][c] = t;
         }
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 1; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < r; c++) sh.blk[4 * r + c] = li[r][c];
+        if (clamp) sh.clamped = 1;
+    }
+    // LDS operations of one wave complete in order: read the block back
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int c4 = i - 4 * h;
+    const double bv = sh.blk[4 * g + (c4 & 3)];
+    if (c4 >= 0 && c4 < 4) set4(x, h, bv);
+}
+
+// C: subtract the rank-4 product of block kb from tile (P, Q).
+__device__ __forceinline__ void chol_update_tile(f64x4& x, int P, int Q, int kb,
+                                                 const CholShared& sh) {
+    // lane index read afresh at every call: the compiler would otherwise keep
+    // the LDS addresses of every tile alive across the loop over blocks
+    int lane;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((int)threadIdx.x));
+    const int g = (lane >> 4) & 3, i = lane & 15;
+    const int T = kb >> 2;
+    const int a = 16 * P + i, b = 16 * Q + i, k = 4 * kb + g;
+    const double ma = a > 4 * kb + 3 ? sh.w[g][a] * sh.inv[kb & 1][g] : 0.0;
+    const double wb = sh.w[g][b];
+    const double we = b < k ? wb : (b == k ? 1.0 : 0.0);
+    if (Q > P) {
+        x = mfma_f64(-ma, wb, x);
+    } else if (Q < P) {
+        x = mfma_f64(-ma, we, x);
+    } else {
+        const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
+        const f64x4 du = mfma_f64(ma, wb, zero);
+        const f64x4 dl = P == T ? mfma_f64(ma, we, zero) : zero;
+#pragma unroll
+        for (int r = 0; r < 4; r++) x[r] -= i >= g + 4 * r ? du[r] : dl[r];
     }
 }
 
+__device__ __forceinline__ bool chol_tile_active(int P, int Q, int kb) {
+    const int T = kb >> 2;
+    if (P < T || (P == T && (kb & 3) == 3)) return false;  // no rows below the block
+    return Q >= P || Q <= T;  // E rows are zero right of the block
+}
+
+// One column block kb: B and C, with A of block kb + 1 on the wave that owns
+// the next diagonal tile.
+__device__ __forceinline__ void chol_step(f64x4 (&x)[CH_SLOTS], const int (&tp)[CH_SLOTS],
+                                          const int (&tq)[CH_SLOTS], int kb, int nkb, int n,
+                                          double tol, int wave, int g, int i, CholShared& sh) {
+    const int T = kb >> 2, h = kb & 3;
+    // B. apply L1^{-1} to the block rows of tile row T, publish them
+    // L1^{-1}[i][g] (unit diagonal, zero above it), rows i < 4
+    const double la = i < 4 ? (g < i ? sh.blk[4 * i + g] : (g == i ? 1.0 : 0.0)) : 0.0;
+#pragma unroll
+    for (int s = 0; s < CH_SLOTS; s++) {
+        if (tp[s] != T) continue;
+        const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
+        const double xr = sel4(x[s], h);
+        const f64x4 dd = mfma_f64(la, xr, zero);
+        const bool keep = tq[s] == T && i >= 4 * h && i < 4 * h + 4;  // factored in A
+        const double v = keep ? xr : dd[0];
+        set4(x[s], h, v);
+        sh.w[g][16 * tq[s] + i] = v;
+    }
+    __syncthreads();
+    // C. rank-4 update; the next diagonal tile first, then its factor
+    const int kb1 = kb + 1;
+    const bool next = kb1 < nkb && wave == (kb1 >> 2);
+    if (next) {
+        chol_update_tile(x[0], kb1 >> 2, kb1 >> 2, kb, sh);
+        chol_factor4(x[0], kb1, n, tol, g, i, sh);
+    }
+#pragma unroll
+    for (int s = 0; s < CH_SLOTS; s++) {
+        if (tp[s] < 0 || (s == 0 && next)) continue;
+        if (chol_tile_active(tp[s], tq[s], kb)) chol_update_tile(x[s], tp[s], tq[s], kb, sh);
+    }
+    __syncthreads();
+}
+
+// Factor the n x n block (n <= 128) whose upper triangle is Gs (leading
+// dimension ld): R and R^{-1} of the block into Rout and Rinv (same leading
+// dimension), pivots clamped at tol.  Every thread of the work-group calls it;
+// the work-group has at least max(Tn, Tn^2 / 4) waves, Tn = ceil(n / 16).
+__device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
+                                           double* __restrict__ Rout, double* __restrict__ Rinv,
+                                           int ld, double tol, int* clamped) {
+    __shared__ CholShared sh;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile numbers in SGPRs
+    const int W = blockDim.x >> 6;
+    const int g = lane >> 4, i = lane & 15;
+    const int Tn = (n + 15) >> 4, nkb = (n + 3) >> 2;
+    // padding rows: a pivot above the clamp threshold, nothing to eliminate
+    const double padv = fmax(1.0, 2.0 * tol);
+
+    int tp[CH_SLOTS], tq[CH_SLOTS];
+    f64x4 x[CH_SLOTS];
+#pragma unroll
+    for (int s = 0; s < CH_SLOTS; s++) {
+        const int u = wave + s * W;
+        int P = -1, Q = -1;
+        if (u < Tn) {
+            P = Q = u;
+        } else if (u - Tn < Tn * (Tn - 1)) {
+            const int t = u - Tn;
+            P = t / (Tn - 1);
+            const int c = t - P * (Tn - 1);
+            Q = c < P ? c : c + 1;
+        }
+        tp[s] = P;
+        tq[s] = Q;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int a = 16 * P + g + 4 * r, b = 16 * Q + i;
+            double v = 0.0;
+            if (P >= 0 && a <= b) v = (b < n) ? Gs[a * ld + b] : (a == b ? padv : 0.0);
+            x[s][r] = v;
+        }
+    }
+    if (tid == 0) sh.clamped = 0;
+    __syncthreads();
+    if (wave == 0) chol_factor4(x[0], 0, n, tol, g, i, sh);
+    __syncthreads();
+    for (int kb = 0; kb < nkb; kb++) chol_step(x, tp, tq, kb, nkb, n, tol, wave, g, i, sh);
+    if (tid == 0 && sh.clamped) *clamped = 1;
+    for (int a = tid; a < n; a += blockDim.x) {
+        const double sq = sqrt(sh.d[a]);
+        sh.sq[a] = sq;
+        sh.rs[a] = 1.0 / sq;
+    }
+    __syncthreads();
+    // R[a][b] = v_a[b] / sqrt(d_a) (b > a), sqrt(d_a) (b = a), 0 below;
+    // R^{-1}[b][a] = E[a][b] / sqrt(d_a) (b < a), 1/sqrt(d_a) (b = a), 0 above.
+#pragma unroll
+    for (int s = 0; s < CH_SLOTS; s++) {
+        if (tp[s] < 0) continue;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int a = 16 * tp[s] + g + 4 * r, b = 16 * tq[s] + i;
+            if (a >= n || b >= n) continue;
+            const double rsq = sh.rs[a];
+            const double xv = x[s][r];
+            Rout[a * ld + b] = b > a ? xv * rsq : (b == a ? sh.sq[a] : 0.0);
+            Rinv[b * ld + a] = b < a ? xv * rsq : (b == a ? rsq : 0.0);
+        }
+    }
+}
 
 // C = alpha op(A) op(B) + beta C for the small blocks of the large-l
 // Cholesky (M, N, K <= 136), on FP64 MFMA 16x16x4: the waves of the work-group
@@ -398,10 +428,10 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
 
 hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
-    // ceil(l/4)^2 tile owners of a diagonal block, rounded up to whole waves
-    const int nt4 = (std::min(lmax, CRT_LMAX) + 3) / 4;
-    const int threads = lmax > CRT_LMAX ? CRT_THREADS
-                                        : std::min(CRT_THREADS, (nt4 * nt4 + 63) / 64 * 64);
+    // one wave per 16 x 16 tile of a diagonal block, at most CH_SLOTS tiles
+    // per wave (16 waves for blocks of 113 .. 128)
+    const int tn = (std::min(lmax, CRT_LMAX) + 15) / 16;
+    const int threads = lmax > CRT_LMAX ? CRT_THREADS : 64 * std::min(16, tn * tn);
     hipLaunchKernelGGL(k_chol_rt, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx,
                        g.toff, g.count, mode, iter);
     return hipGetLastError();
@@ -601,12 +631,12 @@ __global__ __launch_bounds__(QR_THREADS) void k_qrcp(const Prob* __restrict__ pr
 
 // ---------------------------------------------------------------------------
 // Register-resident QRCP of M = R2^T for l <= 128 (one block per problem).
-//   Four adjacent lanes own one column of M; lane t of the quad keeps rows
-//   i = 4u + t (u < RPT) in registers, so the trailing matrix never leaves
-//   the register file and per-column dot products and norms are quad sums
-//   (two DPP steps).  Columns stay in place; the pivot column of step j is
-//   found with the 64-bit key above and retired after the step.  Step j:
-//     1. the pivot quad copies its raw column into slot j of an LDS archive
+//   LPC = 8 adjacent lanes own one column of M; lane t of the group
+//   keeps rows i = LPC u + t (u < RPT) in registers, so the trailing matrix
+//   never leaves the register file and per-column dot products and norms are
+//   group sums (DPP steps).  Columns stay in place; the pivot column of step
+//   j is found with the 64-bit key above and retired after the step.  Step j:
+//     1. the pivot group copies its raw column into slot j of an LDS archive
 //        (laid out [t][u] so that a lane moves 16 bytes at a time), reads
 //        alpha = M[j][p] back and forms beta, tau and scale = 1/(alpha-beta)
 //        (reflector v_i = scale*M[i][p] below j, v_j = 1, zero above);
@@ -614,35 +644,45 @@ __global__ __launch_bounds__(QR_THREADS) void k_qrcp(const Prob* __restrict__ pr
 //        w = tau (col_j + scale sum_{i>j} raw_i col_i), col_j -= w,
 //        col_i -= (w scale) raw_i below j, and posts the squared norm of its
 //        rows below j as the next step's key.
-//   Rows above j are skipped in blocks of 4*CH rows (uniform branches); only
-//   the block holding row j needs per-element selects.  Two barriers per
+//   Rows above j are skipped in blocks of LPC*CH rows (uniform branches);
+//   only the block holding row j needs per-element selects.  Two barriers per
 //   step and no global memory access inside the loop: T, the reflectors,
 //   tau, the signs of T_jj and perm are written from the archive at the end.
+//   Eight lanes per column (rather than four) halve the serial work of a
+//   lane and double the waves that hide the FP64 latency.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double quad_sum(double v) {
+template <int LPC>
+__device__ __forceinline__ double group_sum(double v) {
     v += dpp_mov<0xB1>(v);  // quad_perm 1,0,3,2
     v += dpp_mov<0x4E>(v);  // quad_perm 2,3,0,1
+    if constexpr (LPC == 8) v += dpp_mov<0x141>(v);  // row_half_mirror: the two quads
     return v;
 }
 
 template <int RPT>
 __host__ __device__ constexpr int qrt_stride() { return RPT + 2; }  // doubles per archived lane row
 
-template <int RPT>
-__host__ __device__ constexpr size_t qrt_lds_bytes() {
-    return sizeof(double) * (size_t)(4 * RPT) * 4 * qrt_stride<RPT>();
+// dynamic LDS of the archive for l steps
+template <int RPT, int LPC>
+__host__ __device__ constexpr size_t qrt_lds_bytes(int l) {
+    return sizeof(double) * (size_t)l * LPC * qrt_stride<RPT>();
 }
 
-template <int RPT>
-__global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict__ probs,
+template <int RPT, int LPC>
+__global__ __launch_bounds__(LPC * LPC * RPT) void k_qrcp_rt(const Prob* __restrict__ probs,
                                                          const int32_t* __restrict__ pidx,
                                                          const int32_t* __restrict__ toff,
                                                          int cnt) {
-    constexpr int LR = 4 * RPT;   // rows covered
+    constexpr int LR = LPC * RPT;  // rows covered
     constexpr int ST = qrt_stride<RPT>();
     constexpr int CH = RPT < 8 ? RPT : 8;  // u per row block
     constexpr int NCH = RPT / CH;
-    extern __shared__ __align__(16) double s_arc[];  // [LR steps][4 lanes][ST]
+    constexpr int LSH = LPC == 8 ? 3 : 2;
+    // Partial sums per lane (short FP64 chains).  LPC and NP are the same for
+    // every l, so a problem's arithmetic does not depend on the largest l of
+    // its launch (RPT only adds rows of zeros).
+    constexpr int NP = 4;
+    extern __shared__ __align__(16) double s_arc[];  // [l steps][LPC lanes][ST]
     __shared__ double s_nrm[LR];
     __shared__ double s_tau[LR], s_scale[LR], s_beta[LR];
     __shared__ int s_perm[LR];
@@ -652,20 +692,20 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
     const int l = P.l;
     if (l > LR) return;
     const int tid = threadIdx.x;
-    const int c = tid >> 2, t = tid & 3;
+    const int c = tid >> LSH, t = tid & (LPC - 1);
     const bool incol = c < l;
     const double* __restrict__ R2 = P.R2;
 
     double col[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; u++) {
-        const int i = 4 * u + t;
+        const int i = LPC * u + t;
         col[u] = (incol && i < l) ? R2[c * l + i] : 0.0;  // M[i][c] = R2[c][i]
     }
     double nn = 0.0;
 #pragma unroll
     for (int u = 0; u < RPT; u++) nn = fma(col[u], col[u], nn);
-    nn = quad_sum(nn);
+    nn = group_sum<LPC>(nn);
     if (tid < 2) s_key[tid] = 0ull;
     __syncthreads();
     if (incol && t == 0) {
@@ -678,7 +718,7 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
     for (int j = 0; j < l; j++) {
         const unsigned long long key = s_key[j & 1];
         const int p = 511 - (int)(key & 0x1FFull);
-        double* arc = s_arc + j * 4 * ST;
+        double* arc = s_arc + j * LPC * ST;
         if (c == p) {
 #pragma unroll
             for (int u = 0; u < RPT; u += 2)
@@ -686,7 +726,7 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const double alpha = arc[(j & 3) * ST + (j >> 2)];
+            const double alpha = arc[(j & (LPC - 1)) * ST + (j >> LSH)];
             const double ss = s_nrm[p];  // sum over rows >= j of column p squared
             double tau = 0.0, beta = alpha, scale = 1.0;
             if (ss > 0.0) {
@@ -715,14 +755,14 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
         if (active) {
             const double tau = s_tau[j], scale = s_scale[j];
             const double* arct = arc + t * ST;
-            // v_i = scale raw_i below row j, 1 at row j, 0 above.  Eight
+            // v_i = scale raw_i below row j, 1 at row j, 0 above.  NP
             // partial sums per lane keep the dependent FP64 chains short.
-            double vv[RPT], d8[8];
+            double vv[RPT], d8[NP];
 #pragma unroll
-            for (int e = 0; e < 8; e++) d8[e] = 0.0;
+            for (int e = 0; e < NP; e++) d8[e] = 0.0;
 #pragma unroll
             for (int q = 0; q < NCH; q++) {
-                const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
+                const int lo = LPC * CH * q, hi = lo + LPC * CH - 1;
                 if (hi < j) continue;
 #pragma unroll
                 for (int u = q * CH; u < q * CH + CH; u += 2) {
@@ -733,40 +773,41 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
                 if (lo <= j) {
 #pragma unroll
                     for (int u = q * CH; u < q * CH + CH; u++) {
-                        const int i = 4 * u + t;
+                        const int i = LPC * u + t;
                         vv[u] = i > j ? vv[u] : (i == j ? 1.0 : 0.0);
                     }
                 }
 #pragma unroll
-                for (int u = q * CH; u < q * CH + CH; u++) d8[u & 7] = fma(vv[u], col[u], d8[u & 7]);
+                for (int u = q * CH; u < q * CH + CH; u++) d8[u % NP] = fma(vv[u], col[u], d8[u % NP]);
             }
-            const double dsum = ((d8[0] + d8[1]) + (d8[2] + d8[3])) + ((d8[4] + d8[5]) + (d8[6] + d8[7]));
-            const double w = tau * quad_sum(dsum);
-            double n8[8];
+            double dsum = (d8[0] + d8[1]) + (d8[2] + d8[3]);
+            if constexpr (NP == 8) dsum += (d8[4] + d8[5]) + (d8[6] + d8[7]);
+            const double w = tau * group_sum<LPC>(dsum);
+            double n8[NP];
 #pragma unroll
-            for (int e = 0; e < 8; e++) n8[e] = 0.0;
+            for (int e = 0; e < NP; e++) n8[e] = 0.0;
 #pragma unroll
             for (int q = 0; q < NCH; q++) {
-                const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
+                const int lo = LPC * CH * q, hi = lo + LPC * CH - 1;
                 if (hi < j) continue;
                 if (lo > j) {
 #pragma unroll
                     for (int u = q * CH; u < q * CH + CH; u++) {
                         col[u] = fma(-w, vv[u], col[u]);
-                        n8[u & 7] = fma(col[u], col[u], n8[u & 7]);
+                        n8[u % NP] = fma(col[u], col[u], n8[u % NP]);
                     }
                 } else {
 #pragma unroll
                     for (int u = q * CH; u < q * CH + CH; u++) {
-                        const int i = 4 * u + t;
+                        const int i = LPC * u + t;
                         col[u] = fma(-w, vv[u], col[u]);
-                        if (i > j) n8[u & 7] = fma(col[u], col[u], n8[u & 7]);
+                        if (i > j) n8[u % NP] = fma(col[u], col[u], n8[u % NP]);
                     }
                 }
             }
-            const double n0 = (n8[0] + n8[1]) + (n8[2] + n8[3]);
-            const double n1 = (n8[4] + n8[5]) + (n8[6] + n8[7]);
-            const double n = quad_sum(n0 + n1);
+            double nsum = (n8[0] + n8[1]) + (n8[2] + n8[3]);
+            if constexpr (NP == 8) nsum += (n8[4] + n8[5]) + (n8[6] + n8[7]);
+            const double n = group_sum<LPC>(nsum);
             if (t == 0) {
                 s_nrm[c] = n;
                 atomicMax(&s_key[(j + 1) & 1], qr_key(n, c));
@@ -780,13 +821,13 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
         const int a = e / l, b = e % l;
         // T[a][b] (row a, column b): rows above b hold the archived column b.
         double tv = 0.0;
-        if (a < b) tv = s_arc[b * 4 * ST + (a & 3) * ST + (a >> 2)] * (s_beta[a] < 0.0 ? -1.0 : 1.0);
+        if (a < b) tv = s_arc[(b * LPC + (a & (LPC - 1))) * ST + (a >> LSH)] * (s_beta[a] < 0.0 ? -1.0 : 1.0);
         else if (a == b) tv = fabs(s_beta[a]);
         P.T[e] = tv;
         // reflector a, component b
         double vv = 0.0;
         if (b == a) vv = 1.0;
-        else if (b > a) vv = s_arc[a * 4 * ST + (b & 3) * ST + (b >> 2)] * s_scale[a];
+        else if (b > a) vv = s_arc[(a * LPC + (b & (LPC - 1))) * ST + (b >> LSH)] * s_scale[a];
         P.Qt[e] = vv;
     }
     for (int j = tid; j < l; j += blockDim.x) {
@@ -796,17 +837,21 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qrcp_rt(const Prob* __restrict_
     }
 }
 
-template <int RPT>
-static hipError_t launch_qrcp_rt(const LaunchGroup& g, int threads, hipStream_t s) {
-    constexpr size_t lds = qrt_lds_bytes<RPT>();
+template <int RPT, int LPC>
+static hipError_t launch_qrcp_rt(const LaunchGroup& g, int lmax, hipStream_t s) {
+    constexpr int LR = RPT * LPC;
+    const size_t lds = qrt_lds_bytes<RPT, LPC>(std::min(lmax, LR));
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_qrcp_rt<RPT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute((const void*)k_qrcp_rt<RPT, LPC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)qrt_lds_bytes<RPT, LPC>(LR));
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL(k_qrcp_rt<RPT>, dim3(g.blocks), dim3(threads), lds, s, g.probs, g.pidx,
+    // LPC lanes per column, columns rounded up to whole waves
+    const int threads = (LPC * std::min(lmax, LR) + 63) / 64 * 64;
+    hipLaunchKernelGGL((k_qrcp_rt<RPT, LPC>), dim3(g.blocks), dim3(threads), lds, s, g.probs, g.pidx,
                        g.toff, g.count);
     return hipGetLastError();
 }
@@ -815,11 +860,10 @@ hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
     {
         const int lr = std::min(lmax, QRT_LMAX);
-        const int threads = 4 * ((lr + 15) / 16 * 16);
-        hipError_t e = lr <= 16   ? launch_qrcp_rt<4>(g, threads, s)
-                       : lr <= 32 ? launch_qrcp_rt<8>(g, threads, s)
-                       : lr <= 64 ? launch_qrcp_rt<16>(g, threads, s)
-                                  : launch_qrcp_rt<32>(g, threads, s);
+        hipError_t e = lr <= 16   ? launch_qrcp_rt<2, 8>(g, lr, s)
+                       : lr <= 32 ? launch_qrcp_rt<4, 8>(g, lr, s)
+                       : lr <= 64 ? launch_qrcp_rt<8, 8>(g, lr, s)
+                                  : launch_qrcp_rt<16, 8>(g, lr, s);
         if (e != hipSuccess || lmax <= QRT_LMAX) return e;
     }
     // l > 128: M in LDS (l <= 136) or in global memory.

@@ -232,6 +232,10 @@ struct Plan {
     Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, applyM, applyN, vg, r2, norm;
     std::vector<Grp> skAX, skATX;  // per (precision, column tiles)
     std::vector<Grp> formU;        // per register-tile class of l (nt holds l)
+    // per iteration of the power loop: whether any problem of the plan takes
+    // the second CholeskyQR pass, and whether it is any problem's last one
+    // (kernels return at once for the others; their launches are skipped)
+    std::vector<char> second, last;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     bool async = false;
@@ -285,6 +289,13 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         P->nj = std::max(P->nj, (int)((q.k + q.p + 63) / 64));
         P->lmax = std::max(P->lmax, (int)(q.k + q.p));
     }
+    P->second.assign(P->max_q + 1, 0);
+    P->last.assign(P->max_q + 1, 0);
+    for (int i = 0; i < count; i++)
+        for (int it = 0; it <= probs[i].q; it++) {
+            if (it == probs[i].q || (opts && opts->cholqr2_all)) P->second[it] = 1;
+            if (it == probs[i].q) P->last[it] = 1;
+        }
 
     // Launch tables.
     TableBuilder tb;
@@ -500,10 +511,12 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_gram_reduce(P->redM.g, SIDE_M, 0, it, s));
         E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
         E(launch_apply(P->applyM.g, SIDE_M, AP_Y_RINV_QA, P->lmax, it, s));
-        E(launch_gram(P->gramM.g, SIDE_M, GSRC_QA, it, s));
-        E(launch_gram_reduce(P->redM.g, SIDE_M, 1, it, s));
-        E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
-        E(launch_apply(P->applyM.g, SIDE_M, AP_QA_RINV_Q, P->lmax, it, s));
+        if (P->second[it]) {
+            E(launch_gram(P->gramM.g, SIDE_M, GSRC_QA, it, s));
+            E(launch_gram_reduce(P->redM.g, SIDE_M, 1, it, s));
+            E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
+            E(launch_apply(P->applyM.g, SIDE_M, AP_QA_RINV_Q, P->lmax, it, s));
+        }
         if (fp8) {
             E(launch_op_scales(P->small.g, SIDE_M, it, s));
             E(launch_make_op(P->opM.g, SIDE_M, s));
@@ -515,11 +528,13 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_gram_reduce(P->redN.g, SIDE_N, 0, it, s));
         E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
         E(launch_apply(P->applyN.g, SIDE_N, AP_Y_RINV_QA, P->lmax, it, s));
-        E(launch_gram(P->gramN.g, SIDE_N, GSRC_QA, it, s));
-        E(launch_gram_reduce(P->redN.g, SIDE_N, 1, it, s));
-        E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
-        E(launch_r2(P->r2.g, it, s));
-        E(launch_apply(P->applyN.g, SIDE_N, AP_QA_RINV_Q, P->lmax, it, s));
+        if (P->second[it]) {
+            E(launch_gram(P->gramN.g, SIDE_N, GSRC_QA, it, s));
+            E(launch_gram_reduce(P->redN.g, SIDE_N, 1, it, s));
+            E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
+        }
+        if (P->last[it]) E(launch_r2(P->r2.g, it, s));
+        if (P->second[it]) E(launch_apply(P->applyN.g, SIDE_N, AP_QA_RINV_Q, P->lmax, it, s));
         if (fp8 && it < P->max_q) {
             E(launch_op_scales(P->small.g, SIDE_N, it, s));
             E(launch_make_op(P->opN.g, SIDE_N, s));
