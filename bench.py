@@ -36,6 +36,15 @@ WORKLOADS = {
                    seed=303, desc="20000x10000 BF16, sigma_i=i^-1.5; k=200, l=220, q=2"),
     "c1": dict(m=1000, n=1000, rank=1000, spectrum="c1", k=10, p=5, q=1, prec="f64", seed=101,
                noise=1e-6, desc="1000x1000 FP64, sigma 1 (i<=10) then 1e-3*0.9^(i-10); k=10, l=15, q=1"),
+    # many independent problems in one batched plan (BF16 passes)
+    "c4batched": dict(count=512, seed=404, prec="bf16",
+                      desc="512 problems, m,n ~ U{256..4096}, k ~ U{8..64}, l=k+8, q=1, "
+                           "sigma_i=exp(-i/k), BF16 passes, one batched plan"),
+    # open-loop served requests: BF16-served vs plain sequential FP32
+    "c5served": dict(count=160, seed=505, pool=16,
+                     desc="Poisson requests, m,n log-uniform [512,16384], k ~ U{16..256}, p=8, "
+                          "q ~ U{0,1,2}, 10% robust-PCA 76800x2000; FP32 inputs served in BF16 "
+                          "vs plain sequential FP32"),
 }
 
 
@@ -102,6 +111,213 @@ def cpu_baseline(a_host, w, budget_s=20.0):
                        f"(est. {total:.1f} s per decomposition)")
 
 
+def bench_batched(args, w, cu, torch, np):
+    """Decompositions/s of one batched plan over many independent problems."""
+    import inputs as I
+
+    dev = torch.device("cuda:0")
+    specs = I.batched_problems(w["count"], w["seed"])
+    mats, probs, outs, sigs = [], [], [], []
+    for s in specs:
+        sig = I.spectrum("expk", s["rank"], s["k"])
+        a64, _ = I.lowrank(s["m"], s["n"], sig, s["seed"], backend="torch", device=dev)
+        A = a64.to(torch.bfloat16).contiguous()
+        del a64
+        l = s["k"] + s["p"]
+        o = (torch.empty((s["m"], l), dtype=torch.float64, device=dev),
+             torch.empty((l, l), dtype=torch.float64, device=dev),
+             torch.empty((s["n"], l), dtype=torch.float64, device=dev),
+             torch.empty((l,), dtype=torch.int32, device=dev))
+        probs.append(cu.make_problem(A, s["k"], s["p"], s["q"], s["seed"], *o))
+        mats.append(A)
+        outs.append(o)
+        sigs.append(sig)
+    stream = torch.cuda.Stream()
+    st, plan = cu.cor_plan_create(probs, cu.cor_opts(0, 0))
+    cu.check(st, "plan_create")
+    with torch.cuda.stream(stream):
+        if not args.no_graph:
+            cu.check(cu.cor_plan_capture(plan, stream), "plan_capture")
+        for _ in range(args.warmup):
+            cu.check(cu.cor_plan_run(plan, stream), "plan_run")
+        stream.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(args.steps):
+            cu.check(cu.cor_plan_run(plan, stream), "plan_run")
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        # roofline of the passes: an eager plan over the same problems
+        st2, plan2 = cu.cor_plan_create(probs, cu.cor_opts(0, 0))
+        cu.check(st2, "plan_create")
+        cu.cor_profile_enable(True)
+        cu.cor_profile_read()
+        for _ in range(min(args.steps, 5)):
+            cu.check(cu.cor_plan_run(plan2, stream), "plan_run")
+        torch.cuda.synchronize()
+        prof = cu.cor_profile_read()
+        cu.cor_profile_enable(False)
+        cu.cor_plan_destroy(plan2)
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    elapsed = t1 - t0
+    # accuracy of a sample of the timed results against their optimum
+    worst = 0.0
+    for j in range(0, len(specs), max(1, len(specs) // 16)):
+        s, (U, T, V, _) = specs[j], outs[j]
+        a = mats[j].double()
+        err = float(torch.linalg.norm(a - (U @ T) @ V.T) / torch.linalg.norm(a))
+        s2 = sigs[j] ** 2
+        l = s["k"] + s["p"]
+        opt = float(np.sqrt(s2[l:].sum() / s2.sum())) if len(s2) > l else 0.0
+        worst = max(worst, err / max(opt, 1e-300) if opt > 0 else err)
+        del a
+    launches = max(1, prof["launches"])
+    avg_s = prof["ms"] / launches / 1e3
+    achieved = prof["bytes"] / launches / avg_s / 1e9
+    cu.cor_plan_destroy(plan)
+    return {
+        "metric": "CoR-UTV decompositions/s (roofline of the passes over A; p50/p99 latency)",
+        "value": round(len(specs) * args.steps / elapsed, 3),
+        "unit": "decomps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": args.workload + ": " + w["desc"], "problems": len(specs),
+                   "graph": not args.no_graph},
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
+                       "p99": round(float(np.percentile(step_ms, 99)), 4)},
+        "accuracy": {"worst_err_l_over_opt_sampled": worst},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": PEAKS["hbm_GBs"],
+                     "unit": "GB/s", "frac": round(achieved / PEAKS["hbm_GBs"], 4),
+                     "traffic": None, "kernel": "k_sketch (passes over A, all problems)",
+                     "avg_launch_us": round(avg_s * 1e6, 2)},
+        "cpu_baseline": None,
+    }
+
+
+def bench_served(args, w, cu, torch, np):
+    """Open-loop served requests (FP32 inputs converted and served in BF16)
+    against the plain path (each FP32 request alone, one after another)."""
+    import inputs as I
+
+    dev = torch.device("cuda:0")
+    reqs = I.served_requests(w["count"], w["seed"], rate=1.0, pool=w["pool"])
+    # matrices: a pool of decaying-spectrum FP32 matrices and one robust-PCA input
+    pool = {}
+    for r in reqs:
+        if r["kind"] == "decay" and r["pool"] not in pool:
+            j = r["pool"]
+            m, n = r["m"], r["n"]
+            kj = 16 + (j * 37) % 241
+            rank = min(m, n, 4 * (kj + 8))
+            sig = I.spectrum("expk", rank, kj)
+            a64, _ = I.lowrank(m, n, sig, w["seed"] * 100 + j, backend="torch", device=dev)
+            pool[j] = a64.float().contiguous()
+            del a64
+    rp = None
+    if any(r["kind"] == "rpca" for r in reqs):
+        g = torch.Generator(device=dev).manual_seed(w["seed"])
+        g1 = torch.randn(76800, 5, generator=g, device=dev)
+        g2 = torch.randn(2000, 5, generator=g, device=dev)
+        rp = g1 @ g2.T
+        cnt = int(round(0.05 * rp.numel()))
+        pos = torch.randperm(rp.numel(), generator=g, device=dev)[:cnt]
+        sgn = torch.where(torch.rand(cnt, generator=g, device=dev) < 0.5, -80.0, 80.0)
+        rp.view(-1)[pos] += sgn
+        rp = rp.contiguous()
+
+    def mat(r):
+        return rp if r["kind"] == "rpca" else pool[r["pool"]]
+
+    def outputs(r):
+        l = r["k"] + r["p"]
+        return (torch.empty((r["m"], l), dtype=torch.float64, device=dev),
+                torch.empty((l, l), dtype=torch.float64, device=dev),
+                torch.empty((r["n"], l), dtype=torch.float64, device=dev),
+                torch.empty((l,), dtype=torch.int32, device=dev))
+
+    opts = cu.cor_opts(1, 0)  # report: each result carries its error
+    # plain path: FP32, one request after another (warm the code paths first)
+    for r in reqs[:2]:
+        st, _ = cu.cor_utv_ex(cu.make_problem(mat(r), r["k"], r["p"], r["q"], r["seed"],
+                                              *outputs(r)), opts)
+        cu.check(st, "plain warmup")
+    torch.cuda.synchronize()
+    plain_err, plain_lat = [], []
+    t0 = time.perf_counter()
+    for r in reqs:
+        ts = time.perf_counter()
+        st, info = cu.cor_utv_ex(cu.make_problem(mat(r), r["k"], r["p"], r["q"], r["seed"],
+                                                 *outputs(r)), opts)
+        cu.check(st, "plain")
+        plain_lat.append((time.perf_counter() - ts) * 1e3)
+        plain_err.append(info.err_l)
+    torch.cuda.synchronize()
+    plain_rate = len(reqs) / (time.perf_counter() - t0)
+
+    def serve(rate):
+        st, srv = cu.cor_server_create(hbm_budget=0, max_slots=0, convert_f32_to=cu.COR_BF16)
+        cu.check(st, "server_create")
+        keep, tickets = [], []
+        try:
+            start = time.perf_counter()
+            for r in reqs:
+                due = start + (r["t"] / rate if rate else 0.0)
+                now = time.perf_counter()
+                if due > now:
+                    time.sleep(due - now)
+                o = outputs(r)
+                pr = cu.make_problem(mat(r), r["k"], r["p"], r["q"], r["seed"], *o)
+                st, t = cu.cor_server_submit(srv, pr, opts)
+                cu.check(st, "submit")
+                keep.append((pr, o))
+                tickets.append(t)
+            errs = []
+            for t in tickets:
+                st, info = cu.cor_server_wait(srv, t)
+                cu.check(st, "wait")
+                errs.append(info.err_l)
+            st, stats = cu.cor_server_stats_get(srv)
+            cu.check(st, "stats")
+            return stats.as_dict(), errs
+        finally:
+            cu.check(cu.cor_server_destroy(srv), "destroy")
+
+    sat, errs = serve(0.0)  # every request at once: saturation throughput
+    lam = 0.8 * sat["decomps_per_s"]
+    open_loop, errs2 = serve(lam)  # Poisson arrivals at 0.8 x saturation
+    # Requests whose FP32 error is below the BF16 storage floor (l >= rank(A):
+    # exact recovery up to the format) are compared by absolute difference.
+    floor = 2.0 ** -8
+    big = [(e, p) for e, p in zip(errs, plain_err) if p >= floor]
+    ratio = max((e / p for e, p in big), default=None)
+    absdiff = max(abs(e - p) for e, p in zip(errs, plain_err))
+    return {
+        "metric": "CoR-UTV decompositions/s (roofline of the passes over A; p50/p99 latency)",
+        "value": round(sat["decomps_per_s"], 3),
+        "unit": "decomps/s",
+        "n_gpus": 1, "steps": len(reqs), "warmup": 2,
+        "ms_per_step": round(1e3 / sat["decomps_per_s"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": args.workload + ": " + w["desc"], "requests": len(reqs)},
+        "served_saturation": sat,
+        "served_poisson_0.8": dict(open_loop, arrival_rate_per_s=lam),
+        "plain_fp32": {"decomps_per_s": plain_rate,
+                       "p50_ms": float(np.percentile(plain_lat, 50)),
+                       "p99_ms": float(np.percentile(plain_lat, 99))},
+        "served_over_plain": sat["decomps_per_s"] / plain_rate,
+        "accuracy": {"max_err_l_served_over_plain": ratio, "requests_compared": len(big),
+                     "max_abs_err_l_difference": absdiff, "bf16_floor": floor},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +354,12 @@ def main():
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "c4batched":
+        print(json.dumps(bench_batched(args, w, cu, torch, np)))
+        return
+    if args.workload == "c5served":
+        print(json.dumps(bench_served(args, w, cu, torch, np)))
+        return
     k, p, q = w["k"], w["p"], w["q"]
     l = k + p
     m, n = w["m"], w["n"]

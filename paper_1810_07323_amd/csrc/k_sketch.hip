@@ -32,26 +32,34 @@ template <> struct SkCfg<P_BF16> { static constexpr int BK = 64, VEC = 8; };
 template <> struct SkCfg<P_FP8> { static constexpr int BK = 128, VEC = 16; };
 
 constexpr int SK_RT = 2;                      // row tiles of 16 per wave
-// A X blocks: 4 waves, 128 output rows (each A row contributes a long
-// contiguous K run).  A^T X blocks: 8 waves, 256 output rows, so that every
-// row of A a block reads is a 1 KB (FP32) contiguous run rather than 512 B.
-template <bool TRANS> __host__ __device__ constexpr int sk_waves() { return TRANS ? 8 : 4; }
-template <bool TRANS> __host__ __device__ constexpr int sk_threads() { return 64 * sk_waves<TRANS>(); }
-template <bool TRANS> __host__ __device__ constexpr int sk_bm() { return 32 * sk_waves<TRANS>(); }
+// Block shapes.  A X blocks in FP32/FP64: 4 waves, 128 output rows (each A
+// row contributes a long contiguous K run).  A^T X blocks: 8 waves, 256
+// output rows, so that every row of A a block reads is a 1 KB (FP32)
+// contiguous run rather than 512 B.  BF16 A X blocks: 8 waves too, which
+// halves the X tile traffic per byte of A (the X tile is as large as the A
+// tile at l = 220).  Eight waves mean two per SIMD and half the register file
+// each: shapes whose accumulators do not fit that (FP64 beyond 8 column
+// tiles, FP32 beyond 12, FP8 beyond 10, FP8 A X) keep 4 waves.
+template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_waves() {
+    constexpr int ntmax = PREC == P_F64 ? 8 : PREC == P_F32 ? 12 : PREC == P_FP8 ? 10 : NTMAX;
+    return (NT <= ntmax && (TRANS || PREC == P_BF16)) ? 8 : 4;
+}
+template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_threads() { return 64 * sk_waves<PREC, NT, TRANS>(); }
+template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_bm() { return 32 * sk_waves<PREC, NT, TRANS>(); }
 constexpr int ROWB = 144;                     // LDS bytes per 128-byte K row (+16 pad)
 
-template <int PREC, bool TRANS>
+template <int PREC, int NT, bool TRANS>
 __host__ __device__ constexpr int sk_a_bytes() {
     // Non-transposed (and 1/2-byte transposed) tiles: BM rows of 128 (+16) bytes.
     // F32/F64 transposed tiles: BK rows of BM elements (+16 bytes).
     return (TRANS && (PREC == P_F32 || PREC == P_F64))
-               ? SkCfg<PREC>::BK * (sk_bm<TRANS>() * PrecT<PREC>::SZ + 16)
-               : sk_bm<TRANS>() * ROWB;
+               ? SkCfg<PREC>::BK * (sk_bm<PREC, NT, TRANS>() * PrecT<PREC>::SZ + 16)
+               : sk_bm<PREC, NT, TRANS>() * ROWB;
 }
 
 template <int PREC, int NT, bool TRANS>
 __host__ __device__ constexpr int sk_lds_bytes() {
-    return 2 * (sk_a_bytes<PREC, TRANS>() + NT * 16 * ROWB);
+    return 2 * (sk_a_bytes<PREC, NT, TRANS>() + NT * 16 * ROWB);
 }
 
 // Sixteen zero bytes in global memory: out-of-range rows of a full tile are
@@ -76,18 +84,18 @@ __device__ __forceinline__ i32x4 load16(const T* p, int64_t valid, bool vec_ok) 
 }
 
 template <int PREC, int NT, bool TRANS>
-__global__ __launch_bounds__(sk_threads<TRANS>()) void k_sketch(const Prob* __restrict__ probs,
+__global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(const Prob* __restrict__ probs,
                                                        const int32_t* __restrict__ pidx,
                                                        const int32_t* __restrict__ toff, int cnt,
                                                        int iter) {
     typedef typename PrecT<PREC>::T T;
     typedef typename PrecT<PREC>::Acc Acc;
-    constexpr int SK_THREADS = sk_threads<TRANS>();
-    constexpr int SK_BM = sk_bm<TRANS>();
+    constexpr int SK_THREADS = sk_threads<PREC, NT, TRANS>();
+    constexpr int SK_BM = sk_bm<PREC, NT, TRANS>();
     constexpr int SZ = PrecT<PREC>::SZ;
     constexpr int BK = SkCfg<PREC>::BK;
     constexpr int VEC = SkCfg<PREC>::VEC;
-    constexpr int ABYTES = sk_a_bytes<PREC, TRANS>();
+    constexpr int ABYTES = sk_a_bytes<PREC, NT, TRANS>();
     constexpr int XBYTES = NT * 16 * ROWB;
 
     extern __shared__ __align__(16) unsigned char smem[];
@@ -399,7 +407,7 @@ static hipError_t launch_nt(const LaunchGroup& g, int iter, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sketch<PREC, NT, TRANS>), dim3(g.blocks), dim3(sk_threads<TRANS>()), lds, s,
+    hipLaunchKernelGGL((k_sketch<PREC, NT, TRANS>), dim3(g.blocks), dim3(sk_threads<PREC, NT, TRANS>()), lds, s,
                        g.probs, g.pidx, g.toff, g.count, iter);
     return hipGetLastError();
 }
@@ -428,7 +436,27 @@ hipError_t launch_sketch(int prec, bool trans, int nt, const LaunchGroup& g, int
     return hipErrorInvalidValue;
 }
 
-int sketch_rows_per_block(bool trans) { return trans ? sk_bm<true>() : sk_bm<false>(); }
+template <int PREC, bool TRANS>
+static int rows_nt(int nt) {
+    switch (nt) {
+#define NT_CASE(N) case N: return sk_bm<PREC, N, TRANS>();
+        NT_CASE(1) NT_CASE(2) NT_CASE(3) NT_CASE(4) NT_CASE(5) NT_CASE(6) NT_CASE(7) NT_CASE(8)
+        NT_CASE(9) NT_CASE(10) NT_CASE(11) NT_CASE(12) NT_CASE(13) NT_CASE(14) NT_CASE(15)
+        NT_CASE(16) NT_CASE(17)
+#undef NT_CASE
+        default: return 128;
+    }
+}
+
+int sketch_rows_per_block(int prec, int nt, bool trans) {
+    switch (prec) {
+        case P_F64: return trans ? rows_nt<P_F64, true>(nt) : rows_nt<P_F64, false>(nt);
+        case P_F32: return trans ? rows_nt<P_F32, true>(nt) : rows_nt<P_F32, false>(nt);
+        case P_BF16: return trans ? rows_nt<P_BF16, true>(nt) : rows_nt<P_BF16, false>(nt);
+        default: return trans ? rows_nt<P_FP8, true>(nt) : rows_nt<P_FP8, false>(nt);
+    }
+}
+
 int sketch_k_tile(int prec) {
     switch (prec) {
         case P_F64: return SkCfg<P_F64>::BK;

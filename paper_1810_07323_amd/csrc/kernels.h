@@ -23,7 +23,7 @@ enum Side : int32_t { SIDE_M = 0, SIDE_N = 1 };
 // Passes over A (split-K partial sums).
 hipError_t launch_sketch(int prec, bool trans, int nt, const LaunchGroup& g, int iter,
                          hipStream_t s);
-int sketch_rows_per_block(bool trans);  // output rows per block of A X / A^T X
+int sketch_rows_per_block(int prec, int nt, bool trans);  // output rows per block of A X / A^T X
 int sketch_k_tile(int prec);
 
 // Row-block kernels.

@@ -108,9 +108,9 @@ enum {
 // more), at most 8 splits, each split at least 4 K tiles long.  The layout of
 // a problem depends on its own shape only, never on what it is batched with,
 // so a decomposition gives bitwise the same result alone, batched or served.
-static void split_k(int64_t rows, int64_t K, int bk, int target, bool trans, int32_t* s,
-                    int64_t* kc) {
-    const int64_t nrb = cdiv(rows, sketch_rows_per_block(trans));
+static void split_k(int64_t rows, int64_t K, int bk, int target, int prec, int nt, bool trans,
+                    int32_t* s, int64_t* kc) {
+    const int64_t nrb = cdiv(rows, sketch_rows_per_block(prec, nt, trans));
     int64_t sp = std::min<int64_t>(8, std::max<int64_t>(1, target / nrb));
     sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / (4 * bk)));
     int64_t c = roundup(cdiv(K, sp), bk);
@@ -156,9 +156,13 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
     L.ldx = roundup(n, 64);
     L.ldq = roundup(m, 64);
     const int bk = sketch_k_tile(prec);
-    // A^T X blocks are twice as large (one per CU at a time): half the target
-    split_k(m, n, bk, sketch_target, false, &L.s_ax, &L.kc_ax);
-    split_k(n, m, bk, sketch_target / 2, true, &L.s_atx, &L.kc_atx);
+    // 8-wave blocks are twice as large (one per CU at a time): half the target
+    split_k(m, n, bk,
+            sketch_rows_per_block(prec, L.nt, false) > 128 ? sketch_target / 2 : sketch_target,
+            prec, L.nt, false, &L.s_ax, &L.kc_ax);
+    split_k(n, m, bk,
+            sketch_rows_per_block(prec, L.nt, true) > 128 ? sketch_target / 2 : sketch_target,
+            prec, L.nt, true, &L.s_atx, &L.kc_atx);
     gram_chunks(m, L.lp, gram_target, &L.rb_m, &L.gb_m);
     gram_chunks(n, L.lp, gram_target, &L.rb_n, &L.gb_n);
     const int sz = prec_size(prec);
@@ -342,15 +346,14 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     }
     struct SkRef { int prec, nt; TableBuilder::Ref ax, atx; double bax, fax, batx, fatx; };
     std::vector<SkRef> skrefs;
-    const int64_t bm = sketch_rows_per_block(false), bmt = sketch_rows_per_block(true);
     for (auto& kv : classes) {
         std::vector<int64_t> bax, batx;
         double bytes_ax = 0, fl = 0, bytes_atx = 0;
         for (int i : kv.second) {
             const cor_problem& q = probs[i];
             const Layout& L = P->lay[i];
-            bax.push_back(cdiv(q.m, bm) * L.s_ax);
-            batx.push_back(cdiv(q.n, bmt) * L.s_atx);
+            bax.push_back(cdiv(q.m, sketch_rows_per_block(q.prec, L.nt, false)) * L.s_ax);
+            batx.push_back(cdiv(q.n, sketch_rows_per_block(q.prec, L.nt, true)) * L.s_atx);
             const double sz = prec_size(q.prec);
             const double abytes = (double)q.m * q.n * sz;
             bytes_ax += abytes + (double)q.n * L.l * sz + (double)q.m * L.l * 4.0;
