@@ -13,9 +13,11 @@
 
 namespace cor {
 
-constexpr int QRCP_LDS_MAX = 136;  // l*l doubles + scratch
 constexpr int QRT_LMAX = 128;      // register-resident QRCP: up to 8 lanes per column
 constexpr int QRT_THREADS = 8 * QRT_LMAX;
+constexpr int QHY_RR = 36;     // registers + LDS QRCP: register rows per lane,
+constexpr int QHY_LMAX = 224;  // largest l (LDS rows per lane <= 20: 143 KB)
+constexpr int QHY_LR = (QHY_LMAX + 3) / 4 - QHY_RR;
 
 __device__ __forceinline__ const Prob& group_prob2(const Prob* probs, const int32_t* pidx,
                                                    const int32_t* toff, int cnt, int& local) {
@@ -470,162 +472,404 @@ hipError_t launch_r2(const LaunchGroup& g, int iter, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// QRCP of M = R2^T (l x l), one block of 256 threads per problem.
-//   Pivot: during the trailing update each column posts
+// Pivot keys of the QRCP: during the trailing update each column posts
 //   key = (bits of its squared norm with the 9 low mantissa bits cleared) |
 //   (511 - position) with a 64-bit LDS atomicMax; for non-negative doubles
-//   the bit pattern orders like the value, so the winner is the largest norm
-//   and, among norms equal to 43 bits, the lowest position.
-//   Step j: wave 0 swaps the pivot column into position j and turns it into
-//   the reflector v (v_j = 1 implicit, beta on the diagonal); then every
-//   thread takes a trailing column: w = tau v^T col, col -= w v, and its new
-//   squared norm over the rows below j.  Two barriers per step.
-// Outputs: T (upper, T_jj >= 0), perm, the reflectors VT[j][a] (row j is v_j,
-// zero left of j) in Qt, tau[j] and the column signs sign[j] = tau[LMAX + j].
+// the bit pattern orders like the value, so the winner is the largest norm
+// and, among norms equal to 43 bits, the lowest position.
 // ---------------------------------------------------------------------------
-constexpr int QR_THREADS = 256;
-
 __device__ __forceinline__ unsigned long long qr_key(double nn, int c) {
     return (__double_as_longlong(nn) & ~0x1FFull) | (unsigned long long)(511 - c);
 }
 
-template <bool IN_LDS>
-__global__ __launch_bounds__(QR_THREADS) void k_qrcp(const Prob* __restrict__ probs,
-                                                     const int32_t* __restrict__ pidx,
-                                                     const int32_t* __restrict__ toff, int cnt) {
-    extern __shared__ __align__(16) double sm[];
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_mov<0xB1>(v);  // quad_perm 1,0,3,2
+    v += dpp_mov<0x4E>(v);  // quad_perm 2,3,0,1
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// QRCP of M = R2^T for l > 232 (one block of up to 1024 threads per problem).
+//   M does not fit the registers of one work-group, so it stays in a global
+//   work array W (l x l, row-major, in P.R, which is free once R2 is formed;
+//   it stays in L2).  Four lanes own a column, lane t the rows i = 4 u + t
+//   (a lane group takes a second column when l > 256).
+//   Columns stay in place and a retired column is never written again, so W
+//   itself keeps every pivot column as it was at its step.  Step j:
+//     1. the pivot column goes into an LDS buffer (one element per thread),
+//        and every lane forms beta, tau and scale = 1/(alpha - beta) as in
+//        the register-resident kernel;
+//     2. every remaining column: w = tau (col_j + scale sum_{i>j} raw_i col_i)
+//        over its rows at and below j (loads in batches of 64 rows, four
+//        partial sums per lane, a quad sum), then col -= w v, stored back, and
+//        the squared norm below j posted as the next key.
+//   Rows above j are skipped in batches (uniform branches).  Outputs as in
+//   the register-resident kernel, read from W at the end.
+// ---------------------------------------------------------------------------
+constexpr int QST_THREADS = 1024;
+constexpr int QST_COLS = QST_THREADS / 4;  // columns per pass over the lane groups
+
+__global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict__ probs,
+                                                        const int32_t* __restrict__ pidx,
+                                                        const int32_t* __restrict__ toff, int cnt) {
+    constexpr int UB = 8;  // u per batch (32 rows)
+    __shared__ double s_piv[LMAX];
     __shared__ double s_nrm[LMAX];
-    __shared__ double s_tau[LMAX];
+    __shared__ double s_tau[LMAX], s_scale[LMAX], s_beta[LMAX];
     __shared__ int s_perm[LMAX];
     __shared__ unsigned long long s_key[2];
     int local;
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
     const int l = P.l;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (l <= QRT_LMAX) return;  // k_qrcp_rt
-    if (IN_LDS != (l <= QRCP_LDS_MAX)) return;
-    double* W;
-    if constexpr (IN_LDS) W = sm;
-    else W = P.R;  // P.R is free once R2 is formed
+    if (l <= QHY_LMAX) return;  // k_qrcp_rt, k_qrcp_hy
+    const int tid = threadIdx.x, t = tid & 3;
+    const int ngroups = blockDim.x >> 2;
+    // a lane group owns column tid/4 and, when l exceeds the group count,
+    // column tid/4 + ngroups as well
+    const int ncs = (l + ngroups - 1) / ngroups;  // 1 or 2
+    const int rpt = (l + 3) >> 2;       // rows per lane
+    const int nb = (rpt + UB - 1) / UB; // batches per lane
+    double* __restrict__ W = P.R;
+    const double* __restrict__ R2 = P.R2;
 
-#pragma unroll 8
-    for (int e = tid; e < l * l; e += QR_THREADS) {
-        const int a = e / l, b = e % l;
-        W[e] = P.R2[b * l + a];  // M = R2^T
-    }
-    for (int c = tid; c < l; c += QR_THREADS) s_perm[c] = c;
+    // W = M = R2^T, and the squared column norms
     if (tid < 2) s_key[tid] = 0ull;
     __syncthreads();
-    for (int c = tid; c < l; c += QR_THREADS) {
-        double n4[4] = {0.0, 0.0, 0.0, 0.0};
-        int i = 0;
-        for (; i + 8 <= l; i += 8) {
-            double wv[8];
-#pragma unroll
-            for (int u = 0; u < 8; u++) wv[u] = W[(i + u) * l + c];
-#pragma unroll
-            for (int u = 0; u < 8; u++) n4[u & 3] += wv[u] * wv[u];
+    for (int cs = 0; cs < ncs; cs++) {
+        const int c = (tid >> 2) + cs * ngroups;
+        double nn = 0.0;
+        for (int u = 0; u < rpt; u++) {
+            const int i = 4 * u + t;
+            if (c < l && i < l) {
+                const double v = R2[c * l + i];
+                W[i * l + c] = v;
+                nn = fma(v, v, nn);
+            }
         }
-        for (; i < l; i++) n4[0] += W[i * l + c] * W[i * l + c];
-        const double ss = (n4[0] + n4[1]) + (n4[2] + n4[3]);
-        s_nrm[c] = ss;
-        atomicMax(&s_key[0], qr_key(ss, c));
+        nn = quad_sum(nn);
+        if (c < l && t == 0) {
+            s_nrm[c] = nn;
+            atomicMax(&s_key[0], qr_key(nn, c));
+        }
     }
+    bool active[2] = {(tid >> 2) < l, (tid >> 2) + ngroups < l};
     __syncthreads();
 
     for (int j = 0; j < l; j++) {
-        if (wave == 0) {
-            const unsigned long long key = s_key[j & 1];
-            const int p = 511 - (int)(key & 0x1FFull);
-            const double alpha = W[j * l + p];  // becomes W[j][j] after the swap
-            const double ss = s_nrm[p];         // sum_{i >= j} W[i][p]^2
-            __builtin_amdgcn_wave_barrier();
-            const double xnorm = sqrt(ss);
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (xnorm != 0.0) {
-                beta = alpha >= 0.0 ? -xnorm : xnorm;
-                scale = 1.0 / (alpha - beta);
-                tau = (beta - alpha) / beta;
-            }
-            for (int i = lane; i < l; i += 64) {  // each lane owns rows i = lane (mod 64)
-                double wj = W[i * l + j];
-                if (p != j) {
-                    const double wp = W[i * l + p];
-                    W[i * l + p] = wj;
-                    wj = wp;
-                }
-                if (i > j) wj = xnorm != 0.0 ? wj * scale : wj;
-                else if (i == j) wj = beta;
-                W[i * l + j] = wj;
-            }
-            if (lane == 0) {
-                s_tau[j] = tau;
-                s_key[j & 1] = 0ull;
-                if (p != j) {
-                    const int t = s_perm[j]; s_perm[j] = s_perm[p]; s_perm[p] = t;
-                    s_nrm[p] = s_nrm[j];
-                }
-            }
-        }
+        const unsigned long long key = s_key[j & 1];
+        const int p = 511 - (int)(key & 0x1FFull);
+        // the pivot column into LDS, one element per thread (one round trip);
+        // the key slot of the next step (last read in step j - 1) is cleared
+        // before the barrier, so no posting can precede the clearing
+        if (tid < l) s_piv[tid] = W[tid * l + p];
+        if (tid == 0) s_key[(j + 1) & 1] = 0ull;
         __syncthreads();
-        const double tau = s_tau[j];
-        for (int c = j + 1 + tid; c < l; c += QR_THREADS) {
-            // w = tau v^T col (v_j = 1), 16 rows per batch of independent loads
-            double d4[4] = {W[j * l + c], 0.0, 0.0, 0.0};
-            int i = j + 1;
-            for (; i + 16 <= l; i += 16) {
-                double vv[16], wv[16];
+        // every lane forms the reflector's scalars (no further barrier)
+        const double alpha = s_piv[j];
+        const double ss = s_nrm[p];  // sum over rows >= j of column p squared
+        double tau = 0.0, beta = alpha, scale = 1.0;
+        if (ss > 0.0) {
+            const double h = 0.5 * ss;
+            double y = __builtin_amdgcn_rsq(ss);
 #pragma unroll
-                for (int u = 0; u < 16; u++) {
-                    vv[u] = W[(i + u) * l + j];
-                    wv[u] = W[(i + u) * l + c];
+            for (int it = 0; it < 2; it++) y = fma(y, fma(-h * y, y, 0.5), y);
+            const double xnorm = ss * y;
+            const double sg = alpha >= 0.0 ? -1.0 : 1.0;
+            beta = sg * xnorm;
+            scale = recip_nr(alpha - beta);
+            tau = (beta - alpha) * (sg * y);
+        }
+        if (tid == 0) {
+            s_tau[j] = tau;
+            s_scale[j] = scale;
+            s_beta[j] = beta;
+            s_perm[j] = p;
+        }
+        for (int cs = 0; cs < ncs; cs++) {
+            const int c = (tid >> 2) + cs * ngroups;
+            if (c == p) active[cs] = false;
+            if (!active[cs]) continue;
+            // dot pass: two batches of rows per round trip
+            double d4[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < nb; q += 2) {
+                if (4 * UB * q + 8 * UB - 1 < j) continue;  // both batches above j
+                double cv[2 * UB], pv[2 * UB];
+#pragma unroll
+                for (int e = 0; e < 2 * UB; e++) {
+                    const int i = min(4 * (UB * q + e) + t, l - 1);
+                    cv[e] = W[i * l + c];
+                    pv[e] = s_piv[i];
                 }
 #pragma unroll
-                for (int u = 0; u < 16; u++) d4[u & 3] += vv[u] * wv[u];
+                for (int e = 0; e < 2 * UB; e++) {
+                    const int i = 4 * (UB * q + e) + t;
+                    const double v = (i < l && i > j) ? pv[e] * scale : (i == j ? 1.0 : 0.0);
+                    d4[e & 3] = fma(v, cv[e], d4[e & 3]);
+                }
             }
-            for (; i < l; i++) d4[0] += W[i * l + j] * W[i * l + c];
-            const double w = tau * ((d4[0] + d4[1]) + (d4[2] + d4[3]));
-            W[j * l + c] -= w;
+            const double w = tau * quad_sum((d4[0] + d4[1]) + (d4[2] + d4[3]));
             double n4[4] = {0.0, 0.0, 0.0, 0.0};
-            i = j + 1;
-            for (; i + 16 <= l; i += 16) {
-                double vv[16], wv[16];
+            for (int q = 0; q < nb; q += 2) {
+                if (4 * UB * q + 8 * UB - 1 < j) continue;
+                double cv[2 * UB], pv[2 * UB];
 #pragma unroll
-                for (int u = 0; u < 16; u++) {
-                    vv[u] = W[(i + u) * l + j];
-                    wv[u] = W[(i + u) * l + c];
+                for (int e = 0; e < 2 * UB; e++) {
+                    const int i = min(4 * (UB * q + e) + t, l - 1);
+                    cv[e] = W[i * l + c];
+                    pv[e] = s_piv[i];
                 }
 #pragma unroll
-                for (int u = 0; u < 16; u++) {
-                    const double x = wv[u] - w * vv[u];
-                    W[(i + u) * l + c] = x;
-                    n4[u & 3] += x * x;
+                for (int e = 0; e < 2 * UB; e++) {
+                    const int i = 4 * (UB * q + e) + t;
+                    if (i < l && i >= j) {
+                        const double v = i > j ? pv[e] * scale : 1.0;
+                        const double x = fma(-w, v, cv[e]);
+                        W[i * l + c] = x;
+                        if (i > j) n4[e & 3] = fma(x, x, n4[e & 3]);
+                    }
                 }
             }
-            for (; i < l; i++) {
-                const double x = W[i * l + c] - w * W[i * l + j];
-                W[i * l + c] = x;
-                n4[0] += x * x;
+            const double n = quad_sum((n4[0] + n4[1]) + (n4[2] + n4[3]));
+            if (t == 0) {
+                s_nrm[c] = n;
+                atomicMax(&s_key[(j + 1) & 1], qr_key(n, c));
             }
-            const double nn = (n4[0] + n4[1]) + (n4[2] + n4[3]);
-            s_nrm[c] = nn;
-            atomicMax(&s_key[(j + 1) & 1], qr_key(nn, c));
         }
         __syncthreads();
     }
 
-    double* tau_out = P.tau;
-    for (int j = tid; j < l; j += QR_THREADS) {
-        tau_out[j] = s_tau[j];
-        tau_out[LMAX + j] = W[j * l + j] < 0.0 ? -1.0 : 1.0;
+    // Outputs: column perm[b] of W holds raw_b (frozen since step b).
+    for (int e = tid; e < l * l; e += blockDim.x) {
+        const int a = e / l, b = e % l;
+        double tv = 0.0;
+        if (a < b) tv = W[a * l + s_perm[b]] * (s_beta[a] < 0.0 ? -1.0 : 1.0);
+        else if (a == b) tv = fabs(s_beta[a]);
+        P.T[e] = tv;
+        // reflector a, component b
+        double vv = 0.0;
+        if (b == a) vv = 1.0;
+        else if (b > a) vv = W[b * l + s_perm[a]] * s_scale[a];
+        P.Qt[e] = vv;
+    }
+    for (int j = tid; j < l; j += blockDim.x) {
+        P.tau[j] = s_tau[j];
+        P.tau[LMAX + j] = s_beta[j] < 0.0 ? -1.0 : 1.0;
         P.perm[j] = s_perm[j];
     }
-    for (int e = tid; e < l * l; e += QR_THREADS) {
+}
+
+// ---------------------------------------------------------------------------
+// QRCP of M = R2^T for 128 < l <= 232: registers and LDS (one block of 4 l
+// threads per problem).  Four lanes own a column, lane t the rows
+// i = 4 u + t; rows u < QHY_RR stay in registers and rows u >= QHY_RR in LDS
+// (u-major, so a wave's lanes touch consecutive words).  Step j as in the
+// register-resident kernel: the pivot group puts its raw column into an LDS
+// buffer laid out [t][u] (16-byte reads) and into a global archive (P.R,
+// column j = raw_j, read only at the end) and forms beta, tau and scale;
+// every other column takes w = tau (col_j + scale sum_{i>j} raw_i col_i),
+// col_i -= (w scale) raw_i below j, col_j -= w, and posts its squared norm
+// below j: one FMA per element and pass, masks only in the block of row j.
+// Register rows above j are skipped in blocks of 16 (uniform branches).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict__ probs,
+                                                        const int32_t* __restrict__ pidx,
+                                                        const int32_t* __restrict__ toff,
+                                                        int cnt) {
+    constexpr int RR = QHY_RR, CH = 4;  // register rows, skipped in blocks of 4 CH rows
+    static_assert(RR % CH == 0 && CH % 2 == 0, "register rows in whole blocks of pairs");
+    constexpr int LR = QHY_LR;
+    constexpr int ST = RR + LR + 2;  // doubles per lane row of the pivot buffer
+    extern __shared__ __align__(16) double s_m[];  // [u - RR][thread]
+    __shared__ __align__(16) double s_pv[4 * ST];  // raw pivot column, [t][u]
+    __shared__ double s_nrm[QHY_LMAX];
+    __shared__ double s_tau[QHY_LMAX], s_scale[QHY_LMAX], s_beta[QHY_LMAX];
+    __shared__ int s_perm[QHY_LMAX];
+    __shared__ unsigned long long s_key[2];
+    int local;
+    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
+    const int l = P.l;
+    if (l <= QRT_LMAX || l > QHY_LMAX) return;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int c = tid >> 2, t = tid & 3;
+    const bool incol = c < l;
+    const int rpt = (l + 3) >> 2;  // rows per lane
+    const int lr = rpt - RR;       // of them in LDS (1 .. LR)
+    double* __restrict__ arc = P.R;  // archive: column j = raw pivot column of step j
+    const double* __restrict__ R2 = P.R2;
+
+    // rows past l are zero and stay zero (the pivot column is zero there)
+    double col[RR];
+    double nn = 0.0;
+#pragma unroll
+    for (int u = 0; u < RR; u++) {
+        const int i = 4 * u + t;
+        col[u] = (incol && i < l) ? R2[c * l + i] : 0.0;  // M[i][c] = R2[c][i]
+        nn = fma(col[u], col[u], nn);
+    }
+#pragma unroll
+    for (int k = 0; k < LR; k++) {
+        const int i = 4 * (RR + k) + t;
+        if (k < lr) {
+            const double v = (incol && i < l) ? R2[c * l + i] : 0.0;
+            s_m[k * nth + tid] = v;
+            nn = fma(v, v, nn);
+        }
+    }
+    nn = quad_sum(nn);
+    if (tid < 2) s_key[tid] = 0ull;
+    __syncthreads();
+    if (incol && t == 0) {
+        s_nrm[c] = nn;
+        atomicMax(&s_key[0], qr_key(nn, c));
+    }
+    bool active = incol;
+    __syncthreads();
+
+    for (int j = 0; j < l; j++) {
+        const unsigned long long key = s_key[j & 1];
+        const int p = 511 - (int)(key & 0x1FFull);
+        if (c == p) {
+            double* pv = s_pv + t * ST;
+            double* ar = arc + j * l;  // archive (read back only at the end)
+#pragma unroll
+            for (int u = 0; u < RR; u += 2) {
+                *reinterpret_cast<double2*>(pv + u) = make_double2(col[u], col[u + 1]);
+                if (4 * u + t < l) ar[4 * u + t] = col[u];
+                if (4 * u + 4 + t < l) ar[4 * u + 4 + t] = col[u + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < LR; k++) {
+                const int i = 4 * (RR + k) + t;
+                if (k < lr) {
+                    const double v = s_m[k * nth + tid];
+                    pv[RR + k] = v;
+                    if (i < l) ar[i] = v;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double alpha = s_pv[(j & 3) * ST + (j >> 2)];
+            const double ss = s_nrm[p];  // sum over rows >= j of column p squared
+            double tau = 0.0, beta = alpha, scale = 1.0;
+            if (ss > 0.0) {
+                const double h = 0.5 * ss;
+                double y = __builtin_amdgcn_rsq(ss);
+#pragma unroll
+                for (int it = 0; it < 2; it++) y = fma(y, fma(-h * y, y, 0.5), y);
+                const double xnorm = ss * y;
+                const double sg = alpha >= 0.0 ? -1.0 : 1.0;
+                beta = sg * xnorm;
+                scale = recip_nr(alpha - beta);
+                tau = (beta - alpha) * (sg * y);
+            }
+            if (t == 0) {
+                s_tau[j] = tau;
+                s_scale[j] = scale;
+                s_beta[j] = beta;
+                s_perm[j] = p;
+                s_key[(j + 1) & 1] = 0ull;
+            }
+            active = false;
+        }
+        __syncthreads();
+        if (active) {
+            const double tau = s_tau[j], scale = s_scale[j];
+            const double* pv = s_pv + t * ST;
+            // w = tau (col_j + scale sum_{i > j} raw_i col_i); only the block
+            // that holds row j needs per-element masks
+            double d4[4] = {0.0, 0.0, 0.0, 0.0};
+            double cj = 0.0;  // col_j in the lane that holds row j
+#pragma unroll
+            for (int q = 0; q < RR / CH; q++) {
+                const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
+                if (hi < j) continue;
+#pragma unroll
+                for (int u = q * CH; u < q * CH + CH; u += 2) {
+                    const double2 r = *reinterpret_cast<const double2*>(pv + u);
+                    const int i0 = 4 * u + t, i1 = i0 + 4;
+                    if (lo > j) {
+                        d4[u & 3] = fma(r.x, col[u], d4[u & 3]);
+                        d4[(u + 1) & 3] = fma(r.y, col[u + 1], d4[(u + 1) & 3]);
+                    } else {
+                        d4[u & 3] = fma(i0 > j ? r.x : 0.0, col[u], d4[u & 3]);
+                        d4[(u + 1) & 3] = fma(i1 > j ? r.y : 0.0, col[u + 1], d4[(u + 1) & 3]);
+                        cj = i0 == j ? col[u] : (i1 == j ? col[u + 1] : cj);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < LR; k++) {
+                if (k < lr) {
+                    const int i = 4 * (RR + k) + t;
+                    const double x = s_m[k * nth + tid];
+                    d4[k & 3] = fma(i > j ? pv[RR + k] : 0.0, x, d4[k & 3]);
+                    cj = i == j ? x : cj;
+                }
+            }
+            const double w = tau * quad_sum(fma(scale, (d4[0] + d4[1]) + (d4[2] + d4[3]), cj));
+            const double ws = w * scale;
+            // col_i -= ws raw_i below j, col_j -= w; squared norm below j
+            double n4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < RR / CH; q++) {
+                const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
+                if (hi < j) continue;
+#pragma unroll
+                for (int u = q * CH; u < q * CH + CH; u += 2) {
+                    const double2 r = *reinterpret_cast<const double2*>(pv + u);
+                    const int i0 = 4 * u + t, i1 = i0 + 4;
+                    if (lo > j) {
+                        col[u] = fma(-ws, r.x, col[u]);
+                        col[u + 1] = fma(-ws, r.y, col[u + 1]);
+                        n4[u & 3] = fma(col[u], col[u], n4[u & 3]);
+                        n4[(u + 1) & 3] = fma(col[u + 1], col[u + 1], n4[(u + 1) & 3]);
+                    } else {
+                        col[u] = i0 > j ? fma(-ws, r.x, col[u]) : (i0 == j ? col[u] - w : col[u]);
+                        col[u + 1] = i1 > j ? fma(-ws, r.y, col[u + 1]) : (i1 == j ? col[u + 1] - w : col[u + 1]);
+                        if (i0 > j) n4[u & 3] = fma(col[u], col[u], n4[u & 3]);
+                        if (i1 > j) n4[(u + 1) & 3] = fma(col[u + 1], col[u + 1], n4[(u + 1) & 3]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < LR; k++) {
+                if (k < lr) {
+                    const int i = 4 * (RR + k) + t;
+                    double x = s_m[k * nth + tid];
+                    x = i > j ? fma(-ws, pv[RR + k], x) : (i == j ? x - w : x);
+                    s_m[k * nth + tid] = x;
+                    if (i > j) n4[k & 3] = fma(x, x, n4[k & 3]);
+                }
+            }
+            const double n = quad_sum((n4[0] + n4[1]) + (n4[2] + n4[3]));
+            if (t == 0) {
+                s_nrm[c] = n;
+                atomicMax(&s_key[(j + 1) & 1], qr_key(n, c));
+            }
+        }
+        __syncthreads();
+    }
+
+    // Outputs from the archive: arc[b * l + i] = raw_b[i] (the archive writes
+    // of the pivot groups are visible after the barriers of the loop)
+    for (int e = tid; e < l * l; e += nth) {
         const int a = e / l, b = e % l;
-        const double sg = W[a * l + a] < 0.0 ? -1.0 : 1.0;
-        P.T[e] = b >= a ? sg * W[e] : 0.0;
+        double tv = 0.0;
+        if (a < b) tv = arc[b * l + a] * (s_beta[a] < 0.0 ? -1.0 : 1.0);
+        else if (a == b) tv = fabs(s_beta[a]);
+        P.T[e] = tv;
         // reflector a, component b
-        P.Qt[e] = b < a ? 0.0 : (b == a ? 1.0 : W[b * l + a]);
+        double vv = 0.0;
+        if (b == a) vv = 1.0;
+        else if (b > a) vv = arc[a * l + b] * s_scale[a];
+        P.Qt[e] = vv;
+    }
+    for (int jj = tid; jj < l; jj += nth) {
+        P.tau[jj] = s_tau[jj];
+        P.tau[LMAX + jj] = s_beta[jj] < 0.0 ? -1.0 : 1.0;
+        P.perm[jj] = s_perm[jj];
     }
 }
 
@@ -866,21 +1110,29 @@ hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
                                   : launch_qrcp_rt<16, 8>(g, lr, s);
         if (e != hipSuccess || lmax <= QRT_LMAX) return e;
     }
-    // l > 128: M in LDS (l <= 136) or in global memory.
-    const size_t lds = sizeof(double) * QRCP_LDS_MAX * QRCP_LDS_MAX;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_qrcp<true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr = true;
+    // 128 < l <= 232: registers and LDS
+    {
+        const int lh = std::min(lmax, QHY_LMAX);
+        const size_t lds = sizeof(double) * (size_t)QHY_LR * (4 * QHY_LMAX);
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_qrcp_hy,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        const int threads = (4 * lh + 63) / 64 * 64;
+        // dynamic LDS for the rows of the largest l of the launch
+        const size_t need = sizeof(double) * (size_t)((lh + 3) / 4 - QHY_RR) * threads;
+        hipLaunchKernelGGL(k_qrcp_hy, dim3(g.blocks), dim3(threads), need, s, g.probs, g.pidx,
+                           g.toff, g.count);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || lmax <= QHY_LMAX) return e;
     }
-    hipLaunchKernelGGL(k_qrcp<true>, dim3(g.blocks), dim3(QR_THREADS), lds, s, g.probs, g.pidx,
-                       g.toff, g.count);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || lmax <= QRCP_LDS_MAX) return e;
-    hipLaunchKernelGGL(k_qrcp<false>, dim3(g.blocks), dim3(QR_THREADS), 0, s, g.probs, g.pidx,
-                       g.toff, g.count);
+    // l > 232: M streamed from the L2-resident work array, 4 lanes per column
+    const int threads = std::min(QST_THREADS, (4 * lmax + 63) / 64 * 64);
+    hipLaunchKernelGGL(k_qrcp_st, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx, g.toff,
+                       g.count);
     return hipGetLastError();
 }
 
