@@ -17,6 +17,13 @@
 // The order in which K is visited does not change a dot product, so each lane
 // reads one 16-byte vector of K from LDS and feeds it to consecutive MFMAs.
 //
+// BF16 A^T X tiles are transposed in registers: a thread loads four
+// consecutive rows of A (8 columns each), byte permutes turn them into eight
+// 4-element K runs, one per column, and 8-byte LDS writes put them into
+// [output row][K] rows of 128 bytes whose 16-byte granules are XOR-swizzled by
+// the row, so that both these writes and the 16-byte MFMA operand reads
+// spread over the banks.
+//
 // Output: FP32 partial sums (FP64 in F64 mode) ypart[split][row][lp]; the
 // splits are added in a fixed order by the reduction kernel, so the result
 // does not depend on scheduling.
@@ -61,6 +68,11 @@ template <int PREC, int NT, bool TRANS>
 __host__ __device__ constexpr int sk_lds_bytes() {
     return 2 * (sk_a_bytes<PREC, NT, TRANS>() + NT * 16 * ROWB);
 }
+
+// Swizzled [output row][K] layout of a transposed BF16 tile: row r holds 64 K
+// (eight 16-byte granules); granule g sits in slot g ^ at_swz(r).
+__device__ __forceinline__ int at_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 7; }
+constexpr int AT_ROWB = 128;
 
 // Sixteen zero bytes in global memory: out-of-range rows of a full tile are
 // loaded from here (an address select, not a branch).  Never written.
@@ -128,6 +140,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
     const int li = lane & 15;
     const int lg = lane >> 4;
     constexpr bool ATRANS_SCALAR = TRANS && (PREC == P_F32 || PREC == P_F64);
+    constexpr bool ATRANS_BF16 = TRANS && PREC == P_BF16;
     constexpr int AROWB = SK_BM * SZ + 16;  // row stride of a transposed F32/F64 tile
 
     // ---------------- global -> register staging ----------------
@@ -139,6 +152,23 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
     constexpr int X_LD = (X_CHUNKS + SK_THREADS - 1) / SK_THREADS;
     i32x4 ra[A_LD];
     i32x4 rx[X_LD];
+    // Chunk t of this thread in a transposed tile: K row a_kr(t), column chunk
+    // a_ch.  BF16: K rows 4 q .. 4 q + 3 per thread (transposed in registers);
+    // the 32 lanes of a half wave take 16 column chunks of two K-row groups,
+    // so that their 8-byte LDS writes pair up in the 16-byte granules.
+    constexpr int CPR = SK_BM * SZ / 16;  // chunks per A row segment (transposed)
+    if constexpr (ATRANS_BF16)
+        static_assert(A_LD == 4 && CPR == 32 && SK_THREADS == 512, "one 256 x 64 tile, 4 K rows per thread");
+    const int bq = ((tid >> 6) << 1) | ((tid >> 4) & 1);    // BF16: K-row group
+    const int bch = (tid & 15) | (((tid >> 5) & 1) << 4);   // BF16: column chunk
+    auto a_kr = [&](int t) {
+        if constexpr (ATRANS_BF16) return 4 * bq + t;
+        else return (tid + t * SK_THREADS) / CPR;
+    };
+    auto a_ch = [&](int t) {
+        if constexpr (ATRANS_BF16) return bch;
+        else return (tid + t * SK_THREADS) % CPR;
+    };
 
     // Full tiles (every K of the tile inside the split, 16-byte aligned rows,
     // and for the transposed pass every output row inside the matrix) load
@@ -159,11 +189,9 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 ra[t] = *(gr < rows ? (gi32x4*)a : z16);
             }
         } else {
-            constexpr int CPR = SK_BM * SZ / 16;  // chunks per A row segment
 #pragma unroll
             for (int t = 0; t < A_LD; t++) {
-                const int c = tid + t * SK_THREADS;
-                const int kr = c / CPR, ch = c % CPR;
+                const int kr = a_kr(t), ch = a_ch(t);
                 const T* a = A + (k0 + kr) * lda + row0 + ch * VEC;
                 ra[t] = *(gi32x4*)a;
             }
@@ -196,11 +224,9 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                     ra[t] = i32x4{0, 0, 0, 0};
             }
         } else {
-            constexpr int CPR = SK_BM * SZ / 16;  // chunks per A row segment
 #pragma unroll
             for (int t = 0; t < A_LD; t++) {
-                int c = tid + t * SK_THREADS;
-                int kr = c / CPR, ch = c % CPR;
+                const int kr = a_kr(t), ch = a_ch(t);
                 int64_t gk = k0 + kr;
                 int64_t gc = row0 + ch * VEC;
                 if (gk < kend && gc < rows)
@@ -232,21 +258,30 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 *reinterpret_cast<i32x4*>(As + r * ROWB + ch * 16) = ra[t];
             }
         } else if constexpr (ATRANS_SCALAR) {
-            constexpr int CPR = SK_BM * SZ / 16;
 #pragma unroll
-            for (int t = 0; t < A_LD; t++) {
-                int c = tid + t * SK_THREADS;
-                int kr = c / CPR, ch = c % CPR;
-                *reinterpret_cast<i32x4*>(As + kr * AROWB + ch * 16) = ra[t];
+            for (int t = 0; t < A_LD; t++)
+                *reinterpret_cast<i32x4*>(As + a_kr(t) * AROWB + a_ch(t) * 16) = ra[t];
+        } else if constexpr (ATRANS_BF16) {
+            // ra[t] = columns 8 ch .. 8 ch + 7 of K row k0 + t (two per dword);
+            // column e becomes the K run k0 .. k0 + 3 of output row 8 ch + e.
+            const int q = bq, ch = bch;
+            const int g = q >> 1;  // 16-byte granule of K row 4 q
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int d = e >> 1;
+                const uint32_t sel = (e & 1) ? 0x07060302u : 0x05040100u;
+                const uint32_t lo = __builtin_amdgcn_perm((uint32_t)ra[1][d], (uint32_t)ra[0][d], sel);
+                const uint32_t hi = __builtin_amdgcn_perm((uint32_t)ra[3][d], (uint32_t)ra[2][d], sel);
+                const int r = ch * 8 + e;
+                *reinterpret_cast<uint2*>(As + r * AT_ROWB + 16 * (g ^ at_swz(r)) + 8 * (q & 1)) =
+                    make_uint2(lo, hi);
             }
         } else {
-            // 1- and 2-byte formats: transpose into [output row][K] so that a
-            // lane's MFMA operand (consecutive K of one row) is one vector.
-            constexpr int CPR = SK_BM * SZ / 16;
+            // FP8: transpose into [output row][K] so that a lane's MFMA
+            // operand (consecutive K of one row) is one vector.
 #pragma unroll
             for (int t = 0; t < A_LD; t++) {
-                int c = tid + t * SK_THREADS;
-                int kr = c / CPR, ch = c % CPR;
+                const int kr = a_kr(t), ch = a_ch(t);
                 union { i32x4 v; T e[VEC]; } u;
                 u.v = ra[t];
 #pragma unroll
@@ -330,8 +365,13 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 const int kk = ss * 32 + lg * 8;
                 bf16x8 av[SK_RT];
 #pragma unroll
-                for (int r = 0; r < SK_RT; r++)
-                    av[r] = *reinterpret_cast<const bf16x8*>(As + (wrow + r * 16 + li) * ROWB + kk * 2);
+                for (int r = 0; r < SK_RT; r++) {
+                    const int orow = wrow + r * 16 + li;
+                    if constexpr (TRANS)
+                        av[r] = *reinterpret_cast<const bf16x8*>(As + orow * AT_ROWB + 16 * ((kk >> 3) ^ at_swz(orow)));
+                    else
+                        av[r] = *reinterpret_cast<const bf16x8*>(As + orow * ROWB + kk * 2);
+                }
 #pragma unroll
                 for (int c = 0; c < NT; c++) {
                     bf16x8 bv = *reinterpret_cast<const bf16x8*>(Xs + (c * 16 + li) * ROWB + kk * 2);
