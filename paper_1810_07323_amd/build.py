@@ -24,9 +24,17 @@ FLAGS = [
 ]
 
 
+# Per-file flags.  k_small.hip: LDS atomics stay plain atomics (the wave-level
+# rewrite loops over the active lanes, slower than the LDS unit's own
+# serialisation for a handful of lanes).
+FILE_FLAGS = {
+    "k_small.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = ["hipcc", "-c", src, "-o", obj] + FLAGS
+    cmd = ["hipcc", "-c", src, "-o", obj] + FLAGS + FILE_FLAGS.get(os.path.basename(src), [])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")

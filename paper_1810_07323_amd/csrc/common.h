@@ -104,6 +104,7 @@ template <> struct PrecT<P_FP8> { typedef uint8_t T; typedef float Acc; static c
 // Global-memory view of a device pointer: loads through it are global (not
 // flat) instructions, which the compiler counts without involving LDS.
 typedef const __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) double gdouble_rw;
 __device__ __forceinline__ gdouble* as_global(const double* p) { return (gdouble*)p; }
 
 __device__ __forceinline__ double wave_sum(double v) {

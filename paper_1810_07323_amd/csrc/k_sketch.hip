@@ -17,12 +17,13 @@
 // The order in which K is visited does not change a dot product, so each lane
 // reads one 16-byte vector of K from LDS and feeds it to consecutive MFMAs.
 //
-// BF16 A^T X tiles are transposed in registers: a thread loads four
-// consecutive rows of A (8 columns each), byte permutes turn them into eight
-// 4-element K runs, one per column, and 8-byte LDS writes put them into
-// [output row][K] rows of 128 bytes whose 16-byte granules are XOR-swizzled by
-// the row, so that both these writes and the 16-byte MFMA operand reads
-// spread over the banks.
+// BF16 and FP8 A^T X tiles are transposed in registers: a thread loads four
+// consecutive rows of A (one 16-byte chunk of each), byte permutes turn them
+// into one 4-element K run per column, and 8-byte (BF16) or 4-byte (FP8) LDS
+// writes put these into [output row][K] rows of 128 bytes whose 16-byte
+// granules are XOR-swizzled by the row, so that both these writes (at most
+// two lanes per bank) and the 16-byte MFMA operand reads (none) spread over
+// the banks.
 //
 // Output: FP32 partial sums (FP64 in F64 mode) ypart[split][row][lp]; the
 // splits are added in a fixed order by the reduction kernel, so the result
@@ -46,9 +47,9 @@ constexpr int SK_RT = 2;                      // row tiles of 16 per wave
 // halves the X tile traffic per byte of A (the X tile is as large as the A
 // tile at l = 220).  Eight waves mean two per SIMD and half the register file
 // each: shapes whose accumulators do not fit that (FP64 beyond 8 column
-// tiles, FP32 beyond 12, FP8 beyond 10, FP8 A X) keep 4 waves.
+// tiles, FP32 beyond 12, FP8 beyond 9, FP8 A X) keep 4 waves.
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_waves() {
-    constexpr int ntmax = PREC == P_F64 ? 8 : PREC == P_F32 ? 12 : PREC == P_FP8 ? 10 : NTMAX;
+    constexpr int ntmax = PREC == P_F64 ? 8 : PREC == P_F32 ? 12 : PREC == P_FP8 ? 9 : NTMAX;
     return (NT <= ntmax && (TRANS || PREC == P_BF16)) ? 8 : 4;
 }
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_threads() { return 64 * sk_waves<PREC, NT, TRANS>(); }
@@ -69,9 +70,11 @@ __host__ __device__ constexpr int sk_lds_bytes() {
     return 2 * (sk_a_bytes<PREC, NT, TRANS>() + NT * 16 * ROWB);
 }
 
-// Swizzled [output row][K] layout of a transposed BF16 tile: row r holds 64 K
-// (eight 16-byte granules); granule g sits in slot g ^ at_swz(r).
-__device__ __forceinline__ int at_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 7; }
+// Swizzled [output row][K] layout of a transposed BF16 / FP8 tile: row r holds
+// 128 bytes of K (eight 16-byte granules); granule g sits in slot
+// g ^ at_swz(r).  SH = 3 for BF16 (a thread's columns are 8 rows apart),
+// 4 for FP8 (16 rows apart).
+template <int SH> __device__ __forceinline__ int at_swz(int r) { return ((r >> 1) ^ (r >> SH)) & 7; }
 constexpr int AT_ROWB = 128;
 
 // Sixteen zero bytes in global memory: out-of-range rows of a full tile are
@@ -141,6 +144,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
     const int lg = lane >> 4;
     constexpr bool ATRANS_SCALAR = TRANS && (PREC == P_F32 || PREC == P_F64);
     constexpr bool ATRANS_BF16 = TRANS && PREC == P_BF16;
+    constexpr bool ATRANS_FP8 = TRANS && PREC == P_FP8;
     constexpr int AROWB = SK_BM * SZ + 16;  // row stride of a transposed F32/F64 tile
 
     // ---------------- global -> register staging ----------------
@@ -153,20 +157,23 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
     i32x4 ra[A_LD];
     i32x4 rx[X_LD];
     // Chunk t of this thread in a transposed tile: K row a_kr(t), column chunk
-    // a_ch.  BF16: K rows 4 q .. 4 q + 3 per thread (transposed in registers);
-    // the 32 lanes of a half wave take 16 column chunks of two K-row groups,
-    // so that their 8-byte LDS writes pair up in the 16-byte granules.
+    // a_ch.  BF16 / FP8: K rows 4 q .. 4 q + 3 per thread (transposed in
+    // registers).  BF16: the 32 lanes of a half wave take 16 column chunks of
+    // two K-row groups, so that their 8-byte LDS writes pair up in the
+    // 16-byte granules.
     constexpr int CPR = SK_BM * SZ / 16;  // chunks per A row segment (transposed)
     if constexpr (ATRANS_BF16)
         static_assert(A_LD == 4 && CPR == 32 && SK_THREADS == 512, "one 256 x 64 tile, 4 K rows per thread");
-    const int bq = ((tid >> 6) << 1) | ((tid >> 4) & 1);    // BF16: K-row group
-    const int bch = (tid & 15) | (((tid >> 5) & 1) << 4);   // BF16: column chunk
+    if constexpr (ATRANS_FP8)
+        static_assert(A_LD == 4 && SK_THREADS / CPR * 4 == BK, "4 K rows per thread");
+    const int bq = ATRANS_BF16 ? ((tid >> 6) << 1) | ((tid >> 4) & 1) : tid / CPR;  // K-row group
+    const int bch = ATRANS_BF16 ? (tid & 15) | (((tid >> 5) & 1) << 4) : tid % CPR;  // column chunk
     auto a_kr = [&](int t) {
-        if constexpr (ATRANS_BF16) return 4 * bq + t;
+        if constexpr (ATRANS_BF16 || ATRANS_FP8) return 4 * bq + t;
         else return (tid + t * SK_THREADS) / CPR;
     };
     auto a_ch = [&](int t) {
-        if constexpr (ATRANS_BF16) return bch;
+        if constexpr (ATRANS_BF16 || ATRANS_FP8) return bch;
         else return (tid + t * SK_THREADS) % CPR;
     };
 
@@ -273,20 +280,29 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 const uint32_t lo = __builtin_amdgcn_perm((uint32_t)ra[1][d], (uint32_t)ra[0][d], sel);
                 const uint32_t hi = __builtin_amdgcn_perm((uint32_t)ra[3][d], (uint32_t)ra[2][d], sel);
                 const int r = ch * 8 + e;
-                *reinterpret_cast<uint2*>(As + r * AT_ROWB + 16 * (g ^ at_swz(r)) + 8 * (q & 1)) =
+                *reinterpret_cast<uint2*>(As + r * AT_ROWB + 16 * (g ^ at_swz<3>(r)) + 8 * (q & 1)) =
                     make_uint2(lo, hi);
             }
         } else {
-            // FP8: transpose into [output row][K] so that a lane's MFMA
-            // operand (consecutive K of one row) is one vector.
+            // FP8: ra[t] = columns 16 ch .. 16 ch + 15 of K row k0 + t; a 4 x 4
+            // byte transpose per dword gives column e the K run k0 .. k0 + 3.
+            const int q = bq, ch = bch;
+            const int g = q >> 2;  // 16-byte granule of K row 4 q
 #pragma unroll
-            for (int t = 0; t < A_LD; t++) {
-                const int kr = a_kr(t), ch = a_ch(t);
-                union { i32x4 v; T e[VEC]; } u;
-                u.v = ra[t];
+            for (int d = 0; d < 4; d++) {
+                const uint32_t x01 = __builtin_amdgcn_perm((uint32_t)ra[1][d], (uint32_t)ra[0][d], 0x05010400u);
+                const uint32_t y01 = __builtin_amdgcn_perm((uint32_t)ra[1][d], (uint32_t)ra[0][d], 0x07030602u);
+                const uint32_t x23 = __builtin_amdgcn_perm((uint32_t)ra[3][d], (uint32_t)ra[2][d], 0x05010400u);
+                const uint32_t y23 = __builtin_amdgcn_perm((uint32_t)ra[3][d], (uint32_t)ra[2][d], 0x07030602u);
+                const uint32_t o[4] = {__builtin_amdgcn_perm(x23, x01, 0x05040100u),
+                                       __builtin_amdgcn_perm(x23, x01, 0x07060302u),
+                                       __builtin_amdgcn_perm(y23, y01, 0x05040100u),
+                                       __builtin_amdgcn_perm(y23, y01, 0x07060302u)};
 #pragma unroll
-                for (int e = 0; e < VEC; e++)
-                    *reinterpret_cast<T*>(As + (ch * VEC + e) * ROWB + kr * SZ) = u.e[e];
+                for (int b = 0; b < 4; b++) {
+                    const int r = ch * 16 + 4 * d + b;
+                    *reinterpret_cast<uint32_t*>(As + r * AT_ROWB + 16 * (g ^ at_swz<4>(r)) + 4 * (q & 3)) = o[b];
+                }
             }
         }
 #pragma unroll
@@ -368,7 +384,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 for (int r = 0; r < SK_RT; r++) {
                     const int orow = wrow + r * 16 + li;
                     if constexpr (TRANS)
-                        av[r] = *reinterpret_cast<const bf16x8*>(As + orow * AT_ROWB + 16 * ((kk >> 3) ^ at_swz(orow)));
+                        av[r] = *reinterpret_cast<const bf16x8*>(As + orow * AT_ROWB + 16 * ((kk >> 3) ^ at_swz<3>(orow)));
                     else
                         av[r] = *reinterpret_cast<const bf16x8*>(As + orow * ROWB + kk * 2);
                 }
@@ -385,9 +401,18 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
             i32x8 av[SK_RT];
 #pragma unroll
             for (int r = 0; r < SK_RT; r++) {
-                const unsigned char* p = As + (wrow + r * 16 + li) * ROWB + kk;
-                i32x4 lo = *reinterpret_cast<const i32x4*>(p);
-                i32x4 hi = *reinterpret_cast<const i32x4*>(p + 16);
+                const int orow = wrow + r * 16 + li;
+                i32x4 lo, hi;
+                if constexpr (TRANS) {
+                    const unsigned char* p = As + orow * AT_ROWB;
+                    const int sw = at_swz<4>(orow);
+                    lo = *reinterpret_cast<const i32x4*>(p + 16 * ((2 * lg) ^ sw));
+                    hi = *reinterpret_cast<const i32x4*>(p + 16 * ((2 * lg + 1) ^ sw));
+                } else {
+                    const unsigned char* p = As + orow * ROWB + kk;
+                    lo = *reinterpret_cast<const i32x4*>(p);
+                    hi = *reinterpret_cast<const i32x4*>(p + 16);
+                }
                 av[r] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
             }
 #pragma unroll

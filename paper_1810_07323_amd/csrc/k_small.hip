@@ -489,7 +489,7 @@ __device__ __forceinline__ double quad_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// QRCP of M = R2^T for l > 232 (one block of up to 1024 threads per problem).
+// QRCP of M = R2^T for l > 224 (one block of up to 1024 threads per problem).
 //   M does not fit the registers of one work-group, so it stays in a global
 //   work array W (l x l, row-major, in P.R, which is free once R2 is formed;
 //   it stays in L2).  Four lanes own a column, lane t the rows i = 4 u + t
@@ -659,10 +659,12 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// QRCP of M = R2^T for 128 < l <= 232: registers and LDS (one block of 4 l
+// QRCP of M = R2^T for 128 < l <= 224: registers and LDS (one block of 4 l
 // threads per problem).  Four lanes own a column, lane t the rows
-// i = 4 u + t; rows u < QHY_RR stay in registers and rows u >= QHY_RR in LDS
-// (u-major, so a wave's lanes touch consecutive words).  Step j as in the
+// i = 4 u + t; rows u < QHY_RR stay in registers and the next LRC rows in LDS
+// (thread-major with an odd stride, so that the row offsets are immediates
+// and 8-byte reads are free of bank conflicts; LRC is the launch's LDS row
+// count rounded up to 4, rows past l are zeros and stay zeros).  Step j as in the
 // register-resident kernel: the pivot group puts its raw column into an LDS
 // buffer laid out [t][u] (16-byte reads) and into a global archive (P.R,
 // column j = raw_j, read only at the end) and forms beta, tau and scale;
@@ -672,15 +674,18 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
 // Register rows above j are skipped in blocks of 16 (uniform branches).
 // ---------------------------------------------------------------------------
 
+template <int LRC>
 __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict__ probs,
                                                         const int32_t* __restrict__ pidx,
                                                         const int32_t* __restrict__ toff,
                                                         int cnt) {
     constexpr int RR = QHY_RR, CH = 4;  // register rows, skipped in blocks of 4 CH rows
     static_assert(RR % CH == 0 && CH % 2 == 0, "register rows in whole blocks of pairs");
-    constexpr int LR = QHY_LR;
+    static_assert(LRC % 4 == 0 && LRC <= QHY_LR, "LDS rows");
+    constexpr int LR = LRC;
+    constexpr int LRP = LRC + 1;  // LDS doubles per thread (odd: conflict-free 8-byte reads)
     constexpr int ST = RR + LR + 2;  // doubles per lane row of the pivot buffer
-    extern __shared__ __align__(16) double s_m[];  // [u - RR][thread]
+    extern __shared__ __align__(16) double s_m[];  // [thread][u - RR]
     __shared__ __align__(16) double s_pv[4 * ST];  // raw pivot column, [t][u]
     __shared__ double s_nrm[QHY_LMAX];
     __shared__ double s_tau[QHY_LMAX], s_scale[QHY_LMAX], s_beta[QHY_LMAX];
@@ -693,10 +698,10 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
     const int tid = threadIdx.x, nth = blockDim.x;
     const int c = tid >> 2, t = tid & 3;
     const bool incol = c < l;
-    const int rpt = (l + 3) >> 2;  // rows per lane
-    const int lr = rpt - RR;       // of them in LDS (1 .. LR)
-    double* __restrict__ arc = P.R;  // archive: column j = raw pivot column of step j
-    const double* __restrict__ R2 = P.R2;
+    // archive: column j = raw pivot column of step j (global address space, so
+    // that its stores do not hold up the LDS waits)
+    gdouble_rw* __restrict__ arc = (gdouble_rw*)P.R;
+    gdouble* __restrict__ R2 = as_global(P.R2);
 
     // rows past l are zero and stay zero (the pivot column is zero there)
     double col[RR];
@@ -710,11 +715,9 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
 #pragma unroll
     for (int k = 0; k < LR; k++) {
         const int i = 4 * (RR + k) + t;
-        if (k < lr) {
-            const double v = (incol && i < l) ? R2[c * l + i] : 0.0;
-            s_m[k * nth + tid] = v;
-            nn = fma(v, v, nn);
-        }
+        const double v = (incol && i < l) ? R2[c * l + i] : 0.0;
+        s_m[tid * LRP + k] = v;
+        nn = fma(v, v, nn);
     }
     nn = quad_sum(nn);
     if (tid < 2) s_key[tid] = 0ull;
@@ -731,21 +734,13 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
         const int p = 511 - (int)(key & 0x1FFull);
         if (c == p) {
             double* pv = s_pv + t * ST;
-            double* ar = arc + j * l;  // archive (read back only at the end)
 #pragma unroll
-            for (int u = 0; u < RR; u += 2) {
+            for (int u = 0; u < RR; u += 2)
                 *reinterpret_cast<double2*>(pv + u) = make_double2(col[u], col[u + 1]);
-                if (4 * u + t < l) ar[4 * u + t] = col[u];
-                if (4 * u + 4 + t < l) ar[4 * u + 4 + t] = col[u + 1];
-            }
 #pragma unroll
             for (int k = 0; k < LR; k++) {
-                const int i = 4 * (RR + k) + t;
-                if (k < lr) {
-                    const double v = s_m[k * nth + tid];
-                    pv[RR + k] = v;
-                    if (i < l) ar[i] = v;
-                }
+                pv[RR + k] = s_m[tid * LRP + k];
+                if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // 4 rows in flight
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -774,9 +769,14 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
             active = false;
         }
         __syncthreads();
+        // archive the raw pivot column (global stores, off the pivot group's path)
+        if (tid < l) arc[j * l + tid] = s_pv[(tid & 3) * ST + (tid >> 2)];
         if (active) {
             const double tau = s_tau[j], scale = s_scale[j];
             const double* pv = s_pv + t * ST;
+            // row i = 4 u + t of this lane is below / at row j iff 4 u > / == jt
+            // (compares against constants: no per-row index registers)
+            const int jt = j - t;
             // w = tau (col_j + scale sum_{i > j} raw_i col_i); only the block
             // that holds row j needs per-element masks
             double d4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -788,24 +788,30 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
 #pragma unroll
                 for (int u = q * CH; u < q * CH + CH; u += 2) {
                     const double2 r = *reinterpret_cast<const double2*>(pv + u);
-                    const int i0 = 4 * u + t, i1 = i0 + 4;
                     if (lo > j) {
                         d4[u & 3] = fma(r.x, col[u], d4[u & 3]);
                         d4[(u + 1) & 3] = fma(r.y, col[u + 1], d4[(u + 1) & 3]);
                     } else {
-                        d4[u & 3] = fma(i0 > j ? r.x : 0.0, col[u], d4[u & 3]);
-                        d4[(u + 1) & 3] = fma(i1 > j ? r.y : 0.0, col[u + 1], d4[(u + 1) & 3]);
-                        cj = i0 == j ? col[u] : (i1 == j ? col[u + 1] : cj);
+                        d4[u & 3] = fma(4 * u > jt ? r.x : 0.0, col[u], d4[u & 3]);
+                        d4[(u + 1) & 3] = fma(4 * u + 4 > jt ? r.y : 0.0, col[u + 1], d4[(u + 1) & 3]);
+                        cj = 4 * u == jt ? col[u] : (4 * u + 4 == jt ? col[u + 1] : cj);
                     }
                 }
             }
 #pragma unroll
-            for (int k = 0; k < LR; k++) {
-                if (k < lr) {
-                    const int i = 4 * (RR + k) + t;
-                    const double x = s_m[k * nth + tid];
-                    d4[k & 3] = fma(i > j ? pv[RR + k] : 0.0, x, d4[k & 3]);
-                    cj = i == j ? x : cj;
+            for (int q = 0; q < LR / 4; q++) {  // LDS rows in blocks of 16
+                const int lo = 4 * (RR + 4 * q), hi = lo + 15;
+                if (hi < j) continue;
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++) {
+                    const int k = 4 * q + kk, i4 = 4 * (RR + k);
+                    const double x = s_m[tid * LRP + k];
+                    if (lo > j) {
+                        d4[kk] = fma(pv[RR + k], x, d4[kk]);
+                    } else {
+                        d4[kk] = fma(i4 > jt ? pv[RR + k] : 0.0, x, d4[kk]);
+                        cj = i4 == jt ? x : cj;
+                    }
                 }
             }
             const double w = tau * quad_sum(fma(scale, (d4[0] + d4[1]) + (d4[2] + d4[3]), cj));
@@ -819,28 +825,36 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
 #pragma unroll
                 for (int u = q * CH; u < q * CH + CH; u += 2) {
                     const double2 r = *reinterpret_cast<const double2*>(pv + u);
-                    const int i0 = 4 * u + t, i1 = i0 + 4;
                     if (lo > j) {
                         col[u] = fma(-ws, r.x, col[u]);
                         col[u + 1] = fma(-ws, r.y, col[u + 1]);
                         n4[u & 3] = fma(col[u], col[u], n4[u & 3]);
                         n4[(u + 1) & 3] = fma(col[u + 1], col[u + 1], n4[(u + 1) & 3]);
                     } else {
-                        col[u] = i0 > j ? fma(-ws, r.x, col[u]) : (i0 == j ? col[u] - w : col[u]);
-                        col[u + 1] = i1 > j ? fma(-ws, r.y, col[u + 1]) : (i1 == j ? col[u + 1] - w : col[u + 1]);
-                        if (i0 > j) n4[u & 3] = fma(col[u], col[u], n4[u & 3]);
-                        if (i1 > j) n4[(u + 1) & 3] = fma(col[u + 1], col[u + 1], n4[(u + 1) & 3]);
+                        const int i0 = 4 * u, i1 = i0 + 4;
+                        col[u] = i0 > jt ? fma(-ws, r.x, col[u]) : (i0 == jt ? col[u] - w : col[u]);
+                        col[u + 1] = i1 > jt ? fma(-ws, r.y, col[u + 1]) : (i1 == jt ? col[u + 1] - w : col[u + 1]);
+                        if (i0 > jt) n4[u & 3] = fma(col[u], col[u], n4[u & 3]);
+                        if (i1 > jt) n4[(u + 1) & 3] = fma(col[u + 1], col[u + 1], n4[(u + 1) & 3]);
                     }
                 }
             }
 #pragma unroll
-            for (int k = 0; k < LR; k++) {
-                if (k < lr) {
-                    const int i = 4 * (RR + k) + t;
-                    double x = s_m[k * nth + tid];
-                    x = i > j ? fma(-ws, pv[RR + k], x) : (i == j ? x - w : x);
-                    s_m[k * nth + tid] = x;
-                    if (i > j) n4[k & 3] = fma(x, x, n4[k & 3]);
+            for (int q = 0; q < LR / 4; q++) {
+                const int lo = 4 * (RR + 4 * q), hi = lo + 15;
+                if (hi < j) continue;
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++) {
+                    const int k = 4 * q + kk, i4 = 4 * (RR + k);
+                    double x = s_m[tid * LRP + k];
+                    if (lo > j) {
+                        x = fma(-ws, pv[RR + k], x);
+                        n4[kk] = fma(x, x, n4[kk]);
+                    } else {
+                        x = i4 > jt ? fma(-ws, pv[RR + k], x) : (i4 == jt ? x - w : x);
+                        if (i4 > jt) n4[kk] = fma(x, x, n4[kk]);
+                    }
+                    s_m[tid * LRP + k] = x;
                 }
             }
             const double n = quad_sum((n4[0] + n4[1]) + (n4[2] + n4[3]));
@@ -1100,6 +1114,24 @@ static hipError_t launch_qrcp_rt(const LaunchGroup& g, int lmax, hipStream_t s) 
     return hipGetLastError();
 }
 
+template <int LRC>
+static hipError_t launch_qrcp_hy(const LaunchGroup& g, int lh, hipStream_t s) {
+    const int threads = (4 * lh + 63) / 64 * 64;
+    constexpr int LRP = LRC ? LRC + 1 : 0;
+    const size_t lds = sizeof(double) * (size_t)LRP * threads;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_qrcp_hy<LRC>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(sizeof(double) * LRP * 4 * QHY_LMAX));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_qrcp_hy<LRC>, dim3(g.blocks), dim3(threads), lds, s, g.probs, g.pidx,
+                       g.toff, g.count);
+    return hipGetLastError();
+}
+
 hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
     {
@@ -1110,26 +1142,20 @@ hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
                                   : launch_qrcp_rt<16, 8>(g, lr, s);
         if (e != hipSuccess || lmax <= QRT_LMAX) return e;
     }
-    // 128 < l <= 232: registers and LDS
+    // 128 < l <= 224: registers and LDS
     {
         const int lh = std::min(lmax, QHY_LMAX);
-        const size_t lds = sizeof(double) * (size_t)QHY_LR * (4 * QHY_LMAX);
-        static bool attr = false;
-        if (!attr) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_qrcp_hy,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            attr = true;
-        }
-        const int threads = (4 * lh + 63) / 64 * 64;
-        // dynamic LDS for the rows of the largest l of the launch
-        const size_t need = sizeof(double) * (size_t)((lh + 3) / 4 - QHY_RR) * threads;
-        hipLaunchKernelGGL(k_qrcp_hy, dim3(g.blocks), dim3(threads), need, s, g.probs, g.pidx,
-                           g.toff, g.count);
-        hipError_t e = hipGetLastError();
+        // LDS rows per lane for the largest l of the launch, rounded up to 4
+        const int lrc = std::max(0, ((lh + 3) / 4 - QHY_RR + 3) / 4 * 4);
+        hipError_t e = lrc == 0    ? launch_qrcp_hy<0>(g, lh, s)
+                       : lrc == 4  ? launch_qrcp_hy<4>(g, lh, s)
+                       : lrc == 8  ? launch_qrcp_hy<8>(g, lh, s)
+                       : lrc == 12 ? launch_qrcp_hy<12>(g, lh, s)
+                       : lrc == 16 ? launch_qrcp_hy<16>(g, lh, s)
+                                   : launch_qrcp_hy<20>(g, lh, s);
         if (e != hipSuccess || lmax <= QHY_LMAX) return e;
     }
-    // l > 232: M streamed from the L2-resident work array, 4 lanes per column
+    // l > 224: M streamed from the L2-resident work array, 4 lanes per column
     const int threads = std::min(QST_THREADS, (4 * lmax + 63) / 64 * 64);
     hipLaunchKernelGGL(k_qrcp_st, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx, g.toff,
                        g.count);

@@ -106,6 +106,30 @@ def test_f64_ragged_shapes(cu, dev, orc, m, n, k, p, q, lda_pad):
     assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
 
 
+@pytest.mark.parametrize("l", [130, 150, 170, 185, 200, 224, 240])
+def test_f64_core_qrcp_sizes(cu, dev, orc, l):
+    """l x l core QRCP beyond 128 columns: every LDS row count of the
+    register + LDS kernel (l = 130 .. 224) and the streaming kernel (l = 240)."""
+    import torch
+
+    m, n = 560, 500
+    a, _ = I.lowrank(m, n, np.exp(-np.arange(1, n + 1) / 60.0), seed=l)
+    k, p, q = l - 10, 10, 0
+    om = I.gaussian_omega(n, l, 3)
+    gpu = _run_gpu(cu, dev, torch.from_numpy(a).to(dev), k, p, q, om)
+    mg, mo, ref = _compare_f64(orc, a, k, p, q, om, gpu, f"core l={l}")
+    U, T, V, perm, info = gpu
+    assert abs(mg["err_l"] - mo["err_l"]) <= 1e-12
+    assert abs(mg["err_k"] - mo["err_k"]) <= 1e-12
+    assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
+    assert np.array_equal(np.tril(T, -1), np.zeros_like(T))
+    # |T_ii| is fixed by the pivot order; compare it where the pivots are unique
+    if ref["diag"][1] > 1e-8:
+        assert np.array_equal(perm, ref["perm"])
+        d = np.abs(np.diag(ref["T"]))
+        assert np.abs(np.diag(T) - d).max() <= 1e-10 * d.max()
+
+
 def test_f32_scaled_config2(cu, dev, orc):
     """The FP32 workload's recipe (rank-r Haar, sigma_i = exp(-i/40), k=100,
     p=10, q=2) at 1500x1500 with rank 200 so the oracle finishes in seconds."""
