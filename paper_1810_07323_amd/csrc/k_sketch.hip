@@ -183,7 +183,10 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
     // zero block.  Straight-line loads let the compiler keep them all in
     // flight while the previous tile's MFMAs run.  Other tiles take the
     // element-wise path below.
-    const bool rows_full = !TRANS || row0 + SK_BM <= rows;
+    // A transposed tile whose 16-byte chunks are each wholly inside or wholly
+    // past the last output row also takes the full path (chunks past it read
+    // the zero block), so the last row block is not slower than the others.
+    const bool rows_full = !TRANS || row0 + SK_BM <= rows || rows % VEC == 0;
     auto load_tile_full = [&](int64_t k0) {
         gi32x4* z16 = (gi32x4*)g_zero16;
         if constexpr (!TRANS) {
@@ -199,8 +202,9 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
 #pragma unroll
             for (int t = 0; t < A_LD; t++) {
                 const int kr = a_kr(t), ch = a_ch(t);
-                const T* a = A + (k0 + kr) * lda + row0 + ch * VEC;
-                ra[t] = *(gi32x4*)a;
+                const int64_t gc = row0 + ch * VEC;
+                const T* a = A + (k0 + kr) * lda + min(gc, rows - VEC);
+                ra[t] = *(gc < rows ? (gi32x4*)a : z16);
             }
         }
 #pragma unroll
