@@ -235,20 +235,20 @@ hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Gram partial sums G_b = Z_b^T Z_b of a row chunk Z_b of an FP64 rows x l
-// matrix, on FP64 MFMA 16x16x4.  A block is (row chunk, group of four upper
-// 16x16 tiles); each wave owns one tile and streams the chunk's rows from
-// memory straight into MFMA operands (16 lanes read 128 contiguous bytes of
-// a row), eight K steps per batch with the next batch's loads in flight, so
-// the kernel has no LDS staging and no barrier.  Partials: gpart[chunk][l][l],
-// upper tiles only (every entry with a <= b is written).
+// matrix, on FP64 MFMA 16x16x4.  A block is (row chunk, one upper 16x16
+// tile); its four waves take consecutive quarters of the chunk's rows and
+// stream them from memory straight into MFMA operands (16 lanes read 128
+// contiguous bytes of a row), eight K steps per batch with the next batch's
+// loads in flight; the four partial tiles are added in LDS in wave order (a
+// fixed summation order).  Partials: gpart[chunk][l][l], upper tiles only
+// (every entry with a <= b is written).  The grid is chunks x tiles blocks.
 // ---------------------------------------------------------------------------
 // A zero in global memory: operands outside a matrix are loaded from here (an
 // address select instead of a branch or a mask on the loaded value).  Never
 // written.
 __device__ double g_zero_word[2] = {0.0, 0.0};
 
-constexpr int GT_PER_BLOCK = GRAM_TILES_PER_BLOCK;
-static_assert(GT_PER_BLOCK == 4, "one Gram tile per wave");
+static_assert(GRAM_THREADS == 256, "four waves per Gram tile");
 
 __device__ __forceinline__ void tile_of(int t, int nt, int& ta, int& tb) {
     // t-th upper tile (ta <= tb) in row-major order over ta.
@@ -263,6 +263,7 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
                                                       const int32_t* __restrict__ pidx,
                                                       const int32_t* __restrict__ toff, int cnt,
                                                       int side, int iter) {
+    __shared__ double part[3][4][64];
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter >= 0 && iter > P.q) return;
@@ -270,34 +271,44 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     const int l = P.l, lp = P.lp;
     const int nt = lp / 16;
     const int ntu = nt * (nt + 1) / 2;
-    const int ngroups = (ntu + GT_PER_BLOCK - 1) / GT_PER_BLOCK;
-    const int chunk = local / ngroups;
-    const int grp = local - chunk * ngroups;
+    const int gb = side == SIDE_M ? P.gb_m : P.gb_n;
+    // Blocks are handed to the eight XCDs in turn (block b to XCD b mod 8),
+    // each with its own L2: with a multiple of 8 chunks, chunk c's tiles all
+    // go to blocks b = c (mod 8), so every row of Z is fetched into one L2.
+    int chunk, tt;
+    if (gb % 8 == 0) {
+        const int i = local >> 3;
+        chunk = (local & 7) + 8 * (i / ntu);
+        tt = i - (i / ntu) * ntu;
+    } else {
+        chunk = local / ntu;
+        tt = local - chunk * ntu;
+    }
     const int64_t rows = side == SIDE_M ? P.m : P.n;
     const int rb = side == SIDE_M ? P.rb_m : P.rb_n;
-    const int64_t r0 = (int64_t)chunk * rb;
-    const int64_t r1 = min(rows, r0 + rb);
+    const int64_t c0 = (int64_t)chunk * rb;
+    const int64_t c1 = min(rows, c0 + rb);
     const double* __restrict__ Z = SRC == GSRC_Y ? P.Y : SRC == GSRC_QA ? P.Qa : SRC == GSRC_U ? P.U : P.V;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int tt = grp * GT_PER_BLOCK + wave;
-    if (tt >= ntu) return;  // no barrier below: idle waves may leave
+    // rows of this wave: quarter `wave` of the chunk (whole K steps of 4 rows)
+    const int64_t qr = (((c1 - c0) + 3) / 4 + 3) / 4 * 4;
+    const int64_t r0 = c0 + wave * qr;
+    const int64_t r1 = min(c1, r0 + qr);
     int ta, tb;
     tile_of(tt, nt, ta, tb);
     const int ca = 16 * ta + li, cb = 16 * tb + li;
-    const bool oka = ca < l, okb = cb < l;
+    const bool okb = cb < l;
     // MFMA K slot g of step s is row rs + 4 s + g; U steps per batch, the next
     // batch's loads in flight while this batch's MFMAs run.
     constexpr int U = 8;
     f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
     double xa[U], xb[U], ya[U], yb[U];
-    // Loads are unconditional (clamped addresses, masked values): straight-line
-    // code lets the compiler wait for one batch while the next is in flight.
-    // Columns past l are read at column l - 1 (their tile entries are never
-    // written); rows past the chunk are read from a zero word.  The loads are
-    // unconditional, so straight-line code waits for one batch while the next
-    // is in flight.
+    // Loads are unconditional: columns past l are read at column l - 1 (their
+    // tile entries are never written); rows past the wave's range are read
+    // from a zero word.  Straight-line code lets the compiler wait for the
+    // older batch while the newer one is in flight.
     const int cac = min(ca, l - 1), cbc = min(cb, l - 1);
     gdouble* Zg = as_global(Z);
     gdouble* zw = as_global(g_zero_word);
@@ -311,9 +322,6 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
             vb[u] = *(okr ? zr + cbc : zw);
         }
     };
-    // Two register buffers in turn, every prefetch unconditional (rows past
-    // the chunk read the zero word): the compiler then waits exactly for the
-    // older batch while the newer one is in flight.
     load(r0, xa, xb);
     for (int64_t rs = r0; rs < r1; rs += 8 * U) {
         load(rs + 4 * U, ya, yb);
@@ -323,11 +331,17 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
 #pragma unroll
         for (int u = 0; u < U; u++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[u], yb[u], acc, 0, 0, 0);
     }
+    if (wave > 0)
+#pragma unroll
+        for (int e = 0; e < 4; e++) part[wave - 1][e][lane] = acc[e];
+    __syncthreads();
+    if (wave != 0) return;
     double* out = P.gpart + (int64_t)chunk * l * l;
 #pragma unroll
     for (int e = 0; e < 4; e++) {
+        const double v = ((acc[e] + part[0][e][lane]) + part[1][e][lane]) + part[2][e][lane];
         const int ga = 16 * ta + lg + 4 * e;  // f64 MFMA output row
-        if (ga < l && okb) out[(int64_t)ga * l + cb] = acc[e];
+        if (ga < l && okb) out[(int64_t)ga * l + cb] = v;
     }
 }
 
@@ -398,31 +412,34 @@ hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int it
 }
 
 // ---------------------------------------------------------------------------
-// dst = src S for a block of AP_ROWS = 32 rows, S = R^{-1} (l x l, FP64) of a
-// CholeskyQR pass, on the FP64 MFMA (16x16x4).  Wave w owns row tile w & 1
-// and half w >> 1 of the column tiles.  Lane group g of a wave takes the K
+// dst = src S for a block of AP_ROWS = 16 rows, S = R^{-1} (l x l, FP64) of a
+// CholeskyQR pass, on the FP64 MFMA (16x16x4).  Wave w owns quarter w of the
+// column tiles (two waves per SIMD at a resident set of blocks, so one wave's
+// load latency hides behind the other's MFMAs).  Lane group g of a wave takes the K
 // slots g KQ + s (KQ = lp / 4, s < KQ): both operands stream from memory into
 // registers (S is small and stays in cache), four K steps per batch with the
-// next batch's loads in flight.  The finished 32 x l tile goes through LDS so
+// next batch's loads in flight.  The finished 16 x l tile goes through LDS so
 // that dst (row-major) and the transposed operand copy in the pass format
 // are both written with contiguous runs.  H = column tiles per half (compile
-// time bound of the accumulator array).
+// time bound of the accumulator array, column tiles per quarter).
 // The stage (source, destination) is a template parameter: a run-time switch
 // over these pointers was mis-compiled by the gfx950 backend (the default
 // branch kept the source of another case).
 // ---------------------------------------------------------------------------
-constexpr int AP_ROWS = 32;
+constexpr int AP_ROWS = APPLY_ROWS;
+static_assert(AP_ROWS == 16, "16-row blocks");
 
 template <typename T>
 __device__ void write_op_rows(const Prob& P, int side, int64_t r0, int nrows, const double* xs,
                               int ldx) {
-    // op[c][r0 + rr] for c < l, rr < nrows: two columns per wave pass, lane & 31 = row
+    // op[c][r0 + rr] for c < l, rr < nrows: four columns per wave pass, lane & 15 = row
+    static_assert(AP_ROWS == 16, "one row per lane of a 16-lane group");
     const int l = P.l;
     T* op = reinterpret_cast<T*>(side == SIDE_M ? P.qop : P.xop);
     const int64_t ld = side == SIDE_M ? P.ldq : P.ldx;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rr = lane & 31;
-    for (int c = 2 * wave + (lane >> 5); c < l; c += 8)
+    const int rr = lane & 15;
+    for (int c = 4 * wave + (lane >> 4); c < l; c += 16)
         if (rr < nrows) op[(int64_t)c * ld + r0 + rr] = conv_op<T>(xs[rr * ldx + c], 1.0f);
 }
 
@@ -431,7 +448,7 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
                                                const int32_t* __restrict__ pidx,
                                                const int32_t* __restrict__ toff, int cnt,
                                                int side, int iter) {
-    extern __shared__ __align__(16) double lds[];  // 32 x lp output tile
+    extern __shared__ __align__(16) double lds[];  // 16 x lp output tile
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter >= 0 && iter > P.q) return;
@@ -439,7 +456,7 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
     if (MODE == AP_QA_RINV_Q && !two) return;
     const int l = P.l, lp = P.lp;
     const int nt = lp / 16;
-    const int hn = (nt + 1) / 2;  // column tiles per half
+    const int qn = (nt + 3) / 4;  // column tiles per quarter
     const int kq = lp / 4;        // K steps
     const int64_t rows = side == SIDE_M ? P.m : P.n;
     const int64_t r0 = (int64_t)local * AP_ROWS;
@@ -453,10 +470,9 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int rt = wave & 1, half = wave >> 1;
-    const int ct0 = half * hn;
-    const int nct = min(hn, nt - ct0);  // column tiles of this wave
-    const int64_t arow = r0 + 16 * rt + li;  // row of src this lane feeds
+    const int ct0 = wave * qn;
+    const int nct = min(qn, nt - ct0);  // column tiles of this wave (may be <= 0)
+    const int64_t arow = r0 + li;  // row of src this lane feeds
     const bool arow_ok = arow < rows;
     const double* __restrict__ arp = src + min(arow, rows - 1) * l;  // clamped: loads are unconditional
     const int kbase = lg * kq;
@@ -494,7 +510,7 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
     // l or past the group's kq read the zero word): the compiler then waits
     // exactly for the older batch while the newer one is in flight.
     load(0, a0, b0);
-    for (int s0 = 0; s0 < kq; s0 += 2 * U) {
+    for (int s0 = 0; s0 < (nct > 0 ? kq : 0); s0 += 2 * U) {
         load(s0 + U, a1, b1);
 #pragma unroll
         for (int u = 0; u < U; u++)
@@ -509,13 +525,13 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u][t], acc[t], 0, 0, 0);
     }
     // f64 MFMA output: lane (i, g), entry e -> row g + 4e, column i of the tile.
-    double* xs = lds;  // 32 x lp
+    double* xs = lds;  // 16 x lp
 #pragma unroll
     for (int t = 0; t < H; t++)
         if (t < nct)
 #pragma unroll
             for (int e = 0; e < 4; e++)
-                xs[(16 * rt + lg + 4 * e) * lp + 16 * (ct0 + t) + li] = acc[t][e];
+                xs[(lg + 4 * e) * lp + 16 * (ct0 + t) + li] = acc[t][e];
     __syncthreads();
     for (int r = wave; r < nrows; r += 4)
         for (int c = lane; c < l; c += 64) dst[(r0 + r) * l + c] = xs[r * lp + c];
@@ -542,12 +558,11 @@ template <int MODE>
 static hipError_t launch_apply_m(const LaunchGroup& g, int side, int lmax, int iter,
                                  hipStream_t s) {
     const int nt = (lmax + 15) / 16;
-    const int hn = (nt + 1) / 2;
-    if (hn <= 1) return launch_apply_t<MODE, 1>(g, side, lmax, iter, s);
-    if (hn <= 2) return launch_apply_t<MODE, 2>(g, side, lmax, iter, s);
-    if (hn <= 4) return launch_apply_t<MODE, 4>(g, side, lmax, iter, s);
-    if (hn <= 6) return launch_apply_t<MODE, 6>(g, side, lmax, iter, s);
-    return launch_apply_t<MODE, 9>(g, side, lmax, iter, s);
+    const int qn = (nt + 3) / 4;
+    if (qn <= 1) return launch_apply_t<MODE, 1>(g, side, lmax, iter, s);
+    if (qn <= 2) return launch_apply_t<MODE, 2>(g, side, lmax, iter, s);
+    if (qn <= 3) return launch_apply_t<MODE, 3>(g, side, lmax, iter, s);
+    return launch_apply_t<MODE, 5>(g, side, lmax, iter, s);
 }
 
 hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int iter,

@@ -123,8 +123,13 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
     const int64_t rows = TRANS ? P.n : P.m;    // output rows
     const int64_t K = TRANS ? P.m : P.n;       // contraction length
     const int nrb = (int)((rows + SK_BM - 1) / SK_BM);
-    const int rb = local % nrb;
-    const int split = local / nrb;
+    // Blocks go to the eight XCDs in turn (block b to XCD b mod 8), each with
+    // its own L2.  With 8 K splits, split = b mod 8: the blocks of an XCD all
+    // read the same slice of the skinny operand, which is then fetched into
+    // one L2 instead of all eight.
+    const int nsplit = TRANS ? P.s_atx : P.s_ax;
+    const int rb = nsplit == 8 ? local >> 3 : local % nrb;
+    const int split = nsplit == 8 ? local & 7 : local / nrb;
     const int64_t kc = TRANS ? P.kc_atx : P.kc_ax;
     const int64_t kbeg = (int64_t)split * kc;
     const int64_t kend = min(K, kbeg + kc);

@@ -33,13 +33,13 @@ hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s); 
 // Gram partial sums of a row-major rows x l FP64 matrix picked by `src`.
 enum GramSrc : int32_t { GSRC_Y = 0, GSRC_QA = 1, GSRC_U = 2, GSRC_V = 3 };
 constexpr int GRAM_THREADS = 256;
-// Upper 16 x 16 tiles of the l x l Gram matrix per block (one per wave); a
-// launch covers (row chunks) x ceil(tiles / GRAM_TILES_PER_BLOCK) blocks.
-constexpr int GRAM_TILES_PER_BLOCK = 4;
+// One upper 16 x 16 tile of the l x l Gram matrix per block (four waves
+// split the chunk's rows); a launch covers (row chunks) x (upper tiles) blocks.
 hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStream_t s);
 hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int iter,
                               hipStream_t s);
-// dst = src R^{-1}, row blocks of 32; lmax = largest l of the group.
+// dst = src R^{-1}, row blocks of APPLY_ROWS; lmax = largest l of the group.
+constexpr int APPLY_ROWS = 16;
 enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2 };
 hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int iter,
                         hipStream_t s);

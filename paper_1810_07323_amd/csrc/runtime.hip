@@ -118,18 +118,21 @@ static void split_k(int64_t rows, int64_t K, int bk, int target, int prec, int n
     *s = (int32_t)cdiv(K, c);
 }
 
-static int gram_groups(int lp) {
+static int gram_groups(int lp) {  // blocks per row chunk: the upper 16 x 16 tiles
     const int nt = lp / 16;
-    return (nt * (nt + 1) / 2 + GRAM_TILES_PER_BLOCK - 1) / GRAM_TILES_PER_BLOCK;
+    return nt * (nt + 1) / 2;
 }
 
 static void gram_chunks(int64_t rows, int lp, int target, int32_t* rb, int32_t* gb) {
     // Row chunks of the Gram partial sums: about `target` blocks per problem
     // (chunks x tile groups), at least 64 rows per chunk.  Fewer chunks mean
     // fewer l x l partials to write and reduce.
+    // A multiple of 8 chunks where there are 8 or more lets the Gram kernel
+    // keep each chunk's blocks on one XCD (one L2).
     const int ngroups = gram_groups(lp);
     int64_t g = std::max<int64_t>(1, cdiv(target, ngroups));
     g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(rows, 64)));
+    if (g >= 8) g = g / 8 * 8;
     int64_t r = roundup(cdiv(rows, g), 4);
     *rb = (int32_t)r;
     *gb = (int32_t)cdiv(rows, r);
@@ -280,7 +283,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->report = opts ? opts->report : 0;
     P->reqs.assign(probs, probs + count);
     const int sk_target = sketch_block_target();
-    const int gr_target = 256;
+    const int gr_target = 1024;
     size_t ws = 0;
     std::vector<size_t> base(count);
     for (int i = 0; i < count; i++) {
@@ -319,8 +322,8 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     auto R_gramN = per([&](int i) { return (int64_t)P->lay[i].gb_n * gram_groups(P->lay[i].lp); });
     auto R_red = per([&](int i) { return cdiv((int64_t)P->lay[i].l * P->lay[i].l, 64); });
     auto R_small = per([&](int) { return (int64_t)1; });
-    auto R_applyM = per([&](int i) { return cdiv(probs[i].m, 32); });
-    auto R_applyN = per([&](int i) { return cdiv(probs[i].n, 32); });
+    auto R_applyM = per([&](int i) { return cdiv(probs[i].m, APPLY_ROWS); });
+    auto R_applyN = per([&](int i) { return cdiv(probs[i].n, APPLY_ROWS); });
     auto R_vg = per([&](int i) { return cdiv(probs[i].n * P->lay[i].l, 256); });
     auto R_r2 = per([&](int i) { return (int64_t)P->lay[i].nt * P->lay[i].nt; });
     auto R_norm = per([&](int) { return (int64_t)64; });
@@ -634,7 +637,7 @@ int plan_report(const Plan* P) { return P->report; }
 size_t plan_bytes(const Plan* P) { return P->mem_bytes; }
 
 size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec) {
-    Layout L = make_layout(m, n, l, prec, sketch_block_target(), 256);
+    Layout L = make_layout(m, n, l, prec, sketch_block_target(), 1024);
     return L.total + 256 + 1024;
 }
 
