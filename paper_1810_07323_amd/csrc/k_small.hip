@@ -254,19 +254,39 @@ __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
     // padding rows: a pivot above the clamp threshold, nothing to eliminate
     const double padv = fmax(1.0, 2.0 * tol);
 
+    // Tiles of the waves.  Wave t < Tn holds diagonal tile t in slot 0.  When
+    // the other waves can hold every off-diagonal tile outside tile row 0,
+    // wave t also holds only tile (0, t), which is idle from block 3 on; the
+    // wave that factors the next 4 x 4 block then updates no other tile in
+    // that step.  Otherwise the off-diagonal tiles go round robin.
+    const bool owners_free = Tn <= 7 && (Tn - 1) * (Tn - 1) <= CH_SLOTS * (W - Tn);
     int tp[CH_SLOTS], tq[CH_SLOTS];
     f64x4 x[CH_SLOTS];
 #pragma unroll
     for (int s = 0; s < CH_SLOTS; s++) {
-        const int u = wave + s * W;
         int P = -1, Q = -1;
-        if (u < Tn) {
-            P = Q = u;
-        } else if (u - Tn < Tn * (Tn - 1)) {
-            const int t = u - Tn;
-            P = t / (Tn - 1);
-            const int c = t - P * (Tn - 1);
-            Q = c < P ? c : c + 1;
+        if (owners_free) {
+            if (wave < Tn) {
+                if (s == 0) P = Q = wave;
+                else if (s == 1 && wave > 0) { P = 0; Q = wave; }
+            } else {
+                const int t = (wave - Tn) + s * (W - Tn);  // rows 1 .. Tn-1, Q != P
+                if (t < (Tn - 1) * (Tn - 1)) {
+                    P = 1 + t / (Tn - 1);
+                    const int c = t - (P - 1) * (Tn - 1);
+                    Q = c < P ? c : c + 1;
+                }
+            }
+        } else {
+            const int u = wave + s * W;
+            if (u < Tn) {
+                P = Q = u;
+            } else if (u - Tn < Tn * (Tn - 1)) {
+                const int t = u - Tn;
+                P = t / (Tn - 1);
+                const int c = t - P * (Tn - 1);
+                Q = c < P ? c : c + 1;
+            }
         }
         tp[s] = P;
         tq[s] = Q;
@@ -307,56 +327,147 @@ __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
     }
 }
 
-// C = alpha op(A) op(B) + beta C for the small blocks of the large-l
-// Cholesky (M, N, K <= 136), on FP64 MFMA 16x16x4: the waves of the work-group
-// take the 16 x 16 output tiles in turn; operands are read from (cache
-// resident) global memory, zero outside the matrices.  op(A)[i][k] is
-// A[k * lda + i] when ta, else A[i * lda + k]; likewise op(B) with tb.
-__device__ void blk_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
-                         bool ta, const double* __restrict__ B, int ldb, bool tb, double beta,
-                         double* __restrict__ C, int ldc) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+// Large l (> 128): the Cholesky runs as a sequence of launches.  Diagonal
+// block k (at most 128 wide) is factored by one work-group per problem
+// (k_chol_rt, stage k); the block products between the factors run on many
+// work-groups, one 16 x 16 output tile each (k_chol_gemm):
+//   ROW k : R_kj = (R^{-1}_kk)^T G_kj                  (block row of R)
+//   TR  k : G_jj -= R_kj^T R_kj, upper tiles only      (trailing update)
+//   TM j,i: Tm = sum_{i<m<=j} R_im R^{-1}_mj
+//   RI j,i: R^{-1}_ij = -R^{-1}_ii Tm                  (i = j-1 .. 0)
+// Problems of the launch that have no such step return at once.
+enum CholGemm : int32_t { CG_ROW = 0, CG_TR = 1, CG_TM = 2, CG_RI = 3 };
+constexpr int CG_TILES = 128;  // work-groups per problem (>= the tiles of any product, l <= 264)
+
+__device__ __forceinline__ void chol_blocks(int l, int& nb, int& bs) {
+    nb = (l + CRT_LMAX - 1) / CRT_LMAX;
+    bs = ((l + nb - 1) / nb + 3) / 4 * 4;
+}
+
+__device__ double g_zero_chol[2] = {0.0, 0.0};
+
+// One 16 x 16 tile of C = alpha op(A) op(B) + beta C (op(A)[i][k] is
+// A[k lda + i] when ta, else A[i lda + k]; likewise op(B)); the four waves
+// take every fourth K step of 4 and their partial tiles are added in LDS in
+// wave order.  Loads are unconditional (an address select: operands outside
+// the matrices come from a zero word).
+__device__ __forceinline__ void gemm_tile(int ti, int tj, int M, int N, int K, double alpha,
+                                          const double* __restrict__ A, int lda, bool ta,
+                                          const double* __restrict__ B, int ldb, bool tb,
+                                          double beta, double* __restrict__ C, int ldc) {
+    __shared__ double part[3][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int mt = (M + 15) / 16, ntl = (N + 15) / 16;
-    for (int tile = wave; tile < mt * ntl; tile += nw) {
-        const int ti = tile / ntl, tj = tile - ti * ntl;
-        const int ar = 16 * ti + li, bc = 16 * tj + li;
-        f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            double av[4], bv[4];
+    const int ar = 16 * ti + li, bc = 16 * tj + li;
+    const bool okr = ar < M, okc = bc < N;
+    gdouble* ap = as_global(A) + (ta ? ar : ar * lda);
+    gdouble* bp = as_global(B) + (tb ? bc * ldb : bc);
+    const int as = ta ? lda : 1, bs = tb ? 1 : ldb;
+    gdouble* zw = as_global(g_zero_chol);
+    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int ns = (K + 3) / 4;  // K steps of 4
+    for (int s0 = wave; s0 < ns; s0 += 16) {  // four steps per wave per round
+        double av[4], bv[4];
 #pragma unroll
-            for (int s = 0; s < 4; s++) {
-                const int k = k0 + 4 * s + lg;
-                const bool ok = k < K;
-                av[s] = (ok && ar < M) ? (ta ? A[k * lda + ar] : A[ar * lda + k]) : 0.0;
-                bv[s] = (ok && bc < N) ? (tb ? B[bc * ldb + k] : B[k * ldb + bc]) : 0.0;
-            }
-#pragma unroll
-            for (int s = 0; s < 4; s++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+        for (int u = 0; u < 4; u++) {
+            const int k = 4 * (s0 + 4 * u) + lg;
+            const bool ok = k < K;
+            av[u] = *((ok && okr) ? ap + k * as : zw);
+            bv[u] = *((ok && okc) ? bp + k * bs : zw);
         }
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const int r = 16 * ti + lg + 4 * e;
-            if (r < M && bc < N) {
-                double* c = C + r * ldc + bc;
-                *c = beta == 0.0 ? alpha * acc[e] : fma(alpha, acc[e], beta * *c);
-            }
+        for (int u = 0; u < 4; u++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int e = 0; e < 4; e++) part[wave - 1][e][lane] = acc[e];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        const int r = 16 * ti + lg + 4 * e;
+        if (r < M && okc) {
+            const double v = ((acc[e] + part[0][e][lane]) + part[1][e][lane]) + part[2][e][lane];
+            double* c = C + r * ldc + bc;
+            *c = beta == 0.0 ? alpha * v : fma(alpha, v, beta * *c);
         }
     }
 }
 
-// The Cholesky stage: G = R^T R, R^{-1}, for l <= 264.  l <= 128: one block
-// factor in registers.  Larger l: nb = ceil(l / 128) diagonal blocks, right
-// looking: factor block k, form its block row R_kj = R_kk^{-T} G_kj, subtract
-// R_kj^T R_kj from the trailing blocks of G (in place); then the blocks of
-// R^{-1} above the diagonal, last block column first:
-// R^{-1}_ij = -R^{-1}_ii sum_{i<m<=j} R_im R^{-1}_mj.  All phases run in this
-// one work-group, separated by barriers; the block products read and write
-// cache-resident global memory (Qt serves as the l x l temporary).
+__global__ __launch_bounds__(256) void k_chol_gemm(const Prob* __restrict__ probs,
+                                                   const int32_t* __restrict__ pidx, int cnt,
+                                                   int mode, int iter, int type, int a, int b) {
+    const int pi = blockIdx.x / CG_TILES, tile = blockIdx.x - pi * CG_TILES;
+    if (pi >= cnt) return;
+    const Prob& P = probs[pidx[pi]];
+    if (iter >= 0 && iter > P.q) return;
+    if (mode == CHOL_SECOND && !second_pass(P, iter)) return;
+    const int l = P.l;
+    int nb, bs;
+    chol_blocks(l, nb, bs);
+    double* __restrict__ G = P.G;
+    double* __restrict__ R = P.R;
+    double* __restrict__ Ri = P.Rinv;
+    double* __restrict__ Tm = P.Qt;
+    int M, N, K;
+    double alpha = 1.0, beta = 0.0;
+    const double* Am;
+    const double* Bm;
+    double* Cm;
+    bool ta = false;
+    if (type == CG_ROW || type == CG_TR) {
+        const int k = a;
+        if (k >= nb - 1) return;
+        const int o = k * bs, o2 = o + bs, rest = l - o2;
+        K = bs;
+        if (type == CG_ROW) {
+            M = bs; N = rest;
+            Am = Ri + o * l + o; ta = true;
+            Bm = G + o * l + o2;
+            Cm = R + o * l + o2;
+        } else {
+            M = rest; N = rest; alpha = -1.0; beta = 1.0;
+            Am = R + o * l + o2; ta = true;
+            Bm = R + o * l + o2;
+            Cm = G + o2 * l + o2;
+        }
+    } else {
+        const int j = a, i = b;
+        if (j >= nb) return;
+        const int oj = j * bs, nj = min(bs, l - oj), oi = i * bs, ni = bs;
+        M = ni; N = nj;
+        if (type == CG_TM) {
+            K = oj + nj - (oi + ni);
+            Am = R + oi * l + oi + ni;
+            Bm = Ri + (oi + ni) * l + oj;
+            Cm = Tm;
+            // R is final from here on: the first such step copies it for the
+            // accumulated factor of the pass
+            if (j == 1 && mode == CHOL_FIRST)
+                for (int e = tile * 256 + threadIdx.x; e < l * l; e += CG_TILES * 256) P.Racc[e] = R[e];
+        } else {
+            K = ni; alpha = -1.0;
+            Am = Ri + oi * l + oi;
+            Bm = Tm;
+            Cm = Ri + oi * l + oj;
+        }
+    }
+    const int nt = (N + 15) / 16;
+    const int ti = tile / nt, tj = tile - ti * nt;
+    if (ti >= (M + 15) / 16) return;
+    if (type == CG_TR && tj < ti) return;  // the lower triangle of G is never read
+    gemm_tile(ti, tj, M, N, K, alpha, Am, l, ta, Bm, l, false, beta, Cm, l);
+}
+
+// The Cholesky stage: G = R^T R and R^{-1}.  stage < 0 (l <= 128 for the
+// whole launch): one block factor in registers.  stage = k (l > 128 in the
+// launch): diagonal block k of nb = ceil(l / 128) blocks, right looking; the
+// products between the factors are the k_chol_gemm launches above.  The pivot
+// threshold tol is taken from G before the first block and kept in rep[96].
 __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict__ probs,
                                                         const int32_t* __restrict__ pidx,
                                                         const int32_t* __restrict__ toff, int cnt,
-                                                        int mode, int iter) {
+                                                        int mode, int iter, int stage) {
     __shared__ double s_tol;
     __shared__ int s_clamped_any;
     int local;
@@ -365,78 +476,80 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
     if (mode == CHOL_SECOND && !second_pass(P, iter)) return;
     const int l = P.l;
     const int tid = threadIdx.x, nth = blockDim.x;
+    int nb, bs;
+    chol_blocks(l, nb, bs);
+    const int k = stage < 0 ? 0 : stage;
+    if (k >= nb) return;
     double* __restrict__ G = P.G;
     double* __restrict__ R = P.R;
     double* __restrict__ Ri = P.Rinv;
-    if (tid < 64) {
-        double mx = 0.0;
-        for (int i = tid; i < l; i += 64) mx = fmax(mx, fabs(G[i * l + i]));
+    if (tid == 0) s_clamped_any = 0;
+    if (k == 0) {
+        if (tid < 64) {
+            double mx = 0.0;
+            for (int i = tid; i < l; i += 64) mx = fmax(mx, fabs(G[i * l + i]));
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if (tid == 0) {
-            const double t = (double)l * 0x1.0p-52 * mx;
-            s_tol = t > 0.0 ? t : 0x1.0p-1000;
-            s_clamped_any = 0;
+            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+            if (tid == 0) {
+                const double t = (double)l * 0x1.0p-52 * mx;
+                s_tol = t > 0.0 ? t : 0x1.0p-1000;
+                P.rep[96] = s_tol;
+            }
         }
+        // blocks of R and R^{-1} below the diagonal blocks are zero
+        if (nb > 1)
+            for (int a = tid >> 6; a < l; a += nth >> 6)
+                for (int b = tid & 63; b < (a / bs) * bs; b += 64) {
+                    R[a * l + b] = 0.0;
+                    Ri[a * l + b] = 0.0;
+                }
+    } else if (tid == 0) {
+        s_tol = P.rep[96];
     }
     __syncthreads();
     const double tol = s_tol;
-    {
-        const int nb = (l + CRT_LMAX - 1) / CRT_LMAX;
-        const int bs = ((l + nb - 1) / nb + 3) / 4 * 4;
-        // blocks of R and R^{-1} below the diagonal blocks are zero
-        if (nb > 1)
-            for (int e = tid; e < l * l; e += nth) {
-                const int a = e / l, b = e - (e / l) * l;
-                if (a / bs != b / bs && b < a) { R[e] = 0.0; Ri[e] = 0.0; }
-            }
-        for (int k = 0; k < nb; k++) {
-            const int o = k * bs, n = min(bs, l - o), o2 = o + n, rest = l - o2;
-            chol_block(G + o * l + o, n, R + o * l + o, Ri + o * l + o, l, tol, &s_clamped_any);
-            __syncthreads();
-            if (rest <= 0) break;
-            // block row: R_kj = (R^{-1}_kk)^T G_kj
-            blk_gemm(n, rest, n, 1.0, Ri + o * l + o, l, true, G + o * l + o2, l, false, 0.0,
-                     R + o * l + o2, l);
-            __syncthreads();
-            // trailing update: G_jj -= R_kj^T R_kj (the lower triangle is never read)
-            blk_gemm(rest, rest, n, -1.0, R + o * l + o2, l, true, R + o * l + o2, l, false, 1.0,
-                     G + o2 * l + o2, l);
-            __syncthreads();
-        }
-        // R^{-1} above the diagonal blocks
-        double* __restrict__ Tm = P.Qt;
-        for (int j = 1; j < nb; j++) {
-            const int oj = j * bs, nj = min(bs, l - oj);
-            for (int i = j - 1; i >= 0; i--) {
-                const int oi = i * bs, ni = bs;
-                // Tm = sum_{i<m<=j} R_im R^{-1}_mj  (ni x nj)
-                const int kk = oj + nj - (oi + ni);
-                blk_gemm(ni, nj, kk, 1.0, R + oi * l + oi + ni, l, false, Ri + (oi + ni) * l + oj, l,
-                         false, 0.0, Tm, l);
-                __syncthreads();
-                // R^{-1}_ij = -R^{-1}_ii Tm
-                blk_gemm(ni, nj, ni, -1.0, Ri + oi * l + oi, l, false, Tm, l, false, 0.0,
-                         Ri + oi * l + oj, l);
-                __syncthreads();
-            }
-        }
-    }
+    const int o = k * bs, n = min(bs, l - o);
+    chol_block(G + o * l + o, n, R + o * l + o, Ri + o * l + o, l, tol, &s_clamped_any);
     __syncthreads();
     if (tid == 0 && s_clamped_any) atomicOr(P.flags, FLAG_RANK_DEF);
-    if (mode == CHOL_FIRST)
+    if (nb == 1 && mode == CHOL_FIRST)
         for (int e = tid; e < l * l; e += nth) P.Racc[e] = R[e];
 }
 
 hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
-    // one wave per 16 x 16 tile of a diagonal block, at most CH_SLOTS tiles
-    // per wave (16 waves for blocks of 113 .. 128)
-    const int tn = (std::min(lmax, CRT_LMAX) + 15) / 16;
-    const int threads = lmax > CRT_LMAX ? CRT_THREADS : 64 * std::min(16, tn * tn);
-    hipLaunchKernelGGL(k_chol_rt, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx,
-                       g.toff, g.count, mode, iter);
-    return hipGetLastError();
+    if (lmax <= CRT_LMAX) {
+        // one wave per 16 x 16 tile of the block, at most CH_SLOTS tiles per
+        // wave (16 waves for blocks of 113 .. 128)
+        const int tn = (lmax + 15) / 16;
+        const int threads = 64 * std::min(16, tn * tn);
+        hipLaunchKernelGGL(k_chol_rt, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx,
+                           g.toff, g.count, mode, iter, -1);
+        return hipGetLastError();
+    }
+    const int nbmax = (lmax + CRT_LMAX - 1) / CRT_LMAX;
+    auto gemm = [&](int type, int a, int b) {
+        hipLaunchKernelGGL(k_chol_gemm, dim3(g.count * CG_TILES), dim3(256), 0, s, g.probs,
+                           g.pidx, g.count, mode, iter, type, a, b);
+        return hipGetLastError();
+    };
+    for (int k = 0; k < nbmax; k++) {
+        hipLaunchKernelGGL(k_chol_rt, dim3(g.blocks), dim3(CRT_THREADS), 0, s, g.probs, g.pidx,
+                           g.toff, g.count, mode, iter, k);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (k + 1 < nbmax) {
+            if ((e = gemm(CG_ROW, k, 0)) != hipSuccess) return e;
+            if ((e = gemm(CG_TR, k, 0)) != hipSuccess) return e;
+        }
+    }
+    for (int j = 1; j < nbmax; j++)
+        for (int i = j - 1; i >= 0; i--) {
+            hipError_t e = gemm(CG_TM, j, i);
+            if (e != hipSuccess) return e;
+            if ((e = gemm(CG_RI, j, i)) != hipSuccess) return e;
+        }
+    return hipSuccess;
 }
 
 // R2 = R' R (both upper triangular): the R factor of Y2 after both

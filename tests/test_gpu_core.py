@@ -106,10 +106,11 @@ def test_f64_ragged_shapes(cu, dev, orc, m, n, k, p, q, lda_pad):
     assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
 
 
-@pytest.mark.parametrize("l", [130, 150, 170, 185, 200, 224, 240])
+@pytest.mark.parametrize("l", [130, 150, 170, 185, 200, 224, 240, 260])
 def test_f64_core_qrcp_sizes(cu, dev, orc, l):
-    """l x l core QRCP beyond 128 columns: every LDS row count of the
-    register + LDS kernel (l = 130 .. 224) and the streaming kernel (l = 240)."""
+    """l x l stages beyond 128 columns: every LDS row count of the register +
+    LDS QRCP kernel (l = 130 .. 224), the streaming QRCP kernel (l = 240, 260),
+    and the Cholesky in two (l <= 256) and three (l = 260) diagonal blocks."""
     import torch
 
     m, n = 560, 500
