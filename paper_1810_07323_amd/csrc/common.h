@@ -86,6 +86,12 @@ __device__ __forceinline__ bool second_pass(const Prob& P, int iter) {
     return iter < 0 || iter == P.q || P.cholqr2_all != 0;
 }
 
+// U = Q1 Qt diag(sign) through the l x l product Qs and one MFMA product
+// (large l, or more row blocks of Q1 than the GPU holds at once), else by the
+// reflectors applied straight to the rows of Q1.  Per problem, so that a
+// problem's arithmetic does not depend on what it is batched with.
+__host__ __device__ inline bool u_via_qs(int64_t m, int l) { return l > 128 || m > 16384; }
+
 __device__ __forceinline__ int find_group(const int32_t* __restrict__ toff, int cnt, int b) {
     int lo = 0, hi = cnt - 1;
     while (lo < hi) {

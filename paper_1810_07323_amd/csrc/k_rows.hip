@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter >= 0 && iter > P.q) return;
-    const bool two = second_pass(P, iter);
+    const bool two = MODE != AP_Q1_QS_U && second_pass(P, iter);
     if (MODE == AP_QA_RINV_Q && !two) return;
     const int l = P.l, lp = P.lp;
     const int nt = lp / 16;
@@ -461,12 +461,13 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
     const int64_t rows = side == SIDE_M ? P.m : P.n;
     const int64_t r0 = (int64_t)local * AP_ROWS;
     const int nrows = (int)min((int64_t)AP_ROWS, rows - r0);
-    const double* __restrict__ src = (MODE == AP_QA_RINV_Q) ? P.Qa : P.Y;
-    const double* __restrict__ S = P.Rinv;
-    // First pass: into Qa when a second pass follows, else straight into Q.
-    double* const qdst = side == SIDE_M ? P.Q1 : P.Q2;
+    const double* __restrict__ src = MODE == AP_Q1_QS_U ? P.Q1 : (MODE == AP_QA_RINV_Q) ? P.Qa : P.Y;
+    const double* __restrict__ S = MODE == AP_Q1_QS_U ? P.G : P.Rinv;
+    // First pass: into Qa when a second pass follows, else straight into Q
+    // (and its operand copy for the next pass).  U = Q1 Qs: into U only.
+    double* const qdst = MODE == AP_Q1_QS_U ? P.U : side == SIDE_M ? P.Q1 : P.Q2;
     double* const dst = (MODE == AP_Y_RINV_QA && two) ? P.Qa : qdst;
-    const bool op = !(MODE == AP_Y_RINV_QA && two);
+    const bool op = MODE != AP_Q1_QS_U && !(MODE == AP_Y_RINV_QA && two);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -572,6 +573,7 @@ hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int 
         case AP_Y_RINV_QA: return launch_apply_m<AP_Y_RINV_QA>(g, side, lmax, iter, s);
         case AP_QA_RINV_Q: return launch_apply_m<AP_QA_RINV_Q>(g, side, lmax, iter, s);
         case AP_Y_RINV_Q: return launch_apply_m<AP_Y_RINV_Q>(g, side, lmax, iter, s);
+        case AP_Q1_QS_U: return launch_apply_m<AP_Q1_QS_U>(g, side, lmax, iter, s);
     }
     return hipErrorInvalidValue;
 }

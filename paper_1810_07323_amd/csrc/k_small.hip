@@ -1276,17 +1276,19 @@ hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// U = Q1 H_0 H_1 ... H_{l-1} diag(sign): the reflectors of the QRCP applied
-// to the rows of Q1 (equal to Q1 Qt without forming Qt).  Eight lanes share a
+// The reflectors of the QRCP applied to rows: where u_via_qs, to the rows of
+// the l x l identity, giving Qs = H_0 H_1 ... H_{l-1} diag(sign) in G (free
+// after the last Cholesky), and U = Q1 Qs is then one FP64 MFMA product
+// (k_apply); otherwise straight to the rows of Q1, giving U.  Eight lanes share a
 // row; lane k holds the entries a = k (mod 8) in registers, so a reflector
-// costs two short dot/axpy loops and a three-step shuffle reduction.  The
-// reflectors stream through LDS in panels of 32.
+// costs a dot product (four partial sums), a three-step shuffle reduction and
+// an axpy.  The reflectors stream through LDS in panels of 32.
 // ---------------------------------------------------------------------------
 constexpr int FU_ROWS = 32;
 constexpr int FU_PANEL = 32;
 
 template <int TN>
-__global__ __launch_bounds__(256) void k_form_u(const Prob* __restrict__ probs,
+__global__ __launch_bounds__(256) void k_form_qs(const Prob* __restrict__ probs,
                                                 const int32_t* __restrict__ pidx,
                                                 const int32_t* __restrict__ toff, int cnt) {
     constexpr int LPAD = 8 * TN;                   // reflector rows padded with zeros
@@ -1295,15 +1297,16 @@ __global__ __launch_bounds__(256) void k_form_u(const Prob* __restrict__ probs,
     int local;
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
     const int l = P.l;
+    const bool ident = u_via_qs(P.m, l);
     const int tid = threadIdx.x;
     const int rr = tid >> 3, k = tid & 7;
     const int64_t row = (int64_t)local * FU_ROWS + rr;
-    const bool rv = row < P.m;
+    const bool rv = row < (ident ? (int64_t)l : P.m);
     double u[TN];
 #pragma unroll
     for (int t = 0; t < TN; t++) {
         const int a = k + 8 * t;
-        u[t] = (rv && a < l) ? P.Q1[row * l + a] : 0.0;
+        u[t] = ident ? ((rv && a == row) ? 1.0 : 0.0) : ((rv && a < l) ? P.Q1[row * l + a] : 0.0);
     }
     for (int j0 = 0; j0 < l; j0 += FU_PANEL) {
         const int pj = min(FU_PANEL, l - j0);
@@ -1320,10 +1323,10 @@ __global__ __launch_bounds__(256) void k_form_u(const Prob* __restrict__ probs,
             double vv[TN];
 #pragma unroll
             for (int t = 0; t < TN; t++) vv[t] = v[8 * t];
-            double d = 0.0;
+            double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int t = 0; t < TN; t++) d += u[t] * vv[t];
-            d = sum8_dpp(d);
+            for (int t = 0; t < TN; t++) d4[t & 3] = fma(u[t], vv[t], d4[t & 3]);
+            const double d = sum8_dpp((d4[0] + d4[1]) + (d4[2] + d4[3]));
             const double w = s_tau[jj] * d;
 #pragma unroll
             for (int t = 0; t < TN; t++) u[t] -= w * vv[t];
@@ -1333,11 +1336,11 @@ __global__ __launch_bounds__(256) void k_form_u(const Prob* __restrict__ probs,
 #pragma unroll
     for (int t = 0; t < TN; t++) {
         const int a = k + 8 * t;
-        if (a < l) P.U[row * l + a] = u[t] * P.tau[LMAX + a];
+        if (a < l) (ident ? P.G : P.U)[row * l + a] = u[t] * P.tau[LMAX + a];
     }
 }
 
-hipError_t launch_form_u(const LaunchGroup& g, int l, hipStream_t s) {
+hipError_t launch_form_qs(const LaunchGroup& g, int l, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
     const size_t lds = sizeof(double) * FU_PANEL * 8 * 33;
     const int tn = (l + 7) / 8;
@@ -1345,13 +1348,13 @@ hipError_t launch_form_u(const LaunchGroup& g, int l, hipStream_t s) {
     if (tn <= N) {                                                                              \
         static bool attr = false;                                                               \
         if (!attr) {                                                                            \
-            hipError_t e = hipFuncSetAttribute((const void*)k_form_u<N>,                        \
+            hipError_t e = hipFuncSetAttribute((const void*)k_form_qs<N>,                        \
                                                hipFuncAttributeMaxDynamicSharedMemorySize,      \
                                                (int)lds);                                       \
             if (e != hipSuccess) return e;                                                      \
             attr = true;                                                                        \
         }                                                                                       \
-        hipLaunchKernelGGL(k_form_u<N>, dim3(g.blocks), dim3(256), lds, s, g.probs, g.pidx,     \
+        hipLaunchKernelGGL(k_form_qs<N>, dim3(g.blocks), dim3(256), lds, s, g.probs, g.pidx,     \
                            g.toff, g.count);                                                    \
         return hipGetLastError();                                                               \
     }

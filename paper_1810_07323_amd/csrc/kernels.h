@@ -40,7 +40,8 @@ hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int it
                               hipStream_t s);
 // dst = src R^{-1}, row blocks of APPLY_ROWS; lmax = largest l of the group.
 constexpr int APPLY_ROWS = 16;
-enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2 };
+enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2,
+                           AP_Q1_QS_U = 3 };  // U = Q1 Qs (Qs in G, after the QRCP)
 hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int iter,
                         hipStream_t s);
 hipError_t launch_gather_v(const LaunchGroup& g, hipStream_t s);  // blocks: ceil(n*l/256)
@@ -52,7 +53,9 @@ enum CholMode : int32_t { CHOL_FIRST = 0, CHOL_SECOND = 1 };
 hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipStream_t s);
 hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s);
 hipError_t launch_r2(const LaunchGroup& g, int iter, hipStream_t s);  // blocks: nt*nt
-hipError_t launch_form_u(const LaunchGroup& g, int l, hipStream_t s);  // blocks: ceil(m/32)
+// Reflectors applied to rows of the identity (u_via_qs: Qs into G, blocks
+// ceil(l/32)) or of Q1 (U, blocks ceil(m/32)).
+hipError_t launch_form_qs(const LaunchGroup& g, int l, hipStream_t s);
 hipError_t launch_report(const LaunchGroup& g, int phase, hipStream_t s);
 hipError_t launch_normA(const LaunchGroup& g, hipStream_t s);
 hipError_t launch_clear_flags(const LaunchGroup& g, hipStream_t s);

@@ -239,6 +239,7 @@ struct Plan {
     Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, applyM, applyN, vg, r2, norm;
     std::vector<Grp> skAX, skATX;  // per (precision, column tiles)
     std::vector<Grp> formU;        // per register-tile class of l (nt holds l)
+    Grp applyU;                    // U = Q1 Qs for the problems with u_via_qs
     // per iteration of the power loop: whether any problem of the plan takes
     // the second CholeskyQR pass, and whether it is any problem's last one
     // (kernels return at once for the others; their launches are skipped)
@@ -342,11 +343,19 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         std::vector<int64_t> b;
         int lmax = 0;
         for (int i : kv.second) {
-            b.push_back(cdiv(probs[i].m, 32));
+            b.push_back(cdiv(u_via_qs(probs[i].m, P->lay[i].l) ? (int64_t)P->lay[i].l : probs[i].m, 32));
             lmax = std::max(lmax, (int)P->lay[i].l);
         }
         urefs.push_back({lmax, tb.add(kv.second, b)});
     }
+    std::vector<int> usub;
+    std::vector<int64_t> ublk;
+    for (int i = 0; i < count; i++)
+        if (u_via_qs(probs[i].m, P->lay[i].l)) {
+            usub.push_back(i);
+            ublk.push_back(cdiv(probs[i].m, APPLY_ROWS));
+        }
+    const TableBuilder::Ref R_applyU = tb.add(usub, ublk);
     struct SkRef { int prec, nt; TableBuilder::Ref ax, atx; double bax, fax, batx, fatx; };
     std::vector<SkRef> skrefs;
     for (auto& kv : classes) {
@@ -464,7 +473,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->gramM = mk(R_gramM); P->gramN = mk(R_gramN);
     P->redM = mk(R_red); P->redN = P->redM;
     P->small = mk(R_small);
-    P->applyM = mk(R_applyM); P->applyN = mk(R_applyN);
+    P->applyM = mk(R_applyM); P->applyN = mk(R_applyN); P->applyU = mk(R_applyU);
     P->vg = mk(R_vg); P->r2 = mk(R_r2); P->norm = mk(R_norm);
     for (auto& u : urefs) {
         Plan::Grp g = mk(u.r);
@@ -546,9 +555,10 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
             E(launch_make_op(P->opN.g, SIDE_N, s));
         }
     }
-    // M = Q1^T A Q2 = R2^T; M P = Qt T; U = Q1 Qt, V = Q2 P.
+    // M = Q1^T A Q2 = R2^T; M P = Qt T; U = Q1 Qs (Qs = Qt diag(sign)), V = Q2 P.
     E(launch_qrcp(P->small.g, P->lmax, s));
-    for (const auto& ug : P->formU) E(launch_form_u(ug.g, ug.nt, s));
+    for (const auto& ug : P->formU) E(launch_form_qs(ug.g, ug.nt, s));
+    E(launch_apply(P->applyU.g, SIDE_M, AP_Q1_QS_U, P->lmax, -1, s));
     E(launch_gather_v(P->vg.g, s));
     if (P->report) {
         E(launch_gram(P->gramM.g, SIDE_M, GSRC_U, -1, s));
