@@ -1311,10 +1311,21 @@ __global__ __launch_bounds__(256) void k_form_qs(const Prob* __restrict__ probs,
     for (int j0 = 0; j0 < l; j0 += FU_PANEL) {
         const int pj = min(FU_PANEL, l - j0);
         __syncthreads();
-#pragma unroll 8
-        for (int e = tid; e < pj * LPAD; e += 256) {
-            const int jj = e / LPAD, a = e % LPAD;
-            vt[e] = a < l ? P.Qt[(int64_t)(j0 + jj) * l + a] : 0.0;
+        {
+            // the panel (FU_PANEL x LPAD = 256 TN entries): TN loads per
+            // thread, all in flight (entries outside Qt read a zero word)
+            static_assert(FU_PANEL * 8 == 256, "TN entries of a panel per thread");
+            gdouble* qt = as_global(P.Qt);
+            gdouble* zw = as_global(g_zero_chol);
+            double pv[TN];
+#pragma unroll
+            for (int u = 0; u < TN; u++) {
+                const int e = tid + 256 * u;
+                const int jj = e / LPAD, a = e - (e / LPAD) * LPAD;
+                pv[u] = *((jj < pj && a < l) ? qt + (int64_t)(j0 + jj) * l + a : zw);
+            }
+#pragma unroll
+            for (int u = 0; u < TN; u++) vt[tid + 256 * u] = pv[u];
         }
         if (tid < pj) s_tau[tid] = P.tau[j0 + tid];
         __syncthreads();
