@@ -39,7 +39,6 @@ template <> struct SkCfg<P_F32> { static constexpr int BK = 32, VEC = 4; };
 template <> struct SkCfg<P_BF16> { static constexpr int BK = 64, VEC = 8; };
 template <> struct SkCfg<P_FP8> { static constexpr int BK = 128, VEC = 16; };
 
-constexpr int SK_RT = 2;                      // row tiles of 16 per wave
 // Block shapes.  A X blocks in FP32/FP64: 4 waves, 128 output rows (each A
 // row contributes a long contiguous K run).  A^T X blocks: 8 waves, 256
 // output rows, so that every row of A a block reads is a 1 KB (FP32)
@@ -53,6 +52,18 @@ template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_wav
     return (NT <= ntmax && (TRANS || PREC == P_BF16)) ? 8 : 4;
 }
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_threads() { return 64 * sk_waves<PREC, NT, TRANS>(); }
+// Waves of a block as a grid of row groups x WC column groups: each wave owns
+// RT = 2 WC row tiles of 16 and ceil(NT / WC) column tiles.  BF16 with eight
+// to fourteen column tiles splits the columns in two (4 x 2 waves, 64 rows x
+// NT/2 columns each): the same accumulators as 32 rows x NT, but each wave
+// reads 4 A and NT/2 X fragments from LDS per K step instead of 2 and NT,
+// about a third less LDS traffic per MFMA.
+template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_wc() {
+    return (PREC == P_BF16 && NT >= 8 && NT <= 14 && sk_waves<PREC, NT, TRANS>() == 8) ? 2 : 1;
+}
+template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_rt() {
+    return 2 * sk_wc<PREC, NT, TRANS>();
+}
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_bm() { return 32 * sk_waves<PREC, NT, TRANS>(); }
 constexpr int ROWB = 144;                     // LDS bytes per 128-byte K row (+16 pad)
 
@@ -106,6 +117,10 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
     typedef typename PrecT<PREC>::T T;
     typedef typename PrecT<PREC>::Acc Acc;
     constexpr int SK_THREADS = sk_threads<PREC, NT, TRANS>();
+    constexpr int SK_WC = sk_wc<PREC, NT, TRANS>();
+    constexpr int SK_RT = sk_rt<PREC, NT, TRANS>();
+    constexpr int NTW = (NT + SK_WC - 1) / SK_WC;  // column tiles per wave
+    static_assert(SK_RT * 16 * (SK_THREADS / 64 / SK_WC) == sk_bm<PREC, NT, TRANS>(), "rows per block");
     constexpr int SK_BM = sk_bm<PREC, NT, TRANS>();
     constexpr int SZ = PrecT<PREC>::SZ;
     constexpr int BK = SkCfg<PREC>::BK;
@@ -326,15 +341,17 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
 
     // ---------------- accumulators ----------------
     typedef typename std::conditional<PREC == P_F64, f64x4, f32x4>::type AccV;
-    AccV acc[SK_RT][NT];
+    AccV acc[SK_RT][NTW];
 #pragma unroll
     for (int r = 0; r < SK_RT; r++)
 #pragma unroll
-        for (int c = 0; c < NT; c++)
+        for (int c = 0; c < NTW; c++)
 #pragma unroll
             for (int e = 0; e < 4; e++) acc[r][c][e] = Acc(0);
 
-    const int wrow = wave * (SK_RT * 16);
+    constexpr int WRN = SK_THREADS / 64 / SK_WC;  // row groups
+    const int wrow = (wave % WRN) * (SK_RT * 16);
+    const int c0 = SK_WC == 1 ? 0 : (wave / WRN) * NTW;  // first column tile of this wave
 
     auto compute_tile = [&](int buf) {
         const unsigned char* As = smem + buf * (ABYTES + XBYTES);
@@ -398,8 +415,10 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                         av[r] = *reinterpret_cast<const bf16x8*>(As + orow * ROWB + kk * 2);
                 }
 #pragma unroll
-                for (int c = 0; c < NT; c++) {
-                    bf16x8 bv = *reinterpret_cast<const bf16x8*>(Xs + (c * 16 + li) * ROWB + kk * 2);
+                for (int c = 0; c < NTW; c++) {
+                    const int cc = c0 + c;  // column tile (wave-uniform test)
+                    if (SK_WC > 1 && cc >= NT) break;
+                    bf16x8 bv = *reinterpret_cast<const bf16x8*>(Xs + (cc * 16 + li) * ROWB + kk * 2);
 #pragma unroll
                     for (int r = 0; r < SK_RT; r++)
                         acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bv, acc[r][c], 0, 0, 0);
@@ -458,14 +477,17 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
 #pragma unroll
     for (int r = 0; r < SK_RT; r++)
 #pragma unroll
-        for (int c = 0; c < NT; c++)
+        for (int c = 0; c < NTW; c++) {
+            const int cc = c0 + c;
+            if (SK_WC > 1 && cc >= NT) break;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 // f32 forms: (row 4g + e, col i); f64 form: (row g + 4e, col i)
                 int tr = (PREC == P_F64) ? (lg + 4 * e) : (4 * lg + e);
                 int64_t gr = row0 + wrow + r * 16 + tr;
-                if (gr < rows) out[gr * lp + c * 16 + li] = acc[r][c][e];
+                if (gr < rows) out[gr * lp + cc * 16 + li] = acc[r][c][e];
             }
+        }
 }
 
 // ---------------------------------------------------------------------------
