@@ -100,6 +100,7 @@ __device__ __forceinline__ void set4(f64x4& x, int h, double v) {
 struct CholShared {
     double w[4][CRT_LMAX];  // the four rows of the current block (after B)
     double blk[16];         // the factored 4 x 4 block: rows v and L1^{-1}
+    double f[16];           // the 4 x 4 block before the factor (owner wave only)
     double inv[2][4];       // 1 / d of the block, by block parity
     double d[CRT_LMAX];     // pivots
     double sq[CRT_LMAX];    // sqrt(d)
@@ -113,11 +114,19 @@ __device__ __forceinline__ void chol_factor4(f64x4& x, int kb, int n, double tol
                                              CholShared& sh) {
     const int lane = threadIdx.x & 63, h = kb & 3;
     const double xh = sel4(x, h);
+    // the block through LDS: one write per holding lane, broadcast reads
+    {
+        const int c4 = i - 4 * h;
+        if (c4 >= 0 && c4 < 4) sh.f[4 * g + c4] = xh;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double s[4][4];
 #pragma unroll
     for (int r = 0; r < 4; r++)
 #pragma unroll
-        for (int c = r; c < 4; c++) s[r][c] = readlane_d(xh, 16 * r + 4 * h + c);
+        for (int c = r; c < 4; c++) s[r][c] = sh.f[4 * r + c];
     // Every lane runs the same chain; lane 0 publishes each value once it is
     // final: blk[4 r + c] = v_r[c] (c >= r) or L1^{-1}[r][c] (c < r).
     double m[4][4];
