@@ -72,7 +72,9 @@ typedef enum {
 
 /* cor_info.flags */
 #define COR_FLAG_CHOL_RETRY 1     /* a Cholesky factorisation needed the shifted retry */
-#define COR_FLAG_RANK_DEFICIENT 2 /* a sketch was numerically rank deficient           */
+#define COR_FLAG_RANK_DEFICIENT 2 /* a sketch was numerically rank deficient (the
+                                     * final factors are still orthonormal: the missing
+                                     * directions are completed with Gaussian columns)   */
 #define COR_FLAG_NONFINITE 4      /* a non-finite value reached a Gram matrix          */
 
 typedef struct {

@@ -105,6 +105,7 @@ struct CholShared {
     double d[CRT_LMAX];     // pivots
     double sq[CRT_LMAX];    // sqrt(d)
     double rs[CRT_LMAX];    // 1 / sqrt(d)
+    double dm[CRT_LMAX];    // 1 where the pivot was clamped, else 0
     int clamped;
 };
 
@@ -135,13 +136,15 @@ __device__ __forceinline__ void chol_factor4(f64x4& x, int kb, int n, double tol
     for (int k = 0; k < 4; k++) {
         const double raw = s[k][k];
         const double d = fmax(raw, tol);
-        clamp |= !(raw > tol) && 4 * kb + k < n;
+        const bool ck = !(raw > tol) && 4 * kb + k < n;
+        clamp |= ck;
         const double y = recip3(d);
         if (lane == 0) {
 #pragma unroll
             for (int c = k; c < 4; c++) sh.blk[4 * k + c] = s[k][c];
             sh.inv[kb & 1][k] = y;
             sh.d[4 * kb + k] = d;
+            sh.dm[4 * kb + k] = ck ? 1.0 : 0.0;
         }
 #pragma unroll
         for (int r = k + 1; r < 4; r++) {
@@ -249,11 +252,13 @@ __device__ __forceinline__ void chol_step(f64x4 (&x)[CH_SLOTS], const int (&tp)[
 
 // Factor the n x n block (n <= 128) whose upper triangle is Gs (leading
 // dimension ld): R and R^{-1} of the block into Rout and Rinv (same leading
-// dimension), pivots clamped at tol.  Every thread of the work-group calls it;
+// dimension), pivots clamped at tol; mark[a] = 1 where pivot a was clamped,
+// else 0.  Every thread of the work-group calls it;
 // the work-group has at least max(Tn, Tn^2 / 4) waves, Tn = ceil(n / 16).
 __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
                                            double* __restrict__ Rout, double* __restrict__ Rinv,
-                                           int ld, double tol, int* clamped) {
+                                           int ld, double tol, int* clamped,
+                                           double* __restrict__ mark) {
     __shared__ CholShared sh;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile numbers in SGPRs
@@ -317,6 +322,7 @@ __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
         const double sq = sqrt(sh.d[a]);
         sh.sq[a] = sq;
         sh.rs[a] = 1.0 / sq;
+        mark[a] = sh.dm[a];
     }
     __syncthreads();
     // R[a][b] = v_a[b] / sqrt(d_a) (b > a), sqrt(d_a) (b = a), 0 below;
@@ -518,7 +524,7 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
     __syncthreads();
     const double tol = s_tol;
     const int o = k * bs, n = min(bs, l - o);
-    chol_block(G + o * l + o, n, R + o * l + o, Ri + o * l + o, l, tol, &s_clamped_any);
+    chol_block(G + o * l + o, n, R + o * l + o, Ri + o * l + o, l, tol, &s_clamped_any, P.tau + o);
     __syncthreads();
     if (tid == 0 && s_clamped_any) atomicOr(P.flags, FLAG_RANK_DEF);
     if (nb == 1 && mode == CHOL_FIRST)

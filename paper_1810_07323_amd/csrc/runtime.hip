@@ -237,6 +237,7 @@ struct Plan {
         double bytes = 0, flops = 0;  // algorithmic cost of one launch
     };
     Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, applyM, applyN, vg, r2, norm;
+    Grp fixM, fixN;  // replacement of the clamped directions of a rank-deficient sketch
     std::vector<Grp> skAX, skATX;  // per (precision, column tiles)
     std::vector<Grp> formU;        // per register-tile class of l (nt holds l)
     Grp applyU;                    // U = Q1 Qs for the problems with u_via_qs
@@ -326,6 +327,8 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     auto R_applyM = per([&](int i) { return cdiv(probs[i].m, APPLY_ROWS); });
     auto R_applyN = per([&](int i) { return cdiv(probs[i].n, APPLY_ROWS); });
     auto R_vg = per([&](int i) { return cdiv(probs[i].n * P->lay[i].l, 256); });
+    auto R_fixM = per([&](int i) { return cdiv(probs[i].m, 256); });
+    auto R_fixN = per([&](int i) { return cdiv(probs[i].n, 256); });
     auto R_r2 = per([&](int i) { return (int64_t)P->lay[i].nt * P->lay[i].nt; });
     auto R_norm = per([&](int) { return (int64_t)64; });
     // Sketch tables: one per (precision, column-tile count) class.
@@ -475,6 +478,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->small = mk(R_small);
     P->applyM = mk(R_applyM); P->applyN = mk(R_applyN); P->applyU = mk(R_applyU);
     P->vg = mk(R_vg); P->r2 = mk(R_r2); P->norm = mk(R_norm);
+    P->fixM = mk(R_fixM); P->fixN = mk(R_fixN);
     for (auto& u : urefs) {
         Plan::Grp g = mk(u.r);
         g.nt = u.lmax;
@@ -527,6 +531,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
         E(launch_apply(P->applyM.g, SIDE_M, AP_Y_RINV_QA, P->lmax, it, s));
         if (P->second[it]) {
+            E(launch_fix_deficient(P->fixM.g, SIDE_M, it, s));
             E(launch_gram(P->gramM.g, SIDE_M, GSRC_QA, it, s));
             E(launch_gram_reduce(P->redM.g, SIDE_M, 1, it, s));
             E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
@@ -544,6 +549,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
         E(launch_apply(P->applyN.g, SIDE_N, AP_Y_RINV_QA, P->lmax, it, s));
         if (P->second[it]) {
+            E(launch_fix_deficient(P->fixN.g, SIDE_N, it, s));
             E(launch_gram(P->gramN.g, SIDE_N, GSRC_QA, it, s));
             E(launch_gram_reduce(P->redN.g, SIDE_N, 1, it, s));
             E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));

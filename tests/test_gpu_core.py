@@ -131,6 +131,29 @@ def test_f64_core_qrcp_sizes(cu, dev, orc, l):
         assert np.abs(np.diag(T) - d).max() <= 1e-10 * d.max()
 
 
+@pytest.mark.parametrize("case,q", [("rank5", 0), ("rank5", 2), ("zero", 1)])
+def test_f64_rank_deficient(cu, dev, orc, case, q):
+    """A sketch of rank below l (rank(A) = 5 < l = 15, and A = 0): the
+    reconstruction is exact (the oracle's error, which is rounding level) and
+    U, V are still orthonormal; the library reports the rank-deficient sketch."""
+    import torch
+
+    m, n, k, p = 300, 200, 10, 5
+    if case == "zero":
+        a = np.zeros((m, n))
+    else:
+        a, _ = I.lowrank(m, n, np.array([1.0, 0.5, 0.25, 0.1, 0.05]), seed=1)
+    om = I.gaussian_omega(n, k + p, 7)
+    gpu = _run_gpu(cu, dev, torch.from_numpy(a).to(dev), k, p, q, om)
+    mg, mo, ref = _compare_f64(orc, a, k, p, q, om, gpu, f"{case} q={q}")
+    U, T, V, perm, info = gpu
+    assert np.isfinite(U).all() and np.isfinite(T).all() and np.isfinite(V).all()
+    assert abs(mg["err_l"] - mo["err_l"]) <= 1e-12 and mg["err_l"] <= 1e-13
+    assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
+    assert np.array_equal(np.tril(T, -1), np.zeros_like(T))
+    assert info.flags & cu.COR_FLAG_RANK_DEFICIENT
+
+
 def test_f32_scaled_config2(cu, dev, orc):
     """The FP32 workload's recipe (rank-r Haar, sigma_i = exp(-i/40), k=100,
     p=10, q=2) at 1500x1500 with rank 200 so the oracle finishes in seconds."""
