@@ -464,16 +464,18 @@ hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int it
 }
 
 // ---------------------------------------------------------------------------
-// dst = src S for a block of AP_ROWS = 16 rows, S = R^{-1} (l x l, FP64) of a
-// CholeskyQR pass, on the FP64 MFMA (16x16x4).  Wave w owns quarter w of the
-// column tiles (two waves per SIMD at a resident set of blocks, so one wave's
-// load latency hides behind the other's MFMAs).  Lane group g of a wave takes the K
-// slots g KQ + s (KQ = lp / 4, s < KQ): both operands stream from memory into
-// registers (S is small and stays in cache), four K steps per batch with the
-// next batch's loads in flight.  The finished 16 x l tile goes through LDS so
-// that dst (row-major) and the transposed operand copy in the pass format
-// are both written with contiguous runs.  H = column tiles per half (compile
-// time bound of the accumulator array, column tiles per quarter).
+// dst = src S for a block of AP_ROWS = 16 rows, S an l x l FP64 matrix
+// (R^{-1} of a CholeskyQR pass, or Qs for U = Q1 Qs), on the FP64 MFMA
+// (16x16x4).  Wave w owns quarter w of the column tiles; small blocks give
+// several waves per SIMD, so one wave's load latency hides behind another's
+// MFMAs (64-row blocks with four row tiles per wave measured slower).  Lane
+// group g of a wave takes the K slots g KQ + s (KQ = lp / 4, s < KQ): both
+// operands stream from memory into registers (S is small and stays in
+// cache), four K steps per batch with the next batch's loads in flight.  The
+// finished 16 x l tile goes through LDS so that dst (row-major) and the
+// transposed operand copy in the pass format are both written with
+// contiguous runs.  H = column tiles per quarter (compile-time bound of the
+// accumulator array).
 // The stage (source, destination) is a template parameter: a run-time switch
 // over these pointers was mis-compiled by the gfx950 backend (the default
 // branch kept the source of another case).
