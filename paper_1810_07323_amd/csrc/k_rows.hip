@@ -90,7 +90,7 @@ hipError_t launch_omega_raw(uint64_t seed, int64_t n, int32_t l, double* out, hi
 // no direction of Y.  It is replaced by a Gaussian column of norm about 1
 // (its own counter-based stream) and row j of the accumulated R is zeroed, so
 // that the second pass makes Q orthonormal while Q R still reproduces Y.  A
-// full-rank sketch leaves everything untouched.  Blocks: ceil(rows / 256).
+// full-rank sketch leaves everything untouched.  One block per problem.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fix_deficient(const Prob* __restrict__ probs,
                                                        const int32_t* __restrict__ pidx,
@@ -115,17 +115,15 @@ __global__ __launch_bounds__(256) void k_fix_deficient(const Prob* __restrict__ 
     if (!s_any) return;
     const uint64_t stream = P.seed ^ (side == SIDE_M ? 0x6A09E667F3BCC908ull : 0xBB67AE8584CAA73Bull);
     const double sc = 1.0 / sqrt((double)rows);
-    const int64_t r = (int64_t)local * 256 + threadIdx.x;
-    if (r < rows)
+    for (int64_t r = threadIdx.x; r < rows; r += 256)
         for (int j = 0; j < l; j++)
             if (s_def[j]) {
                 double z0, z1;
                 gauss_pair(stream, (uint64_t)(r * l + j), z0, z1);
                 P.Qa[r * l + j] = z0 * sc;
             }
-    if (local == 0)
-        for (int e = threadIdx.x; e < l * l; e += 256)
-            if (s_def[e / l]) P.Racc[e] = 0.0;
+    for (int e = threadIdx.x; e < l * l; e += 256)
+        if (s_def[e / l]) P.Racc[e] = 0.0;
 }
 
 hipError_t launch_fix_deficient(const LaunchGroup& g, int side, int iter, hipStream_t s) {

@@ -49,6 +49,10 @@ template <> struct SkCfg<P_FP8> { static constexpr int BK = 128, VEC = 16; };
 // tiles, FP32 beyond 12, FP8 beyond 9, FP8 A X) keep 4 waves.
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_waves() {
     constexpr int ntmax = PREC == P_F64 ? 8 : PREC == P_F32 ? 12 : PREC == P_FP8 ? 9 : NTMAX;
+    // BF16 with at most 4 column tiles (l <= 64): 4 waves, whose smaller LDS
+    // tiles let three blocks share a CU, so more A tiles are in flight where
+    // the MFMA work per tile is too short to hide one tile's load.
+    if (PREC == P_BF16 && NT <= 4) return 4;
     return (NT <= ntmax && (TRANS || PREC == P_BF16)) ? 8 : 4;
 }
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_threads() { return 64 * sk_waves<PREC, NT, TRANS>(); }
@@ -178,16 +182,16 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
     i32x4 rx[X_LD];
     // Chunk t of this thread in a transposed tile: K row a_kr(t), column chunk
     // a_ch.  BF16 / FP8: K rows 4 q .. 4 q + 3 per thread (transposed in
-    // registers).  BF16: the 32 lanes of a half wave take 16 column chunks of
+    // registers).  BF16 256-row tiles: the 32 lanes of a half wave take 16 column chunks of
     // two K-row groups, so that their 8-byte LDS writes pair up in the
     // 16-byte granules.
     constexpr int CPR = SK_BM * SZ / 16;  // chunks per A row segment (transposed)
-    if constexpr (ATRANS_BF16)
-        static_assert(A_LD == 4 && CPR == 32 && SK_THREADS == 512, "one 256 x 64 tile, 4 K rows per thread");
-    if constexpr (ATRANS_FP8)
+    if constexpr (ATRANS_BF16 || ATRANS_FP8)
         static_assert(A_LD == 4 && SK_THREADS / CPR * 4 == BK, "4 K rows per thread");
-    const int bq = ATRANS_BF16 ? ((tid >> 6) << 1) | ((tid >> 4) & 1) : tid / CPR;  // K-row group
-    const int bch = ATRANS_BF16 ? (tid & 15) | (((tid >> 5) & 1) << 4) : tid % CPR;  // column chunk
+    // BF16 256 x 64 tiles (CPR = 32, 512 threads): the paired-lane map
+    constexpr bool BPAIR = ATRANS_BF16 && CPR == 32 && SK_THREADS == 512;
+    const int bq = BPAIR ? ((tid >> 6) << 1) | ((tid >> 4) & 1) : tid / CPR;  // K-row group
+    const int bch = BPAIR ? (tid & 15) | (((tid >> 5) & 1) << 4) : tid % CPR;  // column chunk
     auto a_kr = [&](int t) {
         if constexpr (ATRANS_BF16 || ATRANS_FP8) return 4 * bq + t;
         else return (tid + t * SK_THREADS) / CPR;

@@ -112,7 +112,9 @@ static void split_k(int64_t rows, int64_t K, int bk, int target, int prec, int n
                     int32_t* s, int64_t* kc) {
     const int64_t nrb = cdiv(rows, sketch_rows_per_block(prec, nt, trans));
     int64_t sp = std::min<int64_t>(8, std::max<int64_t>(1, target / nrb));
-    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / (4 * bk)));
+    // at least 16 K tiles per split: short splits cost more in prologue,
+    // epilogue and partial sums than they win (small problems of a batch)
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / (16 * bk)));
     int64_t c = roundup(cdiv(K, sp), bk);
     *kc = c;
     *s = (int32_t)cdiv(K, c);
@@ -125,13 +127,14 @@ static int gram_groups(int lp) {  // blocks per row chunk: the upper 16 x 16 til
 
 static void gram_chunks(int64_t rows, int lp, int target, int32_t* rb, int32_t* gb) {
     // Row chunks of the Gram partial sums: about `target` blocks per problem
-    // (chunks x tile groups), at least 64 rows per chunk.  Fewer chunks mean
-    // fewer l x l partials to write and reduce.
+    // (chunks x tiles), at least 256 rows per chunk (64 per wave).  Fewer
+    // chunks mean fewer l x l partials to write and reduce, and small
+    // problems of a batch fewer blocks.
     // A multiple of 8 chunks where there are 8 or more lets the Gram kernel
     // keep each chunk's blocks on one XCD (one L2).
     const int ngroups = gram_groups(lp);
     int64_t g = std::max<int64_t>(1, cdiv(target, ngroups));
-    g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(rows, 64)));
+    g = std::min<int64_t>(g, std::max<int64_t>(1, cdiv(rows, 256)));
     if (g >= 8) g = g / 8 * 8;
     int64_t r = roundup(cdiv(rows, g), 4);
     *rb = (int32_t)r;
@@ -327,8 +330,6 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     auto R_applyM = per([&](int i) { return cdiv(probs[i].m, APPLY_ROWS); });
     auto R_applyN = per([&](int i) { return cdiv(probs[i].n, APPLY_ROWS); });
     auto R_vg = per([&](int i) { return cdiv(probs[i].n * P->lay[i].l, 256); });
-    auto R_fixM = per([&](int i) { return cdiv(probs[i].m, 256); });
-    auto R_fixN = per([&](int i) { return cdiv(probs[i].n, 256); });
     auto R_r2 = per([&](int i) { return (int64_t)P->lay[i].nt * P->lay[i].nt; });
     auto R_norm = per([&](int) { return (int64_t)64; });
     // Sketch tables: one per (precision, column-tile count) class.
@@ -478,7 +479,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->small = mk(R_small);
     P->applyM = mk(R_applyM); P->applyN = mk(R_applyN); P->applyU = mk(R_applyU);
     P->vg = mk(R_vg); P->r2 = mk(R_r2); P->norm = mk(R_norm);
-    P->fixM = mk(R_fixM); P->fixN = mk(R_fixN);
+    P->fixM = mk(R_small); P->fixN = P->fixM;
     for (auto& u : urefs) {
         Plan::Grp g = mk(u.r);
         g.nt = u.lmax;
