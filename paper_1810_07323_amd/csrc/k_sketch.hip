@@ -49,10 +49,10 @@ template <> struct SkCfg<P_FP8> { static constexpr int BK = 128, VEC = 16; };
 // tiles, FP32 beyond 12, FP8 beyond 9, FP8 A X) keep 4 waves.
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_waves() {
     constexpr int ntmax = PREC == P_F64 ? 8 : PREC == P_F32 ? 12 : PREC == P_FP8 ? 9 : NTMAX;
-    // BF16 with at most 4 column tiles (l <= 64): 4 waves, whose smaller LDS
-    // tiles let three blocks share a CU, so more A tiles are in flight where
+    // BF16 with at most 7 column tiles (l <= 112): 4 waves, whose smaller LDS
+    // tiles let two or three blocks share a CU, so more A tiles are in flight where
     // the MFMA work per tile is too short to hide one tile's load.
-    if (PREC == P_BF16 && NT <= 4) return 4;
+    if (PREC == P_BF16 && NT <= 7) return 4;
     return (NT <= ntmax && (TRANS || PREC == P_BF16)) ? 8 : 4;
 }
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_threads() { return 64 * sk_waves<PREC, NT, TRANS>(); }
