@@ -105,16 +105,20 @@ enum {
 };
 
 // K splits of a pass: about `target` blocks in all (row blocks x splits, never
-// more), at most 8 splits, each split at least 4 K tiles long.  The layout of
+// more), at most 8 splits, each split at least 16 K tiles long in BF16 and FP8
+// and 4 in FP32 and FP64.  The layout of
 // a problem depends on its own shape only, never on what it is batched with,
 // so a decomposition gives bitwise the same result alone, batched or served.
 static void split_k(int64_t rows, int64_t K, int bk, int target, int prec, int nt, bool trans,
                     int32_t* s, int64_t* kc) {
     const int64_t nrb = cdiv(rows, sketch_rows_per_block(prec, nt, trans));
     int64_t sp = std::min<int64_t>(8, std::max<int64_t>(1, target / nrb));
-    // at least 16 K tiles per split: short splits cost more in prologue,
-    // epilogue and partial sums than they win (small problems of a batch)
-    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / (16 * bk)));
+    // Short BF16 and FP8 splits cost more in prologue, epilogue and partial
+    // sums than they win (small problems of a batch); an FP32 or FP64 tile
+    // holds 2-4x fewer elements of K, so more MFMA work, and small problems
+    // alone on the GPU gain from the shorter chain of tiles.
+    const int64_t min_tiles = (prec == P_BF16 || prec == P_FP8) ? 16 : 4;
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / (min_tiles * bk)));
     int64_t c = roundup(cdiv(K, sp), bk);
     *kc = c;
     *s = (int32_t)cdiv(K, c);
