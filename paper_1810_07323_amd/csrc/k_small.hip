@@ -30,7 +30,7 @@ __device__ __forceinline__ const Prob& group_prob2(const Prob* probs, const int3
 // Cholesky and inverse in one sweep over an n x n block (n <= 128), with the
 // work matrix held in FP64 MFMA accumulator tiles.
 //
-// Symmetric Gaussian elimination on [G | I], four columns at a time.  The
+// Symmetric Gaussian elimination on [G | I], sixteen columns at a time.  The
 // upper triangle of the np x np work matrix X (np = n rounded up to 16) holds
 // the Schur complement, the strict lower triangle accumulates E = L^{-1}
 // (G = L D L^T, L unit lower).  Row j is final once its column block has been
@@ -40,26 +40,30 @@ __device__ __forceinline__ const Prob& group_prob2(const Prob* probs, const int3
 //   R^-1 = L^{-T} D^-1/2 : R^-1[b][j] = E[j][b] / sqrt(d_j)         (b <  j)
 // X is cut into 16 x 16 tiles kept in the registers of the work-group in the
 // layout of the f64 16x16x4 MFMA result (lane 16 g + i, register r holds row
-// g + 4 r, column i).  The four rows of column block kb are register kb & 3
-// of tile row kb >> 2.  Diagonal tile t sits in slot 0 of wave t.  Per block:
-//   A. the wave owning the diagonal tile reads the 4 x 4 diagonal block with
-//      lane reads, factors it (B = L1 D1 L1^T) with the same scalar chain in
-//      every lane, writes the rows v (upper part) and L1^{-1} (lower part)
-//      back, and publishes them with 1/d and d;
-//   B. every tile of the block's tile row applies L1^{-1} to the four rows
-//      (one MFMA with K = 4), then publishes the rows;
-//   C. every tile with rows below the block subtracts the rank-4 product
-//      sum_k (v_k[a] / d_k) w_k[b] (one MFMA), w = v in the upper triangle
-//      and the E rows (1 on the diagonal, 0 right of it) in the lower one.
-// The owner of the next diagonal tile updates it first and factors the next
-// 4 x 4 block while the other tiles are updated, so the serial path per block
-// is one exchange, one MFMA and the 4 x 4 factor.  Two barriers per block.
+// g + 4 r, column i).  Diagonal tile t sits in slot 0 of wave t.  Per tile
+// column K:
+//   A. the wave owning diagonal tile K factors it, X_KK = L_K D_K L_K^T, in
+//      registers: lane a holds row a, pivot step j takes row j from lane j by
+//      lane reads, and the sixteen dependent steps need no LDS and no barrier;
+//      it publishes the rows v (upper part) and L_K^{-1} (lower part) and 1/d;
+//   B. every other tile of tile row K becomes L_K^{-1} X_KQ (four MFMAs with
+//      K = 4), and the tile row is published;
+//   C. every tile with rows below tile row K subtracts
+//      sum_k (v_k[a] / d_k) w_k[b] over the sixteen rows k of the tile row
+//      (four MFMAs), w = v in the upper triangle and the E rows in the lower
+//      one (L_K^{-1}, 1 on the diagonal and 0 right of it, for tile column K).
+// The owner of the next diagonal tile updates it first and factors it while
+// the other tiles are updated, so the serial path per tile column is the
+// 16 x 16 factor and two four-MFMA products.  Two barriers per tile column.
 // A pivot d_j <= tol (l 2^-52 max_i G_ii) is clamped to tol (numerically
 // rank-deficient sketch) and flagged; padding rows get a pivot above tol.
 // ---------------------------------------------------------------------------
 constexpr int CRT_THREADS = 1024;
 constexpr int CRT_LMAX = 128;
 constexpr int CH_SLOTS = 4;  // 16 x 16 tiles per wave (64 tiles on 16 waves)
+// Row stride of the published tile row: rows g and g + 1 of an MFMA operand
+// read fall into different halves of the LDS banks.
+constexpr int CH_WLD = CRT_LMAX + 16;
 
 // 1/d from the hardware estimate and two Newton steps y <- y + y (1 - d y).
 __device__ __forceinline__ double recip_nr(double d) {
@@ -87,167 +91,128 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ double sel4(const f64x4& x, int h) {
-    return h == 0 ? x[0] : h == 1 ? x[1] : h == 2 ? x[2] : x[3];
-}
-__device__ __forceinline__ void set4(f64x4& x, int h, double v) {
-    x[0] = h == 0 ? v : x[0];
-    x[1] = h == 1 ? v : x[1];
-    x[2] = h == 2 ? v : x[2];
-    x[3] = h == 3 ? v : x[3];
+// LDS operations of one wave complete in order: this orders a wave's own
+// LDS writes before its later reads.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 struct CholShared {
-    double w[4][CRT_LMAX];  // the four rows of the current block (after B)
-    double blk[16];         // the factored 4 x 4 block: rows v and L1^{-1}
-    double f[16];           // the 4 x 4 block before the factor (owner wave only)
-    double inv[2][4];       // 1 / d of the block, by block parity
-    double d[CRT_LMAX];     // pivots
-    double sq[CRT_LMAX];    // sqrt(d)
-    double rs[CRT_LMAX];    // 1 / sqrt(d)
-    double dm[CRT_LMAX];    // 1 where the pivot was clamped, else 0
+    double w[16][CH_WLD];  // tile row K after B (rows 16 K .. 16 K + 15)
+    double dt[2][16][17];  // factored diagonal tile by parity of K: v, L_K^{-1}
+    double inv[2][16];     // 1 / d of tile column K, by parity of K
+    double d[CRT_LMAX];    // pivots
+    double sq[CRT_LMAX];   // sqrt(d)
+    double rs[CRT_LMAX];   // 1 / sqrt(d)
+    double dm[CRT_LMAX];   // 1 where the pivot was clamped, else 0
     int clamped;
 };
 
-// A: factor the 4 x 4 diagonal block kb held in register kb & 3 of the
-// wave's diagonal tile x (element (r, c) in lane 16 r + 4 (kb & 3) + c).
-__device__ __forceinline__ void chol_factor4(f64x4& x, int kb, int n, double tol, int g, int i,
-                                             CholShared& sh) {
-    const int lane = threadIdx.x & 63, h = kb & 3;
-    const double xh = sel4(x, h);
-    // the block through LDS: one write per holding lane, broadcast reads
-    {
-        const int c4 = i - 4 * h;
-        if (c4 >= 0 && c4 < 4) sh.f[4 * g + c4] = xh;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    double s[4][4];
+// A: factor diagonal tile K (x: upper triangle = Schur complement, strict
+// lower triangle zero).  Lane a (of each 16) keeps row a of the symmetric
+// block in t[0..15]; entries left of the diagonal turn into the E row as
+// their pivot step passes (t[j] = -m), so a pivot step is the same fifteen
+// FMAs t[c] -= m t_j[c] for every c != j in every row below the pivot.
+__device__ __forceinline__ void chol_factor16(f64x4& x, int K, int n, double tol, int g, int i,
+                                              CholShared& sh) {
+    const int lane = threadIdx.x & 63, a = lane & 15;
+    double (*dt)[17] = sh.dt[K & 1];
 #pragma unroll
-    for (int r = 0; r < 4; r++)
+    for (int r = 0; r < 4; r++) dt[4 * r + g][i] = x[r];
+    wave_lds_sync();
+    double t[16];
 #pragma unroll
-        for (int c = r; c < 4; c++) s[r][c] = sh.f[4 * r + c];
-    // Every lane runs the same chain; lane 0 publishes each value once it is
-    // final: blk[4 r + c] = v_r[c] (c >= r) or L1^{-1}[r][c] (c < r).
-    double m[4][4];
-    bool clamp = false;
+    for (int c = 0; c < 16; c++) t[c] = c >= a ? dt[a][c] : dt[c][a];
+    double myd = 0.0, myy = 0.0;
+    bool myck = false;
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const double raw = s[k][k];
+    for (int j = 0; j < 16; j++) {
+        const double raw = readlane_d(t[j], j);
+        double rt[16];
+#pragma unroll
+        for (int c = 0; c < 16; c++)
+            if (c != j) rt[c] = readlane_d(t[c], j);
         const double d = fmax(raw, tol);
-        const bool ck = !(raw > tol) && 4 * kb + k < n;
-        clamp |= ck;
+        const bool ck = !(raw > tol) && 16 * K + j < n;
         const double y = recip3(d);
-        if (lane == 0) {
-#pragma unroll
-            for (int c = k; c < 4; c++) sh.blk[4 * k + c] = s[k][c];
-            sh.inv[kb & 1][k] = y;
-            sh.d[4 * kb + k] = d;
-            sh.dm[4 * kb + k] = ck ? 1.0 : 0.0;
+        if (a == j) {
+            myd = d;
+            myy = y;
+            myck = ck;
         }
+        if (a > j) {
+            const double m = t[j] * y;
 #pragma unroll
-        for (int r = k + 1; r < 4; r++) {
-            m[r][k] = s[k][r] * y;
-            // the next pivot first: one FMA after y
-            s[r][r] = fma(-(s[k][r] * s[k][r]), y, s[r][r]);
-#pragma unroll
-            for (int c = r + 1; c < 4; c++) s[r][c] = fma(-m[r][k], s[k][c], s[r][c]);
+            for (int c = 0; c < 16; c++)
+                if (c != j) t[c] = fma(-m, rt[c], t[c]);
+            t[j] = -m;
         }
     }
-    // L1^{-1} (unit lower)
-    double li[4][4];
+    if (lane < 16) {
 #pragma unroll
-    for (int r = 1; r < 4; r++)
-#pragma unroll
-        for (int c = 0; c < r; c++) {
-            double t = -m[r][c];
-#pragma unroll
-            for (int k = c + 1; k < r; k++) t = fma(-m[r][k], li[k][c], t);
-            li[r][c] = t;
-        }
-    if (lane == 0) {
-#pragma unroll
-        for (int r = 1; r < 4; r++)
-#pragma unroll
-            for (int c = 0; c < r; c++) sh.blk[4 * r + c] = li[r][c];
-        if (clamp) sh.clamped = 1;
+        for (int c = 0; c < 16; c++) dt[a][c] = t[c];
+        sh.inv[K & 1][a] = myy;
+        sh.d[16 * K + a] = myd;
+        sh.dm[16 * K + a] = myck ? 1.0 : 0.0;
+        if (myck) sh.clamped = 1;
     }
-    // LDS operations of one wave complete in order: read the block back
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int c4 = i - 4 * h;
-    const double bv = sh.blk[4 * g + (c4 & 3)];
-    if (c4 >= 0 && c4 < 4) set4(x, h, bv);
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 4; r++) x[r] = dt[4 * r + g][i];
 }
 
-// C: subtract the rank-4 product of block kb from tile (P, Q).
-__device__ __forceinline__ void chol_update_tile(f64x4& x, int P, int Q, int kb,
-                                                 const CholShared& sh) {
-    // lane index read afresh at every call: the compiler would otherwise keep
-    // the LDS addresses of every tile alive across the loop over blocks
+// The lane index read afresh at every call: the compiler would otherwise keep
+// the LDS addresses of every tile alive across the loop over tile columns.
+__device__ __forceinline__ int fresh_lane() {
     int lane;
     asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"((int)threadIdx.x));
-    const int g = (lane >> 4) & 3, i = lane & 15;
-    const int T = kb >> 2;
-    const int a = 16 * P + i, b = 16 * Q + i, k = 4 * kb + g;
-    const double ma = a > 4 * kb + 3 ? sh.w[g][a] * sh.inv[kb & 1][g] : 0.0;
-    const double wb = sh.w[g][b];
-    const double we = b < k ? wb : (b == k ? 1.0 : 0.0);
-    if (Q > P) {
-        x = mfma_f64(-ma, wb, x);
-    } else if (Q < P) {
-        x = mfma_f64(-ma, we, x);
+    return lane & 63;
+}
+
+// B: tile (K, Q) <- L_K^{-1} X_KQ, published to the tile row.
+__device__ __forceinline__ void chol_row_tile(f64x4& x, int Q, int K, CholShared& sh) {
+    const int lane = fresh_lane(), g = lane >> 4, i = lane & 15;
+    const double (*dt)[17] = sh.dt[K & 1];
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        const int c = 4 * s + g;  // A[i][c] = L_K^{-1}[i][c]; B = rows 4 s .. 4 s + 3 of x
+        const double la = c < i ? dt[i][c] : (c == i ? 1.0 : 0.0);
+        acc = mfma_f64(la, x[s], acc);
+    }
+    x = acc;
+#pragma unroll
+    for (int r = 0; r < 4; r++) sh.w[4 * r + g][16 * Q + i] = x[r];
+}
+
+// C: tile (P, Q) below tile row K subtracts sum_k (v_k[a] / d_k) w_k[b].
+__device__ __forceinline__ void chol_update_tile(f64x4& x, int P, int Q, int K,
+                                                 const CholShared& sh) {
+    const int lane = fresh_lane(), g = lane >> 4, i = lane & 15;
+    const double* inv = sh.inv[K & 1];
+    const double (*dt)[17] = sh.dt[K & 1];
+    if (Q == P) {
+        // diagonal tile: the upper triangle only (the lower one is E, still zero)
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int k = 4 * s + g;
+            acc = mfma_f64(sh.w[k][16 * P + i] * inv[k], sh.w[k][16 * Q + i], acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) x[r] -= i >= g + 4 * r ? acc[r] : 0.0;
     } else {
-        const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
-        const f64x4 du = mfma_f64(ma, wb, zero);
-        const f64x4 dl = P == T ? mfma_f64(ma, we, zero) : zero;
 #pragma unroll
-        for (int r = 0; r < 4; r++) x[r] -= i >= g + 4 * r ? du[r] : dl[r];
+        for (int s = 0; s < 4; s++) {
+            const int k = 4 * s + g;
+            const double ma = sh.w[k][16 * P + i] * inv[k];
+            const double wb = Q == K ? (i < k ? dt[k][i] : (i == k ? 1.0 : 0.0))
+                                     : sh.w[k][16 * Q + i];
+            x = mfma_f64(-ma, wb, x);
+        }
     }
-}
-
-__device__ __forceinline__ bool chol_tile_active(int P, int Q, int kb) {
-    const int T = kb >> 2;
-    if (P < T || (P == T && (kb & 3) == 3)) return false;  // no rows below the block
-    return Q >= P || Q <= T;  // E rows are zero right of the block
-}
-
-// One column block kb: B and C, with A of block kb + 1 on the wave that owns
-// the next diagonal tile.
-__device__ __forceinline__ void chol_step(f64x4 (&x)[CH_SLOTS], const int (&tp)[CH_SLOTS],
-                                          const int (&tq)[CH_SLOTS], int kb, int nkb, int n,
-                                          double tol, int wave, int g, int i, CholShared& sh) {
-    const int T = kb >> 2, h = kb & 3;
-    // B. apply L1^{-1} to the block rows of tile row T, publish them
-    // L1^{-1}[i][g] (unit diagonal, zero above it), rows i < 4
-    const double la = i < 4 ? (g < i ? sh.blk[4 * i + g] : (g == i ? 1.0 : 0.0)) : 0.0;
-#pragma unroll
-    for (int s = 0; s < CH_SLOTS; s++) {
-        if (tp[s] != T) continue;
-        const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
-        const double xr = sel4(x[s], h);
-        const f64x4 dd = mfma_f64(la, xr, zero);
-        const bool keep = tq[s] == T && i >= 4 * h && i < 4 * h + 4;  // factored in A
-        const double v = keep ? xr : dd[0];
-        set4(x[s], h, v);
-        sh.w[g][16 * tq[s] + i] = v;
-    }
-    __syncthreads();
-    // C. rank-4 update; the next diagonal tile first, then its factor
-    const int kb1 = kb + 1;
-    const bool next = kb1 < nkb && wave == (kb1 >> 2);
-    if (next) {
-        chol_update_tile(x[0], kb1 >> 2, kb1 >> 2, kb, sh);
-        chol_factor4(x[0], kb1, n, tol, g, i, sh);
-    }
-#pragma unroll
-    for (int s = 0; s < CH_SLOTS; s++) {
-        if (tp[s] < 0 || (s == 0 && next)) continue;
-        if (chol_tile_active(tp[s], tq[s], kb)) chol_update_tile(x[s], tp[s], tq[s], kb, sh);
-    }
-    __syncthreads();
 }
 
 // Factor the n x n block (n <= 128) whose upper triangle is Gs (leading
@@ -264,15 +229,15 @@ __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: tile numbers in SGPRs
     const int W = blockDim.x >> 6;
     const int g = lane >> 4, i = lane & 15;
-    const int Tn = (n + 15) >> 4, nkb = (n + 3) >> 2;
+    const int Tn = (n + 15) >> 4;
     // padding rows: a pivot above the clamp threshold, nothing to eliminate
     const double padv = fmax(1.0, 2.0 * tol);
 
     // Tiles of the waves.  Wave t < Tn holds diagonal tile t in slot 0.  When
     // the other waves can hold every off-diagonal tile outside tile row 0,
-    // wave t also holds only tile (0, t), which is idle from block 3 on; the
-    // wave that factors the next 4 x 4 block then updates no other tile in
-    // that step.  Otherwise the off-diagonal tiles go round robin.
+    // wave t also holds only tile (0, t), which is idle after tile column 0;
+    // the wave that factors the next diagonal tile then updates no other tile
+    // in that step.  Otherwise the off-diagonal tiles go round robin.
     const bool owners_free = Tn <= 7 && (Tn - 1) * (Tn - 1) <= CH_SLOTS * (W - Tn);
     int tp[CH_SLOTS], tq[CH_SLOTS];
     f64x4 x[CH_SLOTS];
@@ -314,9 +279,32 @@ __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
     }
     if (tid == 0) sh.clamped = 0;
     __syncthreads();
-    if (wave == 0) chol_factor4(x[0], 0, n, tol, g, i, sh);
-    __syncthreads();
-    for (int kb = 0; kb < nkb; kb++) chol_step(x, tp, tq, kb, nkb, n, tol, wave, g, i, sh);
+    for (int K = 0; K < Tn; K++) {
+        // C of tile column K - 1 (after its B), with A of tile column K: the
+        // owner of diagonal tile K updates it first and factors it, then the
+        // other tiles are updated
+        const bool own = wave == K;
+        if (own) {
+            if (K > 0) chol_update_tile(x[0], K, K, K - 1, sh);
+            chol_factor16(x[0], K, n, tol, g, i, sh);
+        }
+        if (K > 0) {
+            const int Kp = K - 1;
+#pragma unroll
+            for (int s = 0; s < CH_SLOTS; s++) {
+                if (tp[s] <= Kp || (s == 0 && own)) continue;
+                // E tiles right of tile column Kp are still zero
+                if (tq[s] >= tp[s] || tq[s] <= Kp) chol_update_tile(x[s], tp[s], tq[s], Kp, sh);
+            }
+        }
+        __syncthreads();
+        // B. the rest of tile row K
+#pragma unroll
+        for (int s = 0; s < CH_SLOTS; s++)
+            if (tp[s] == K && tq[s] != K) chol_row_tile(x[s], tq[s], K, sh);
+        __syncthreads();
+    }
+    // C of the last tile column has no rows below it
     if (tid == 0 && sh.clamped) *clamped = 1;
     for (int a = tid; a < n; a += blockDim.x) {
         const double sq = sqrt(sh.d[a]);
