@@ -106,6 +106,32 @@ def test_f64_ragged_shapes(cu, dev, orc, m, n, k, p, q, lda_pad):
     assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
 
 
+@pytest.mark.parametrize("l", [2, 17, 31, 48, 64, 97, 112, 113, 120, 128])
+def test_f64_core_small_sizes(cu, dev, orc, l):
+    """l x l stages up to 128 columns in one work-group: the Cholesky with one
+    to eight 16-column tiles (full and ragged; 113 .. 128 take the round-robin
+    tile map) and every register-resident QRCP width (l <= 16, 32, 64, 128)."""
+    import torch
+
+    m, n = 400, 360
+    a, _ = I.lowrank(m, n, np.exp(-np.arange(1, n + 1) / 40.0), seed=1000 + l)
+    p = 1 if l < 4 else 3
+    k, q = l - p, 1
+    om = I.gaussian_omega(n, l, 4)
+    gpu = _run_gpu(cu, dev, torch.from_numpy(a).to(dev), k, p, q, om)
+    mg, mo, ref = _compare_f64(orc, a, k, p, q, om, gpu, f"core l={l}")
+    U, T, V, perm, info = gpu
+    assert abs(mg["err_l"] - mo["err_l"]) <= 1e-12
+    assert abs(mg["err_k"] - mo["err_k"]) <= 1e-12
+    assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
+    assert np.array_equal(np.tril(T, -1), np.zeros_like(T))
+    assert np.all(np.diag(T) >= 0)
+    if ref["diag"][1] > 1e-8:
+        assert np.array_equal(perm, ref["perm"])
+        d = np.abs(np.diag(ref["T"]))
+        assert np.abs(np.diag(T) - d).max() <= 1e-10 * d.max()
+
+
 @pytest.mark.parametrize("l", [130, 150, 170, 185, 200, 224, 240, 260])
 def test_f64_core_qrcp_sizes(cu, dev, orc, l):
     """l x l stages beyond 128 columns: every LDS row count of the register +
