@@ -217,12 +217,16 @@ __device__ __forceinline__ void chol_update_tile(f64x4& x, int P, int Q, int K,
 
 // Factor the n x n block (n <= 128) whose upper triangle is Gs (leading
 // dimension ld): R and R^{-1} of the block into Rout and Rinv (same leading
-// dimension), pivots clamped at tol; mark[a] = 1 where pivot a was clamped,
-// else 0.  Every thread of the work-group calls it;
-// the work-group has at least max(Tn, Tn^2 / 4) waves, Tn = ceil(n / 16).
+// dimension), and R also into Rcopy unless it is null; pivots clamped at
+// *tolp, an LDS word that the caller may still be writing when it calls (it
+// is read after the first barrier, so the tile loads overlap its
+// computation); mark[a] = 1 where pivot a was clamped, else 0.  Every thread
+// of the work-group calls it; the work-group has at least max(Tn, Tn^2 / 4)
+// waves, Tn = ceil(n / 16).
 __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
                                            double* __restrict__ Rout, double* __restrict__ Rinv,
-                                           int ld, double tol, int* clamped,
+                                           double* __restrict__ Rcopy, int ld,
+                                           const double* tolp, int* clamped,
                                            double* __restrict__ mark) {
     __shared__ CholShared sh;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -230,8 +234,6 @@ __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
     const int W = blockDim.x >> 6;
     const int g = lane >> 4, i = lane & 15;
     const int Tn = (n + 15) >> 4;
-    // padding rows: a pivot above the clamp threshold, nothing to eliminate
-    const double padv = fmax(1.0, 2.0 * tol);
 
     // Tiles of the waves.  Wave t < Tn holds diagonal tile t in slot 0.  When
     // the other waves can hold every off-diagonal tile outside tile row 0,
@@ -272,13 +274,22 @@ __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int a = 16 * P + g + 4 * r, b = 16 * Q + i;
-            double v = 0.0;
-            if (P >= 0 && a <= b) v = (b < n) ? Gs[a * ld + b] : (a == b ? padv : 0.0);
-            x[s][r] = v;
+            x[s][r] = (P >= 0 && a <= b && b < n) ? Gs[a * ld + b] : 0.0;
         }
     }
     if (tid == 0) sh.clamped = 0;
     __syncthreads();
+    const double tol = *tolp;
+    // padding rows: a pivot above the clamp threshold, nothing to eliminate
+    const double padv = fmax(1.0, 2.0 * tol);
+#pragma unroll
+    for (int s = 0; s < CH_SLOTS; s++)
+        if (tp[s] >= 0 && tp[s] == tq[s])
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int a = 16 * tp[s] + g + 4 * r;
+                if (a >= n && a == 16 * tq[s] + i) x[s][r] = padv;
+            }
     for (int K = 0; K < Tn; K++) {
         // C of tile column K - 1 (after its B), with A of tile column K: the
         // owner of diagonal tile K updates it first and factors it, then the
@@ -324,7 +335,9 @@ __device__ __forceinline__ void chol_block(const double* __restrict__ Gs, int n,
             if (a >= n || b >= n) continue;
             const double rsq = sh.rs[a];
             const double xv = x[s][r];
-            Rout[a * ld + b] = b > a ? xv * rsq : (b == a ? sh.sq[a] : 0.0);
+            const double rv = b > a ? xv * rsq : (b == a ? sh.sq[a] : 0.0);
+            Rout[a * ld + b] = rv;
+            if (Rcopy) Rcopy[a * ld + b] = rv;
             Rinv[b * ld + a] = b < a ? xv * rsq : (b == a ? rsq : 0.0);
         }
     }
@@ -509,14 +522,14 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
     } else if (tid == 0) {
         s_tol = P.rep[96];
     }
-    __syncthreads();
-    const double tol = s_tol;
+    // no barrier here: chol_block reads s_tol after its first one
     const int o = k * bs, n = min(bs, l - o);
-    chol_block(G + o * l + o, n, R + o * l + o, Ri + o * l + o, l, tol, &s_clamped_any, P.tau + o);
+    // one diagonal block: R of the first CholeskyQR pass is also kept in Racc
+    double* Rc = (nb == 1 && mode == CHOL_FIRST) ? P.Racc : nullptr;
+    chol_block(G + o * l + o, n, R + o * l + o, Ri + o * l + o, Rc, l, &s_tol, &s_clamped_any,
+               P.tau + o);
     __syncthreads();
     if (tid == 0 && s_clamped_any) atomicOr(P.flags, FLAG_RANK_DEF);
-    if (nb == 1 && mode == CHOL_FIRST)
-        for (int e = tid; e < l * l; e += nth) P.Racc[e] = R[e];
 }
 
 hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipStream_t s) {
