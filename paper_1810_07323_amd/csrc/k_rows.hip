@@ -43,6 +43,8 @@ __global__ __launch_bounds__(256) void k_omega(const Prob* __restrict__ probs,
                                                const int32_t* __restrict__ toff, int cnt) {
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
+    // the first stage of a decomposition: its flag word starts cleared
+    if (local == 0 && threadIdx.x == 0) *P.flags = 0;
     const int64_t total = P.n * P.l;
     const int64_t t = (int64_t)local * 256 + threadIdx.x;  // pair index
     const int64_t e = 2 * t;

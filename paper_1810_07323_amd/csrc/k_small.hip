@@ -1486,20 +1486,6 @@ hipError_t launch_report(const LaunchGroup& g, int phase, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_clear_flags(const Prob* __restrict__ probs, const int32_t* __restrict__ pidx,
-                              const int32_t* __restrict__ toff, int cnt) {
-    int local;
-    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
-    if (threadIdx.x == 0) *P.flags = 0;
-}
-
-hipError_t launch_clear_flags(const LaunchGroup& g, hipStream_t s) {
-    if (g.blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_clear_flags, dim3(g.blocks), dim3(64), 0, s, g.probs, g.pidx, g.toff,
-                       g.count);
-    return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // Format conversion of a stored FP32 matrix (cor_quantize).
 // ---------------------------------------------------------------------------

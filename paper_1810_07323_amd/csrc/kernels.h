@@ -61,7 +61,6 @@ hipError_t launch_r2(const LaunchGroup& g, int iter, hipStream_t s);  // blocks:
 hipError_t launch_form_qs(const LaunchGroup& g, int l, hipStream_t s);
 hipError_t launch_report(const LaunchGroup& g, int phase, hipStream_t s);
 hipError_t launch_normA(const LaunchGroup& g, hipStream_t s);
-hipError_t launch_clear_flags(const LaunchGroup& g, hipStream_t s);
 
 // Stand-alone helpers of the C ABI.
 hipError_t launch_quantize(const float* a32, int64_t m, int64_t n, int64_t lda, int to, void* out,

@@ -522,7 +522,6 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         if (e_ != hipSuccess) return e_;       \
     } while (0)
     const bool fp8 = (P->prec_mix >> P_FP8) & 1;
-    E(launch_clear_flags(P->small.g, s));
     if (P->report) E(launch_normA(P->norm.g, s));
     E(launch_omega(P->omega.g, s));  // Q2 <- Omega (FP64)
     if (fp8) E(launch_op_scales(P->small.g, SIDE_N, 0, s));
