@@ -86,56 +86,6 @@ hipError_t launch_omega_raw(uint64_t seed, int64_t n, int32_t l, double* out, hi
 }
 
 // ---------------------------------------------------------------------------
-// Rank-deficient sketch at the final orthonormalisation (a sketch of rank
-// below l, e.g. rank(A) < l): column j of the first CholeskyQR factor Qa
-// whose pivot was clamped (marker tau[j] = 1, written by the Cholesky) spans
-// no direction of Y.  It is replaced by a Gaussian column of norm about 1
-// (its own counter-based stream) and row j of the accumulated R is zeroed, so
-// that the second pass makes Q orthonormal while Q R still reproduces Y.  A
-// full-rank sketch leaves everything untouched.  One block per problem.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_fix_deficient(const Prob* __restrict__ probs,
-                                                       const int32_t* __restrict__ pidx,
-                                                       const int32_t* __restrict__ toff, int cnt,
-                                                       int side, int iter) {
-    __shared__ int s_def[LMAX];
-    __shared__ int s_any;
-    int local;
-    const Prob& P = group_prob(probs, pidx, toff, cnt, local);
-    if (iter >= 0 && iter > P.q) return;
-    if (!second_pass(P, iter)) return;
-    const int l = P.l;
-    const int64_t rows = side == SIDE_M ? P.m : P.n;
-    if (threadIdx.x == 0) s_any = 0;
-    __syncthreads();
-    for (int j = threadIdx.x; j < l; j += 256) {
-        const int d = P.tau[j] != 0.0;
-        s_def[j] = d;
-        if (d) s_any = 1;
-    }
-    __syncthreads();
-    if (!s_any) return;
-    const uint64_t stream = P.seed ^ (side == SIDE_M ? 0x6A09E667F3BCC908ull : 0xBB67AE8584CAA73Bull);
-    const double sc = 1.0 / sqrt((double)rows);
-    for (int64_t r = threadIdx.x; r < rows; r += 256)
-        for (int j = 0; j < l; j++)
-            if (s_def[j]) {
-                double z0, z1;
-                gauss_pair(stream, (uint64_t)(r * l + j), z0, z1);
-                P.Qa[r * l + j] = z0 * sc;
-            }
-    for (int e = threadIdx.x; e < l * l; e += 256)
-        if (s_def[e / l]) P.Racc[e] = 0.0;
-}
-
-hipError_t launch_fix_deficient(const LaunchGroup& g, int side, int iter, hipStream_t s) {
-    if (g.blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fix_deficient, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff,
-                       g.count, side, iter);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Operand copy of an FP64 factor F (rows x l, row-major) in the pass format,
 // stored transposed: op[c][r], c < lp, r < ld; zero outside rows x l.
 // n-side (Omega / Q2): FP8 folds the column scale of A into the rows first.
@@ -588,6 +538,48 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
             for (int e = 0; e < 4; e++)
                 xs[(lg + 4 * e) * lp + 16 * (ct0 + t) + li] = acc[t][e];
     __syncthreads();
+    if (MODE == AP_Y_RINV_QA && two) {
+        // First factor of the final orthonormalisation.  Rank-deficient
+        // sketch (rank below l, e.g. rank(A) < l): column j whose Cholesky
+        // pivot was clamped (marker tau[j] = 1) spans no direction of Y; it
+        // becomes a Gaussian column of norm about 1 (its own counter-based
+        // stream) and row j of the accumulated R is zeroed, so the second
+        // pass makes Q orthonormal while Q R still reproduces Y.  A full-rank
+        // sketch leaves everything untouched.
+        const uint64_t stream =
+            P.seed ^ (side == SIDE_M ? 0x6A09E667F3BCC908ull : 0xBB67AE8584CAA73Bull);
+        const double sc = 1.0 / sqrt((double)rows);
+        constexpr int NQ = (LMAX + 63) / 64;  // columns per lane
+        bool def[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; q++) def[q] = lane + 64 * q < l && P.tau[lane + 64 * q] != 0.0;
+        for (int r = wave; r < nrows; r += 4)
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                const int c = lane + 64 * q;
+                if (c >= l) break;
+                double v = xs[r * lp + c];
+                if (def[q]) {
+                    double z0, z1;
+                    gauss_pair(stream, (uint64_t)((r0 + r) * l + c), z0, z1);
+                    v = z0 * sc;
+                }
+                dst[(r0 + r) * l + c] = v;
+            }
+        if (local == 0)
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                // rows j = 64 q + bit of the clamped pivots, wave j % 4 each
+                unsigned long long mk = __ballot(def[q]);
+                while (mk) {
+                    const int j = 64 * q + __ffsll((long long)mk) - 1;
+                    mk &= mk - 1;
+                    if ((j & 3) == wave)
+                        for (int c = lane; c < l; c += 64) P.Racc[j * l + c] = 0.0;
+                }
+            }
+        return;
+    }
     for (int r = wave; r < nrows; r += 4)
         for (int c = lane; c < l; c += 64) dst[(r0 + r) * l + c] = xs[r * lp + c];
     if (op && P.prec != P_FP8) {

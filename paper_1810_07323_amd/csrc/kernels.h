@@ -45,9 +45,6 @@ enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2,
 hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int iter,
                         hipStream_t s);
 hipError_t launch_gather_v(const LaunchGroup& g, hipStream_t s);  // blocks: ceil(n*l/256)
-// Columns of Qa with a clamped pivot -> Gaussian columns, rows of Racc -> 0
-// (final orthonormalisation only); one block per problem.
-hipError_t launch_fix_deficient(const LaunchGroup& g, int side, int iter, hipStream_t s);
 // Column maxima of the FP64 factor and FP8 operand scales.
 hipError_t launch_op_scales(const LaunchGroup& g, int side, int iter, hipStream_t s);
 

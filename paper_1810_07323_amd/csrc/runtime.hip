@@ -244,7 +244,6 @@ struct Plan {
         double bytes = 0, flops = 0;  // algorithmic cost of one launch
     };
     Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, applyM, applyN, vg, r2, norm;
-    Grp fixM, fixN;  // replacement of the clamped directions of a rank-deficient sketch
     std::vector<Grp> skAX, skATX;  // per (precision, column tiles)
     std::vector<Grp> formU;        // per register-tile class of l (nt holds l)
     Grp applyU;                    // U = Q1 Qs for the problems with u_via_qs
@@ -483,7 +482,6 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->small = mk(R_small);
     P->applyM = mk(R_applyM); P->applyN = mk(R_applyN); P->applyU = mk(R_applyU);
     P->vg = mk(R_vg); P->r2 = mk(R_r2); P->norm = mk(R_norm);
-    P->fixM = mk(R_small); P->fixN = P->fixM;
     for (auto& u : urefs) {
         Plan::Grp g = mk(u.r);
         g.nt = u.lmax;
@@ -535,7 +533,6 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
         E(launch_apply(P->applyM.g, SIDE_M, AP_Y_RINV_QA, P->lmax, it, s));
         if (P->second[it]) {
-            E(launch_fix_deficient(P->fixM.g, SIDE_M, it, s));
             E(launch_gram(P->gramM.g, SIDE_M, GSRC_QA, it, s));
             E(launch_gram_reduce(P->redM.g, SIDE_M, 1, it, s));
             E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
@@ -553,7 +550,6 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
         E(launch_apply(P->applyN.g, SIDE_N, AP_Y_RINV_QA, P->lmax, it, s));
         if (P->second[it]) {
-            E(launch_fix_deficient(P->fixN.g, SIDE_N, it, s));
             E(launch_gram(P->gramN.g, SIDE_N, GSRC_QA, it, s));
             E(launch_gram_reduce(P->redN.g, SIDE_N, 1, it, s));
             E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
