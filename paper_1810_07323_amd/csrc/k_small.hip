@@ -576,21 +576,34 @@ __global__ __launch_bounds__(256) void k_r2(const Prob* __restrict__ probs,
     int local;
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
     if (iter != P.q) return;  // only the R factor of the last Y2 is used
+    // Rows 16 ta .. 16 ta + 15 of R and columns 16 tb .. 16 tb + 15 of Racc
+    // through LDS: every load of the block is in flight at once.
+    __shared__ double sa[16][LPMAX + 1];
+    __shared__ double sb[LPMAX][17];
     const int l = P.l, nt = P.lp / 16;
     const int ta = local / nt, tb = local % nt;
+    for (int e = threadIdx.x; e < 16 * l; e += 256) {
+        const int r = e / l, c = e - r * l;
+        sa[r][c] = 16 * ta + r < l ? P.R[(16 * ta + r) * l + c] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 16 * l; e += 256) {
+        const int t = e >> 4, j = e & 15;
+        sb[t][j] = 16 * tb + j < l ? P.Racc[t * l + 16 * tb + j] : 0.0;
+    }
+    __syncthreads();
     const int a = ta * 16 + (threadIdx.x >> 4), b = tb * 16 + (threadIdx.x & 15);
     if (a >= l || b >= l) return;
-    const double* __restrict__ Ra = P.R + a * l;
-    const double* __restrict__ Rb = P.Racc + b;
+    const double* Ra = sa[threadIdx.x >> 4];
+    const int jb = threadIdx.x & 15;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int t = a;
     for (; t + 3 <= b; t += 4) {
-        s0 += Ra[t] * Rb[t * l];
-        s1 += Ra[t + 1] * Rb[(t + 1) * l];
-        s2 += Ra[t + 2] * Rb[(t + 2) * l];
-        s3 += Ra[t + 3] * Rb[(t + 3) * l];
+        s0 += Ra[t] * sb[t][jb];
+        s1 += Ra[t + 1] * sb[t + 1][jb];
+        s2 += Ra[t + 2] * sb[t + 2][jb];
+        s3 += Ra[t + 3] * sb[t + 3][jb];
     }
-    for (; t <= b; t++) s0 += Ra[t] * Rb[t * l];
+    for (; t <= b; t++) s0 += Ra[t] * sb[t][jb];
     P.R2[a * l + b] = (s0 + s1) + (s2 + s3);
 }
 
