@@ -89,6 +89,8 @@ hipError_t launch_omega_raw(uint64_t seed, int64_t n, int32_t l, double* out, hi
 // Operand copy of an FP64 factor F (rows x l, row-major) in the pass format,
 // stored transposed: op[c][r], c < lp, r < ld; zero outside rows x l.
 // n-side (Omega / Q2): FP8 folds the column scale of A into the rows first.
+// A block transposes one tile through LDS, so that both the reads of F and
+// the writes of op are contiguous runs.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T conv_op(double v, float scale_inv);
@@ -98,40 +100,59 @@ template <> __device__ __forceinline__ uint16_t conv_op<uint16_t>(double v, floa
 template <> __device__ __forceinline__ uint8_t conv_op<uint8_t>(double v, float sinv) { return f32_to_e4m3((float)v * sinv); }
 
 template <typename T>
-__device__ void make_op_body(const Prob& P, int side, int64_t local) {
+__device__ void make_op_body(const Prob& P, int side, int64_t local, double (*tile)[MO_ROWS + 1]) {
     const int64_t rows = side == SIDE_M ? P.m : P.n;
     const int64_t ld = side == SIDE_M ? P.ldq : P.ldx;
     const double* F = side == SIDE_M ? P.Q1 : P.Q2;
     T* op = reinterpret_cast<T*>(side == SIDE_M ? P.qop : P.xop);
     const float* sc = side == SIDE_M ? P.qscale : P.xscale;
-    const int64_t idx = local * 256 + threadIdx.x;
-    if (idx >= (int64_t)P.lp * ld) return;
-    const int c = (int)(idx / ld);
-    const int64_t r = idx % ld;
-    T v = T(0);
-    if (c < P.l && r < rows) {
-        double x = F[r * P.l + c];
-        float sinv = 1.0f;
-        if constexpr (std::is_same<T, uint8_t>::value) {
-            if (side == SIDE_N) x *= (double)P.colscale[r];
-            sinv = 1.0f / sc[c];
-        }
-        v = conv_op<T>(x, sinv);
+    const int l = P.l;
+    const int64_t nrt = (ld + MO_ROWS - 1) / MO_ROWS;
+    const int64_t r0 = (local % nrt) * MO_ROWS;
+    const int c0 = (int)(local / nrt) * MO_COLS;
+    const int tid = threadIdx.x;
+    // read MO_ROWS rows x MO_COLS columns of F, each row segment contiguous
+#pragma unroll
+    for (int p = 0; p < MO_ROWS * MO_COLS / 256; p++) {
+        const int rr = p * (256 / MO_COLS) + tid / MO_COLS, cc = tid % MO_COLS;
+        const int64_t r = r0 + rr;
+        const int c = c0 + cc;
+        tile[cc][rr] = (r < rows && c < l) ? F[r * l + c] : 0.0;
     }
-    op[idx] = v;
+    __syncthreads();
+    // write them transposed: op[c][r], each column segment contiguous
+#pragma unroll
+    for (int p = 0; p < MO_ROWS * MO_COLS / 256; p++) {
+        const int cc = p * (256 / MO_ROWS) + tid / MO_ROWS, rr = tid % MO_ROWS;
+        const int64_t r = r0 + rr;
+        const int c = c0 + cc;
+        if (r >= ld) continue;
+        T v = T(0);
+        if (c < l && r < rows) {
+            double x = tile[cc][rr];
+            float sinv = 1.0f;
+            if constexpr (std::is_same<T, uint8_t>::value) {
+                if (side == SIDE_N) x *= (double)P.colscale[r];
+                sinv = 1.0f / sc[c];
+            }
+            v = conv_op<T>(x, sinv);
+        }
+        op[(int64_t)c * ld + r] = v;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_make_op(const Prob* __restrict__ probs,
                                                  const int32_t* __restrict__ pidx,
                                                  const int32_t* __restrict__ toff, int cnt,
                                                  int side) {
+    __shared__ double tile[MO_COLS][MO_ROWS + 1];
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     switch (P.prec) {
-        case P_F64: make_op_body<double>(P, side, local); break;
-        case P_F32: make_op_body<float>(P, side, local); break;
-        case P_BF16: make_op_body<uint16_t>(P, side, local); break;
-        default: make_op_body<uint8_t>(P, side, local); break;
+        case P_F64: make_op_body<double>(P, side, local, tile); break;
+        case P_F32: make_op_body<float>(P, side, local, tile); break;
+        case P_BF16: make_op_body<uint16_t>(P, side, local, tile); break;
+        default: make_op_body<uint8_t>(P, side, local, tile); break;
     }
 }
 

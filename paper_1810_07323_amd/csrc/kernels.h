@@ -38,6 +38,10 @@ constexpr int GRAM_THREADS = 256;
 hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStream_t s);
 hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int iter,
                               hipStream_t s);
+// Operand copies: tiles of MO_ROWS rows x MO_COLS columns per block, blocks
+// per problem ceil(ld / MO_ROWS) * (lp / MO_COLS).
+constexpr int MO_ROWS = 64;
+constexpr int MO_COLS = 16;
 // dst = src R^{-1}, row blocks of APPLY_ROWS; lmax = largest l of the group.
 constexpr int APPLY_ROWS = 16;
 enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2,

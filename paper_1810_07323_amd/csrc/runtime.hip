@@ -322,8 +322,8 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         return tb.add(all, b);
     };
     auto R_omega = per([&](int i) { return cdiv(cdiv(probs[i].n * P->lay[i].l, 2), 256); });
-    auto R_opM = per([&](int i) { return cdiv(P->lay[i].lp * P->lay[i].ldq, 256); });
-    auto R_opN = per([&](int i) { return cdiv(P->lay[i].lp * P->lay[i].ldx, 256); });
+    auto R_opM = per([&](int i) { return cdiv(P->lay[i].ldq, MO_ROWS) * (P->lay[i].lp / MO_COLS); });
+    auto R_opN = per([&](int i) { return cdiv(P->lay[i].ldx, MO_ROWS) * (P->lay[i].lp / MO_COLS); });
     auto R_sumM = per([&](int i) { return cdiv(probs[i].m * P->lay[i].lp / 4, 256); });
     auto R_sumN = per([&](int i) { return cdiv(probs[i].n * P->lay[i].lp / 4, 256); });
     auto R_gramM = per([&](int i) { return (int64_t)P->lay[i].gb_m * gram_groups(P->lay[i].lp); });
