@@ -236,16 +236,25 @@ __global__ __launch_bounds__(256) void k_sum(const Prob* __restrict__ probs,
             acc[0] += (double)u.x; acc[1] += (double)u.y; acc[2] += (double)u.z; acc[3] += (double)u.w;
         }
     }
+    if (P.prec == P_FP8) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int c = min(c0 + e, l - 1);
+            acc[e] *= side == SIDE_M ? (double)P.xscale[c]
+                                     : (double)P.colscale[r] * (double)P.qscale[c];
+        }
+    }
+    double* y = P.Y + r * l + c0;
+    if ((l & 1) == 0 && c0 + 4 <= l) {
+        // even l: the four entries are two aligned 16-byte stores
+        reinterpret_cast<double2*>(y)[0] = make_double2(acc[0], acc[1]);
+        reinterpret_cast<double2*>(y)[1] = make_double2(acc[2], acc[3]);
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-        const int c = c0 + e;
-        if (c >= l) break;
-        double v = acc[e];
-        if (P.prec == P_FP8) {
-            if (side == SIDE_M) v *= (double)P.xscale[c];
-            else v *= (double)P.colscale[r] * (double)P.qscale[c];
-        }
-        P.Y[r * l + c] = v;
+        if (c0 + e >= l) break;
+        y[e] = acc[e];
     }
 }
 
