@@ -412,9 +412,12 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const Prob* __restrict__ pr
     const int e = local * 64 + lane;
     const int nb = side == SIDE_M ? P.gb_m : P.gb_n;
     double s = 0.0;
-    if (e < l * l) {
-        const int a = e / l, b = e % l;
-        const int64_t o = (int64_t)min(a, b) * l + max(a, b);
+    // upper entries only (contiguous reads of the partials); each is also
+    // written to its mirror position
+    const int a = e / l, b = e - (e / l) * l;
+    const bool up = e < l * l && a <= b;
+    if (up) {
+        const int64_t o = (int64_t)a * l + b;
         const int64_t ll = (int64_t)l * l;
         double s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int c = wave;
@@ -429,9 +432,10 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const Prob* __restrict__ pr
     }
     part[wave][lane] = s;
     __syncthreads();
-    if (wave == 0 && e < l * l) {
+    if (wave == 0 && up) {
         const double g = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
         P.G[e] = g;
+        if (a != b) P.G[(int64_t)b * l + a] = g;
         if (!isfinite(g)) atomicOr(P.flags, FLAG_NONFINITE);
     }
 }
