@@ -54,7 +54,7 @@ typedef enum {
     COR_E_INVAL = 1,    /* bad argument (shape, rank parameters, null pointer, lda)        */
     COR_E_NOMEM = 2,    /* device or host allocation failed                                 */
     COR_E_DEVICE = 3,   /* a HIP call failed                                                */
-    COR_E_NUMERIC = 4,  /* non-finite input or a Cholesky breakdown that survived the retry */
+    COR_E_NUMERIC = 4,  /* a non-finite value reached a Gram matrix (NaN/Inf in A)          */
     COR_E_BUSY = 5,     /* served request still running (cor_server_poll)                   */
     COR_E_NOTFOUND = 6  /* unknown ticket                                                   */
 } cor_status;
@@ -70,11 +70,12 @@ typedef enum {
                    /* A[i][j] ~ fp8(code[i][j]) * colscale[j]                       */
 } cor_prec;
 
-/* cor_info.flags */
-#define COR_FLAG_CHOL_RETRY 1     /* a Cholesky factorisation needed the shifted retry */
-#define COR_FLAG_RANK_DEFICIENT 2 /* a sketch was numerically rank deficient (the
-                                     * final factors are still orthonormal: the missing
-                                     * directions are completed with Gaussian columns)   */
+/* cor_info.flags (bit 0 is unused).  A Cholesky pivot of a sketch's Gram
+ * matrix at or below l 2^-52 max_i G_ii (a numerically rank-deficient sketch,
+ * or one too ill-conditioned for CholeskyQR) is clamped to that threshold;
+ * at the final orthonormalisation the columns whose pivot was clamped are
+ * replaced by Gaussian columns, so U and V stay orthonormal. */
+#define COR_FLAG_RANK_DEFICIENT 2 /* a pivot was clamped in some orthonormalisation    */
 #define COR_FLAG_NONFINITE 4      /* a non-finite value reached a Gram matrix          */
 
 typedef struct {
@@ -110,9 +111,9 @@ typedef struct {
 } cor_opts;
 
 /* ---------------------------------------------------------------------------
- * Single decomposition (the paper's problem statement: "Input: matrix A,
- * integers k, l and q"; Alg. 3).  A has lda = n.  COR_FP8 needs a column scale
- * and is only reachable through cor_utv_ex.  Returns after the work on
+ * Single decomposition with the inputs of Alg. 3 (A, k, l = k + p, q) plus the
+ * seed of the Gaussian test matrix.  A has lda = n.  COR_FP8 needs a column
+ * scale and is only reachable through cor_utv_ex.  Returns after the work on
  * `stream` has completed; `info` may be NULL.
  * ------------------------------------------------------------------------- */
 cor_status cor_utv(const void* A, int64_t m, int64_t n, int32_t k, int32_t p, int32_t q,
@@ -149,10 +150,12 @@ cor_status cor_plan_destroy(cor_plan* plan);
 /* ---------------------------------------------------------------------------
  * Served decompositions with continuous batching.  A server thread admits
  * queued requests while their workspace fits the HBM budget and a slot is
- * free, runs every admitted request's pipeline concurrently on the device and
- * retires each request as soon as its own pipeline completes, so requests that
- * arrive while others run join without waiting for them.  A request's result
- * does not depend on what runs beside it (fixed reduction orders).
+ * free.  The requests admitted together form a round: one grouped launch per
+ * stage covers all of them, on a stream of its own, so rounds run
+ * concurrently on the device.  A round retires as soon as its own pipeline
+ * completes; requests that arrive while rounds run form the next round
+ * without waiting for the device to drain.  A request's result does not
+ * depend on what runs beside it (fixed reduction orders).
  * A, outputs and colscale must stay valid until the request completes.
  * ------------------------------------------------------------------------- */
 typedef struct cor_server cor_server;

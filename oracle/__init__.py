@@ -48,6 +48,9 @@ def lib():
         _lib.orc_qrcp.argtypes = [d, C.c_int32, d, d, i32, d]
         _lib.orc_cor_utv.argtypes = [d, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                      C.c_int32, d, d, d, d, i32, d, d, d, d, d]
+        _lib.orc_cor_utv_fmt.argtypes = [d, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
+                                         C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_int32,
+                                         d, d, d, d, i32, d]
         _lib.orc_metrics.argtypes = [d, C.c_int64, C.c_int64, C.c_int64, d, d, d, C.c_int32,
                                      C.c_int32, d]
         _lib.orc_gemm_nn.argtypes = [d, C.c_int64, C.c_int64, C.c_int64, d, C.c_int64,
@@ -139,6 +142,37 @@ def cor_utv(a, k: int, p: int, q: int, omega_arr, want_intermediates: bool = Fal
     if want_intermediates:
         out.update(Q1=Q1, Q2=Q2, M=M, R2=R2)
     return out
+
+
+FMT = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
+
+
+def cor_utv_fmt(aq, fmt: str, k: int, p: int, q: int, omega_arr, colscale=None):
+    """The method with the passes over A read in a storage format (orc_cor_utv_fmt).
+
+    aq: decoded stored values of A (FP8: decoded codes, A = aq diag(colscale)).
+    Returns dict(U, T, V, perm, diag)."""
+    aq = _f64(aq)
+    m, n = aq.shape
+    l = k + p
+    om = _f64(omega_arr)
+    if om.shape != (n, l):
+        raise ValueError("omega must be n x l")
+    cs = None
+    if fmt == "fp8":
+        cs_arr = np.ascontiguousarray(colscale, dtype=np.float32)
+        cs = cs_arr.ctypes.data_as(C.POINTER(C.c_float))
+    U = np.empty((m, l))
+    T = np.empty((l, l))
+    V = np.empty((n, l))
+    perm = np.empty(l, dtype=np.int32)
+    diag = np.zeros(4)
+    st = lib().orc_cor_utv_fmt(_dp(aq), m, n, n, FMT[fmt], cs, k, p, q, _dp(om), _dp(U),
+                               _dp(T), _dp(V), perm.ctypes.data_as(C.POINTER(C.c_int32)),
+                               _dp(diag))
+    if st:
+        raise ValueError("orc_cor_utv_fmt status %d" % st)
+    return dict(U=U, T=T, V=V, perm=perm, diag=diag)
 
 
 def metrics(a, U, T, V, k: int):

@@ -220,28 +220,87 @@ int orc_qrcp(const double* M, int32_t l, double* Qt, double* T, int32_t* perm, d
 /* Helpers for the diagnostics.                                              */
 /* ------------------------------------------------------------------------ */
 static double orth_loss(const double* Q, int64_t r, int32_t c) {
+    /* G = Q^T Q accumulated row by row: every entry still sums over i in
+     * increasing order, while the reads of Q stay contiguous. */
+    double* G = (double*)calloc((size_t)c * (size_t)c, sizeof(double));
+    if (!G) return NAN;
+    for (int64_t i = 0; i < r; i++) {
+        const double* qi = Q + i * (int64_t)c;
+        for (int32_t a = 0; a < c; a++) {
+            const double qa = qi[a];
+            double* ga = G + (int64_t)a * c;
+            for (int32_t b = 0; b < c; b++) ga[b] += qa * qi[b];
+        }
+    }
     double s = 0.0;
     for (int32_t a = 0; a < c; a++)
         for (int32_t b = 0; b < c; b++) {
-            double g = 0.0;
-            for (int64_t i = 0; i < r; i++) g += Q[IDX(i, a, c)] * Q[IDX(i, b, c)];
+            double g = G[IDX(a, b, c)];
             if (a == b) g -= 1.0;
             s += g * g;
         }
+    free(G);
     return sqrt(s);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Alg. 3 (Alg. 2 when q = 0).                                               */
 /* ------------------------------------------------------------------------ */
-int orc_cor_utv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t k, int32_t p,
-                int32_t q, const double* omega, double* U, double* T, double* V,
-                int32_t* perm, double* Q1o, double* Q2o, double* Mo, double* R2o,
-                double* diag) {
+/* Skinny operand of a pass in a stored-format mode: the FP64 factor F
+ * (r x l) as the pass reads it.  FP32: binary32 rounding; BF16: the binary32
+ * value rounded to bfloat16; FP8: F' = diag(rowscale) F (rowscale = the
+ * column scales of A on the n side, none on the m side), column scales
+ * t_c = max_r |binary32(F'[r][c])| / 448 (1 for a zero column) and codes
+ * E4M3(binary32(F'[r][c]) / t_c).  out receives the decoded values (without
+ * t), tsc the column scales (1 except in FP8). */
+static void quantize_operand(int32_t fmt, const double* F, int64_t r, int32_t l,
+                             const float* rowscale, double* out, double* tsc) {
+    for (int32_t c = 0; c < l; c++) tsc[c] = 1.0;
+    if (fmt == ORC_FMT_F32) {
+        for (int64_t i = 0; i < r * l; i++) out[i] = (double)(float)F[i];
+    } else if (fmt == ORC_FMT_BF16) {
+        for (int64_t i = 0; i < r * l; i++) out[i] = orc_bf16_to_f64(orc_bf16_from_f32((float)F[i]));
+    } else {
+        for (int32_t c = 0; c < l; c++) {
+            float mx = 0.0f;
+            for (int64_t i = 0; i < r; i++) {
+                double x = F[IDX(i, c, l)];
+                if (rowscale) x *= (double)rowscale[i];
+                float v = fabsf((float)x);
+                if (v > mx) mx = v;
+            }
+            const float t = mx > 0.0f ? mx / 448.0f : 1.0f;
+            tsc[c] = (double)t;
+            for (int64_t i = 0; i < r; i++) {
+                double x = F[IDX(i, c, l)];
+                if (rowscale) x *= (double)rowscale[i];
+                out[IDX(i, c, l)] = orc_fp8_to_f64(orc_fp8_from_f32((float)x / t));
+            }
+        }
+    }
+}
+
+/* Alg. 3 with the passes over A read in a storage format (FP64 when fmt is
+ * ORC_FMT_F64, which is the plain method).  Aq holds the decoded stored
+ * values of A (for FP8 the decoded codes, without the column scales).  In the
+ * other formats the two products are
+ *   C1 = Aq Xq diag(t)                       (Xq: quantize_operand of X, with
+ *                                             rowscale = colscale in FP8)
+ *   C2 = diag(colscale) Aq^T Q1q diag(t)     (Q1q: quantize_operand of Q1)
+ * with colscale = 1 outside FP8, and the compression is eq. (14) with the
+ * operand the pass read on the left, D = Q1q^T (A Q2) (in exact arithmetic
+ * the R2^T of that second sketch).  U, T, V are assembled from the FP64
+ * factors as in eq. (16). */
+static int cor_utv_core(const double* A, int64_t m, int64_t n, int64_t lda, int32_t fmt,
+                        const float* colscale, int32_t k, int32_t p, int32_t q,
+                        const double* omega, double* U, double* T, double* V, int32_t* perm,
+                        double* Q1o, double* Q2o, double* Mo, double* R2o, double* diag) {
     const int32_t l = k + p;
     const int64_t mn = m < n ? m : n;
     if (k < 1 || p < 0 || q < 0 || l < 2 || (int64_t)l >= mn || lda < n) return ORC_EINVAL;
     if (!A || !omega || !U || !T || !V || !perm) return ORC_EINVAL;
+    if (fmt < ORC_FMT_F64 || fmt > ORC_FMT_FP8 || (fmt == ORC_FMT_FP8 && !colscale))
+        return ORC_EINVAL;
 
     size_t sz_m = sizeof(double) * (size_t)m * (size_t)l;
     size_t sz_n = sizeof(double) * (size_t)n * (size_t)l;
@@ -262,20 +321,72 @@ int orc_cor_utv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t k, i
         return ORC_ENOMEM;
     }
     memcpy(X, omega, sz_n);
+    /* Operands of the stored-format passes (unused in FP64). */
+    double* Xq = NULL;
+    double* Q1q = NULL;
+    double* tsc = NULL;
+    if (fmt != ORC_FMT_F64) {
+        Xq = (double*)malloc(sz_n);
+        Q1q = (double*)malloc(sz_m);
+        tsc = (double*)malloc(sizeof(double) * (size_t)l);
+        if (!Xq || !Q1q || !tsc) {
+            free(Xq); free(Q1q); free(tsc);
+            free(X); free(Y1); free(Q1); free(R1); free(Y2);
+            free(Q2); free(R2); free(Z); free(M); free(Qt);
+            return ORC_ENOMEM;
+        }
+    }
+    const float* rs = fmt == ORC_FMT_FP8 ? colscale : NULL;
 
     /* Power loop (Alg. 3): C1 = A C2, C2 = A^T C1, q + 1 times, each product
      * orthonormalised before it is used. */
     for (int32_t it = 0; it <= q; it++) {
-        orc_gemm_nn(A, m, n, lda, X, l, l, Y1);    /* C1 = A X        */
+        if (fmt == ORC_FMT_F64) {
+            orc_gemm_nn(A, m, n, lda, X, l, l, Y1);    /* C1 = A X        */
+        } else {
+            quantize_operand(fmt, X, n, l, rs, Xq, tsc);
+            orc_gemm_nn(A, m, n, lda, Xq, l, l, Y1);
+            for (int64_t i = 0; i < m; i++)
+                for (int32_t c = 0; c < l; c++) Y1[IDX(i, c, l)] *= tsc[c];
+        }
         orc_qr(Y1, m, l, l, Q1, R1);               /* C1 = Q1 R1      */
-        orc_gemm_tn(A, m, n, lda, Q1, l, l, Y2);   /* C2 = A^T Q1     */
+        if (fmt == ORC_FMT_F64) {
+            orc_gemm_tn(A, m, n, lda, Q1, l, l, Y2);   /* C2 = A^T Q1     */
+        } else {
+            quantize_operand(fmt, Q1, m, l, NULL, Q1q, tsc);
+            orc_gemm_tn(A, m, n, lda, Q1q, l, l, Y2);
+            for (int64_t i = 0; i < n; i++)
+                for (int32_t c = 0; c < l; c++)
+                    Y2[IDX(i, c, l)] *= (rs ? (double)rs[i] : 1.0) * tsc[c];
+        }
         orc_qr(Y2, n, l, l, Q2, R2);               /* C2 = Q2 R2      */
         memcpy(X, Q2, sz_n);
     }
 
-    /* Compression D = Q1^T A Q2, eq. (14), by its definition. */
-    orc_gemm_nn(A, m, n, lda, Q2, l, l, Z);
-    orc_gemm_tn(Q1, m, l, l, Z, l, l, M);
+    /* Compression D = Q1^T A Q2, eq. (14), by its definition (with the left
+     * operand the second sketch read, in a stored format). */
+    if (fmt == ORC_FMT_F64) {
+        orc_gemm_nn(A, m, n, lda, Q2, l, l, Z);
+        orc_gemm_tn(Q1, m, l, l, Z, l, l, M);
+    } else {
+        double* Q2s = (double*)malloc(sz_n); /* diag(colscale) Q2: A = Aq diag(colscale) */
+        if (!Q2s) {
+            free(Xq); free(Q1q); free(tsc);
+            free(X); free(Y1); free(Q1); free(R1); free(Y2);
+            free(Q2); free(R2); free(Z); free(M); free(Qt);
+            return ORC_ENOMEM;
+        }
+        for (int64_t i = 0; i < n; i++)
+            for (int32_t c = 0; c < l; c++)
+                Q2s[IDX(i, c, l)] = (rs ? (double)rs[i] : 1.0) * Q2[IDX(i, c, l)];
+        orc_gemm_nn(A, m, n, lda, Q2s, l, l, Z);
+        orc_gemm_tn(Q1q, m, l, l, Z, l, l, M);
+        if (fmt == ORC_FMT_FP8)
+            for (int32_t a = 0; a < l; a++)
+                for (int32_t b = 0; b < l; b++) M[IDX(a, b, l)] *= tsc[a];
+        free(Q2s);
+    }
+    free(Xq); free(Q1q); free(tsc);
 
     double gap = 1.0;
     orc_qrcp(M, l, Qt, T, perm, &gap);            /* D P~ = Q~ R~     */
@@ -308,14 +419,31 @@ int orc_cor_utv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t k, i
     return ORC_OK;
 }
 
+int orc_cor_utv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t k, int32_t p,
+                int32_t q, const double* omega, double* U, double* T, double* V,
+                int32_t* perm, double* Q1o, double* Q2o, double* Mo, double* R2o,
+                double* diag) {
+    return cor_utv_core(A, m, n, lda, ORC_FMT_F64, NULL, k, p, q, omega, U, T, V, perm, Q1o,
+                        Q2o, Mo, R2o, diag);
+}
+
+int orc_cor_utv_fmt(const double* Aq, int64_t m, int64_t n, int64_t lda, int32_t fmt,
+                    const float* colscale, int32_t k, int32_t p, int32_t q,
+                    const double* omega, double* U, double* T, double* V, int32_t* perm,
+                    double* diag) {
+    return cor_utv_core(Aq, m, n, lda, fmt, colscale, k, p, q, omega, U, T, V, perm, NULL, NULL,
+                        NULL, NULL, diag);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Accuracy report.                                                          */
 /* ------------------------------------------------------------------------ */
 void orc_metrics(const double* A, int64_t m, int64_t n, int64_t lda, const double* U,
                  const double* T, const double* V, int32_t l, int32_t k, double* out) {
-    /* W = T V^T (l x n). */
-    double* W = (double*)malloc(sizeof(double) * (size_t)l * (size_t)n);
-    if (!W) {
+    /* W = T V^T (l x n), stored transposed (Wt[j][a] = W[a][j]) so that the
+     * sums below run over contiguous memory. */
+    double* Wt = (double*)malloc(sizeof(double) * (size_t)l * (size_t)n);
+    if (!Wt) {
         out[0] = out[1] = out[2] = out[3] = NAN;
         return;
     }
@@ -323,15 +451,15 @@ void orc_metrics(const double* A, int64_t m, int64_t n, int64_t lda, const doubl
         for (int64_t j = 0; j < n; j++) {
             double s = 0.0;
             for (int32_t b = 0; b < l; b++) s += T[IDX(a, b, l)] * V[IDX(j, b, l)];
-            W[IDX(a, j, n)] = s;
+            Wt[IDX(j, a, l)] = s;
         }
     double na = 0.0, rl = 0.0, rk = 0.0;
     for (int64_t i = 0; i < m; i++) {
         for (int64_t j = 0; j < n; j++) {
             double hk = 0.0;
-            for (int32_t a = 0; a < k; a++) hk += U[IDX(i, a, l)] * W[IDX(a, j, n)];
+            for (int32_t a = 0; a < k; a++) hk += U[IDX(i, a, l)] * Wt[IDX(j, a, l)];
             double hl = hk;
-            for (int32_t a = k; a < l; a++) hl += U[IDX(i, a, l)] * W[IDX(a, j, n)];
+            for (int32_t a = k; a < l; a++) hl += U[IDX(i, a, l)] * Wt[IDX(j, a, l)];
             double x = A[IDX(i, j, lda)];
             na += x * x;
             rl += (x - hl) * (x - hl);
@@ -342,7 +470,7 @@ void orc_metrics(const double* A, int64_t m, int64_t n, int64_t lda, const doubl
     out[1] = na > 0.0 ? sqrt(rk / na) : 0.0;
     out[2] = orth_loss(U, m, l);
     out[3] = orth_loss(V, n, l);
-    free(W);
+    free(Wt);
 }
 
 /* ------------------------------------------------------------------------ */

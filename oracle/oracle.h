@@ -66,6 +66,21 @@ int orc_cor_utv(const double* A, int64_t m, int64_t n, int64_t lda, int32_t k, i
                 int32_t q, const double* omega, double* U, double* T, double* V,
                 int32_t* perm, double* Q1, double* Q2, double* M, double* R2, double* diag);
 
+/* Alg. 3 with the passes over A read in a storage format, as the reduced-
+ * precision modes compute it: fmt is ORC_FMT_F64 (the plain method),
+ * ORC_FMT_F32, ORC_FMT_BF16 or ORC_FMT_FP8.  Aq holds the decoded stored
+ * values of A (FP8: the decoded codes; A = Aq diag(colscale)).  Each pass
+ * reads its skinny operand in the same format (binary32; bfloat16 of the
+ * binary32 value; FP8 with per-column scales over diag(colscale) X on the n
+ * side), forms the product exactly in FP64 and applies the scales; the
+ * compression is D = Q1q^T A Q2 with Q1q the operand the second product read.
+ * Everything else is FP64 as in orc_cor_utv.  Outputs as orc_cor_utv. */
+enum { ORC_FMT_F64 = 0, ORC_FMT_F32 = 1, ORC_FMT_BF16 = 2, ORC_FMT_FP8 = 3 };
+int orc_cor_utv_fmt(const double* Aq, int64_t m, int64_t n, int64_t lda, int32_t fmt,
+                    const float* colscale, int32_t k, int32_t p, int32_t q,
+                    const double* omega, double* U, double* T, double* V, int32_t* perm,
+                    double* diag);
+
 /* Accuracy report: out[0] = ||A - U T V^T||_F / ||A||_F,
  * out[1] = ||A - U[:, :k] T[:k, :] V^T||_F / ||A||_F, out[2] = ||U^T U - I||_F,
  * out[3] = ||V^T V - I||_F. */

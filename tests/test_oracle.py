@@ -214,6 +214,124 @@ def test_compression_equals_r2_transpose_and_d_approx(orc):
     assert r["diag"][0] < 1e-13
 
 
+@pytest.mark.parametrize("q", [1, 2])
+def test_power_loop_matches_literal_alg3(orc, q):
+    # Alg. 3 as printed: C2 = Psi; q + 1 times C1 = A C2, C2 = A^T C1 (no QR
+    # inside the loop); then QR of C1 and C2, D = Q1^T A Q2 and the single-pass
+    # D_approx = Q1^T C1 (Q2^T C2_old)^+ with the C2 that produced the last C1.
+    # On a well-conditioned matrix (singular values in [1, 3]) the loop
+    # without re-orthonormalisation loses nothing, so the oracle's form
+    # (orthonormalise after every product, second sketch A^T Q1) must give
+    # the same sign-fixed Q1, Q2, the same D and the same T.
+    rng = np.random.default_rng(70 + q)
+    m, n, k, p = 40, 30, 4, 2
+    l = k + p
+    sig = np.linspace(3.0, 1.0, n)
+    u, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    v, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    a = (u * sig) @ v.T
+    om = I.gaussian_omega(n, l, 40 + q)
+    c2 = om.copy()
+    for _ in range(q + 1):
+        c2_old = c2
+        c1 = a @ c2
+        c2 = a.T @ c1
+    q1, _ = _signfix_qr(c1)
+    q2, _ = _signfix_qr(c2)
+    d = q1.T @ a @ q2
+    d_approx = q1.T @ c1 @ np.linalg.pinv(q2.T @ c2_old)
+    r = orc.cor_utv(a, k, p, q, om, want_intermediates=True)
+    assert np.abs(r["Q1"] - q1).max() < 1e-10
+    assert np.abs(r["Q2"] - q2).max() < 1e-10
+    assert np.abs(r["M"] - d).max() < 1e-10 * np.abs(d).max()
+    assert np.abs(d_approx - d).max() < 1e-10 * np.abs(d).max()
+    # T of the QRCP of the literal D (LAPACK geqp3, sign-fixed)
+    qd, td, pd = sla.qr(d, pivoting=True)
+    td = td * np.sign(np.diag(td))[:, None]
+    assert np.array_equal(r["perm"], pd)
+    assert np.abs(r["T"] - td).max() < 1e-10 * np.abs(td).max()
+
+
+def test_err_k_closed_form(orc):
+    # With M = Q1^T A Q2 formed explicitly, U^T A V = T, so the rank-k
+    # truncation U[:, :k] T[:k, :] V^T = P_k A P_V (P_k the projector on the
+    # first k columns of U, P_V on V) and, by Pythagoras,
+    # ||A - U[:, :k] T[:k, :] V^T||_F^2 = ||A||_F^2 - ||T[:k, :]||_F^2.
+    # The test matrix makes the k x (l - k) block T[:k, k:] large enough that
+    # truncating to T[:k, :k] instead would fail by a wide margin.
+    a, _ = I.lowrank(300, 200, 1.0 / np.arange(1, 201) ** 0.5, seed=31)
+    k, p = 10, 15
+    r = _run(orc, a, k, p, 0, seed=6)
+    met = orc.metrics(a, r["U"], r["T"], r["V"], k)
+    na2 = (a ** 2).sum()
+    t = r["T"]
+    closed = np.sqrt(1.0 - (t[:k, :] ** 2).sum() / na2)
+    wrong = np.sqrt(1.0 - (t[:k, :k] ** 2).sum() / na2)
+    assert abs(met["err_k"] - closed) < 1e-12
+    assert abs(wrong - closed) > 1e4 * 1e-12
+    # and the rank-l error by the same identity with all of T
+    assert abs(met["err_l"] - np.sqrt(1.0 - (t ** 2).sum() / na2)) < 1e-12
+
+
+def _torch_operand(x, fmt, rowscale=None):
+    """Decoded operand and column scales of a stored-format pass, from torch's
+    own format conversions (independent of the oracle's)."""
+    import torch
+
+    if rowscale is not None:
+        x = x * rowscale[:, None]
+    xf = x.astype(np.float32)
+    if fmt == "bf16":
+        return torch.from_numpy(xf).to(torch.bfloat16).double().numpy(), np.ones(x.shape[1])
+    mx = np.abs(xf).max(axis=0)
+    t = np.where(mx > 0, mx / np.float32(448.0), np.float32(1.0)).astype(np.float32)
+    y = np.clip(xf / t[None, :], -448.0, 448.0).astype(np.float32)
+    dec = torch.from_numpy(y).to(torch.float8_e4m3fn).double().numpy()
+    return dec, t.astype(np.float64)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_stored_format_passes_match_torch_conversions(orc, fmt):
+    # q = 0: span(U) = span(Aq Xq diag(t)) and span(V) = span of the second
+    # sketch diag(s) Aq^T Q1q diag(t), with the operands quantised by torch.
+    rng = np.random.default_rng(5 if fmt == "bf16" else 6)
+    m, n, k, p = 60, 40, 4, 2
+    l = k + p
+    a = rng.standard_normal((m, n)) * (0.8 ** np.arange(n))[None, :]
+    a32 = a.astype(np.float32)
+    if fmt == "bf16":
+        aq = orc.bf16_to_f64(orc.quantize_bf16(a32))
+        cs = None
+        rs = None
+    else:
+        codes, cs = orc.quantize_fp8(a32)
+        aq = orc.fp8_to_f64(codes).reshape(codes.shape)
+        rs = cs.astype(np.float64)
+    om = I.gaussian_omega(n, l, 9)
+    r = orc.cor_utv_fmt(aq, fmt, k, p, 0, om, colscale=cs)
+    xq, t = _torch_operand(om, fmt, rs)
+    q1, _ = _signfix_qr(aq @ xq * t[None, :])
+    assert np.abs(r["U"] @ r["U"].T - q1 @ q1.T).max() < 1e-12
+    q1q, t1 = _torch_operand(q1, fmt)
+    y2 = aq.T @ q1q * t1[None, :]
+    if rs is not None:
+        y2 = y2 * rs[:, None]
+    q2, _ = _signfix_qr(y2)
+    assert np.abs(r["V"] @ r["V"].T - q2 @ q2.T).max() < 1e-12
+    # the operand rounding is really there: FP64 passes give another span
+    r64 = orc.cor_utv(aq * (rs[None, :] if rs is not None else 1.0), k, p, 0, om)
+    assert np.abs(r64["U"] @ r64["U"].T - q1 @ q1.T).max() > 1e-6
+
+
+def test_stored_format_fp64_is_the_plain_method(orc):
+    a = np.random.default_rng(8).standard_normal((70, 50))
+    om = I.gaussian_omega(50, 9, 2)
+    r = orc.cor_utv(a, 6, 3, 1, om)
+    f = orc.cor_utv_fmt(a, "f64", 6, 3, 1, om)
+    for key in ("U", "T", "V", "perm"):
+        assert np.array_equal(r[key], f[key])
+
+
 def test_power_iteration_improves_accuracy(orc):
     # Slowly decaying spectrum: q = 1 beats q = 0, and q = 2 gives a rank-k
     # error within 1% of the optimum (Sec. VI-B observations).
