@@ -18,6 +18,7 @@ Recipes (the paper's constructions, Sec. "Numerical Experiments"):
 """
 
 from .gen import (  # noqa: F401
+    gaussian,
     haar,
     lowrank,
     spectrum,

@@ -4,6 +4,13 @@ Every function takes an explicit integer seed.  Small inputs are built with
 numpy (LAPACK QR for the orthonormal factors); large ones may be built with
 torch on a device (``backend="torch"``), which is the only fast way to draw a
 20000x10000 random orthonormal factor.  Results are float64.
+
+Both backends draw the Gaussian matrices with numpy's seeded generator
+(``gauss="numpy"``, the default), so the host and the device build the same
+matrix up to the rounding of their QR and product routines: a value stored by
+a host script for a large workload describes the matrix a device run builds.
+``gauss="device"`` draws on the device instead (fast, for workloads of many
+matrices that nothing stored refers to).
 """
 
 from __future__ import annotations
@@ -46,30 +53,40 @@ def spectrum(kind: str, r: int, k: int | None = None) -> np.ndarray:
     raise ValueError(kind)
 
 
-def haar(rows: int, cols: int, seed: int, backend: str = "numpy", device=None):
+def gaussian(rows: int, cols: int, seed: int) -> np.ndarray:
+    """i.i.d. N(0,1) rows x cols from numpy's seeded generator (PCG64)."""
+    return np.random.default_rng(seed).standard_normal((rows, cols))
+
+
+def haar(rows: int, cols: int, seed: int, backend: str = "numpy", device=None,
+         gauss: str = "numpy"):
     """Random orthonormal rows x cols factor: Q of QR(G), columns * sign(diag R).
 
     G is i.i.d. N(0,1).  With the sign correction Q is Haar distributed
-    (Mezzadri, Notices AMS 2007).
+    (Mezzadri, Notices AMS 2007), and unique given G.
     """
     if backend == "numpy":
-        g = np.random.default_rng(seed).standard_normal((rows, cols))
+        g = gaussian(rows, cols, seed)
         q, r = np.linalg.qr(g)
         s = np.sign(np.diag(r))
         s[s == 0] = 1.0
         return q * s
     import torch
 
-    gen = torch.Generator(device=device).manual_seed(seed)
-    g = torch.randn(rows, cols, generator=gen, dtype=torch.float64, device=device)
+    if gauss == "numpy":
+        g = torch.from_numpy(gaussian(rows, cols, seed)).to(device)
+    else:
+        gen = torch.Generator(device=device).manual_seed(seed)
+        g = torch.randn(rows, cols, generator=gen, dtype=torch.float64, device=device)
     q, r = torch.linalg.qr(g)
+    del g
     s = torch.sign(torch.diagonal(r))
     s[s == 0] = 1.0
     return q * s
 
 
 def lowrank(m: int, n: int, sigma, seed: int, noise: float = 0.0,
-            backend: str = "numpy", device=None):
+            backend: str = "numpy", device=None, gauss: str = "numpy"):
     """A = U diag(sigma) V^T (+ noise * N(0,1)), U m x r, V n x r random orthonormal.
 
     Returns (A, sigma) with sigma as given (the exact singular values of the
@@ -81,18 +98,21 @@ def lowrank(m: int, n: int, sigma, seed: int, noise: float = 0.0,
         v = haar(n, r, seed * 2 + 2)
         a = (u * np.asarray(sigma)[None, :]) @ v.T
         if noise:
-            a = a + noise * np.random.default_rng(seed * 2 + 3).standard_normal((m, n))
+            a = a + noise * gaussian(m, n, seed * 2 + 3)
         return a, np.asarray(sigma)
     import torch
 
-    u = haar(m, r, seed * 2 + 1, backend="torch", device=device)
-    v = haar(n, r, seed * 2 + 2, backend="torch", device=device)
+    u = haar(m, r, seed * 2 + 1, backend="torch", device=device, gauss=gauss)
+    v = haar(n, r, seed * 2 + 2, backend="torch", device=device, gauss=gauss)
     s = torch.as_tensor(np.asarray(sigma), dtype=torch.float64, device=device)
     a = (u * s[None, :]) @ v.T
     del u, v
     if noise:
-        gen = torch.Generator(device=device).manual_seed(seed * 2 + 3)
-        a += noise * torch.randn(m, n, generator=gen, dtype=torch.float64, device=device)
+        if gauss == "numpy":
+            a += noise * torch.from_numpy(gaussian(m, n, seed * 2 + 3)).to(device)
+        else:
+            gen = torch.Generator(device=device).manual_seed(seed * 2 + 3)
+            a += noise * torch.randn(m, n, generator=gen, dtype=torch.float64, device=device)
     return a, np.asarray(sigma)
 
 
