@@ -25,7 +25,6 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // Flags (device word per problem; mirrored by COR_FLAG_* of the public header).
-constexpr int32_t FLAG_CHOL_RETRY = 1;
 constexpr int32_t FLAG_RANK_DEF = 2;
 constexpr int32_t FLAG_NONFINITE = 4;
 

@@ -85,6 +85,23 @@ hipError_t launch_omega_raw(uint64_t seed, int64_t n, int32_t l, double* out, hi
     return hipGetLastError();
 }
 
+// Zero fill of a device byte range (16-byte words; `bytes` a multiple of 16,
+// `p` 16-byte aligned): the workspace clear of plans in caller-provided memory.
+__global__ __launch_bounds__(256) void k_zero16(uint4* __restrict__ p, int64_t words) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += stride)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    const int64_t words = (int64_t)(bytes / 16);
+    if (words <= 0) return hipSuccess;
+    const int64_t want = (words + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 2048 ? want : 2048);
+    hipLaunchKernelGGL(k_zero16, dim3(blocks), dim3(256), 0, s, reinterpret_cast<uint4*>(p), words);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Operand copy of an FP64 factor F (rows x l, row-major) in the pass format,
 // stored transposed: op[c][r], c < lp, r < ld; zero outside rows x l.

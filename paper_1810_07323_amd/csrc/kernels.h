@@ -67,5 +67,7 @@ hipError_t launch_normA(const LaunchGroup& g, hipStream_t s);
 hipError_t launch_quantize(const float* a32, int64_t m, int64_t n, int64_t lda, int to, void* out,
                            float* colscale, hipStream_t s);
 hipError_t launch_omega_raw(uint64_t seed, int64_t n, int32_t l, double* out, hipStream_t s);
+// Zero `bytes` (a multiple of 16) at the 16-byte aligned device address p.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace cor

@@ -16,9 +16,12 @@ cor_status fail(cor_status st, const std::string& msg);
 cor_status hip_fail(hipError_t e, const char* what);
 
 // Build a plan for `count` problems.  async: allocate, upload and clear on
-// `astream` (stream-ordered; no device-wide synchronisation).
+// `astream` (stream-ordered; no device-wide synchronisation).  ext_mem: use
+// these ext_bytes of device memory instead of allocating (COR_E_INVAL if the
+// plan needs more); uploads and the clear are enqueued on `astream`.
 cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* opts, Plan** out,
-                       hipStream_t astream, bool async);
+                       hipStream_t astream, bool async, void* ext_mem = nullptr,
+                       size_t ext_bytes = 0);
 cor_status plan_run(Plan* P, hipStream_t s);
 cor_status plan_info(Plan* P, cor_info* infos, hipStream_t s);
 void plan_destroy(Plan* P, hipStream_t s);

@@ -254,6 +254,7 @@ struct Plan {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     bool async = false;
+    bool owned = true;  // mem was allocated by the plan (else caller-provided)
     std::vector<int32_t> tab_host;
 };
 
@@ -279,7 +280,8 @@ struct TableBuilder {
 };
 
 cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* opts,
-                       Plan** out, hipStream_t astream, bool async) {
+                       Plan** out, hipStream_t astream, bool async, void* ext_mem,
+                       size_t ext_bytes) {
     if (!probs || count < 1 || !out) return fail(COR_E_INVAL, "no problems");
     for (int i = 0; i < count; i++) {
         cor_status st = validate(probs[i]);
@@ -389,11 +391,25 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     const size_t tab_bytes = roundup(tb.host.size() * sizeof(int32_t), 256);
     P->mem_bytes = desc_bytes + tab_bytes + ws;
     P->async = async;
-    hipError_t e = async ? hipMallocAsync(&P->mem, P->mem_bytes, astream)
-                         : hipMalloc(&P->mem, P->mem_bytes);
-    if (e != hipSuccess) {
-        delete P;
-        return fail(COR_E_NOMEM, "workspace allocation failed");
+    hipError_t e = hipSuccess;
+    if (ext_mem) {
+        // Caller-provided device memory: nothing is allocated or freed.
+        if (P->mem_bytes > ext_bytes) {
+            const size_t need = P->mem_bytes;
+            delete P;
+            return fail(COR_E_INVAL, "problem needs " + std::to_string(need) +
+                                         " bytes of workspace, more than the " +
+                                         std::to_string(ext_bytes) + " available");
+        }
+        P->mem = ext_mem;
+        P->owned = false;
+    } else {
+        e = async ? hipMallocAsync(&P->mem, P->mem_bytes, astream)
+                  : hipMalloc(&P->mem, P->mem_bytes);
+        if (e != hipSuccess) {
+            delete P;
+            return fail(COR_E_NOMEM, "workspace allocation failed");
+        }
     }
     char* mem = (char*)P->mem;
     P->d_probs = (Prob*)mem;
@@ -445,7 +461,16 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         d.seed = q.seed;
     }
     P->tab_host.swap(tb.host);
-    if (async) {
+    if (ext_mem) {
+        // Stream-ordered uploads (the host copies live in the plan) and a
+        // fill kernel for the workspace clear.
+        e = hipMemcpyAsync(P->d_probs, P->hp.data(), sizeof(Prob) * count, hipMemcpyHostToDevice,
+                           astream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_tab, P->tab_host.data(), P->tab_host.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, astream);
+        if (e == hipSuccess) e = launch_zero(d_ws, ws, astream);
+    } else if (async) {
         e = hipMemcpyAsync(P->d_probs, P->hp.data(), sizeof(Prob) * count, hipMemcpyHostToDevice,
                            astream);
         if (e == hipSuccess)
@@ -461,8 +486,10 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         if (e == hipSuccess) e = hipMemset(d_ws, 0, ws);
     }
     if (e != hipSuccess) {
-        if (async) (void)hipFreeAsync(P->mem, astream);
-        else (void)hipFree(P->mem);
+        if (P->owned) {
+            if (async) (void)hipFreeAsync(P->mem, astream);
+            else (void)hipFree(P->mem);
+        }
         delete P;
         return hip_fail(e, "plan upload");
     }
@@ -637,7 +664,7 @@ void plan_destroy(Plan* P, hipStream_t s) {
     if (!P) return;
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
-    if (P->mem) {
+    if (P->mem && P->owned) {
         if (P->async) (void)hipFreeAsync(P->mem, s);
         else (void)hipFree(P->mem);
     }
@@ -657,12 +684,21 @@ size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec) {
     return L.total + 256 + 1024;
 }
 
-// Cache of the last single-problem plan (reused when the same call repeats).
+// Cache of recent single-problem plans (reused when the same call repeats).
+// A plan taken from the cache is marked busy until its call returns, so no
+// other thread runs or evicts it meanwhile; a thread that finds its plan busy
+// builds one of its own.  Eviction drops the oldest idle entry.
 struct Cache {
     std::mutex mu;
-    std::vector<std::pair<std::vector<char>, Plan*>> items;
+    struct Item {
+        std::vector<char> key;
+        Plan* plan;
+        bool busy;
+    };
+    std::vector<Item> items;
 };
 static Cache g_cache;
+constexpr size_t CACHE_PLANS = 4;
 
 static std::vector<char> key_of(const cor_problem& p, const cor_opts* o, int dev) {
     std::vector<char> k(sizeof(cor_problem) + sizeof(cor_opts) + sizeof(int), 0);
@@ -672,6 +708,32 @@ static std::vector<char> key_of(const cor_problem& p, const cor_opts* o, int dev
     memcpy(k.data() + sizeof(p), &oo, sizeof(oo));
     memcpy(k.data() + sizeof(p) + sizeof(oo), &dev, sizeof(int));
     return k;
+}
+
+// Return a plan to the cache after its call (idle again), or destroy it when
+// the cache is full of other plans.
+static void cache_return(const std::vector<char>& key, Plan* P, bool from_cache) {
+    Plan* drop = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache.mu);
+        if (from_cache) {
+            for (auto& it : g_cache.items)
+                if (it.plan == P) it.busy = false;
+            return;
+        }
+        if (g_cache.items.size() >= CACHE_PLANS) {
+            auto old = std::find_if(g_cache.items.begin(), g_cache.items.end(),
+                                    [](const Cache::Item& it) { return !it.busy; });
+            if (old == g_cache.items.end()) {
+                drop = P;  // every cached plan is running: do not cache this one
+            } else {
+                drop = old->plan;
+                g_cache.items.erase(old);
+            }
+        }
+        if (drop != P) g_cache.items.push_back({key, P, false});
+    }
+    if (drop) plan_destroy(drop, nullptr);
 }
 
 cor_status run_single(const cor_problem& p, const cor_opts* opts, cor_info* info,
@@ -685,38 +747,50 @@ cor_status run_single(const cor_problem& p, const cor_opts* opts, cor_info* info
     {
         std::lock_guard<std::mutex> lk(g_cache.mu);
         for (auto& it : g_cache.items)
-            if (it.first == key) P = it.second;
+            if (!it.busy && it.key == key) {
+                it.busy = true;
+                P = it.plan;
+                break;
+            }
     }
+    const bool from_cache = P != nullptr;
     if (!P) {
         st = plan_create(&p, 1, opts, &P, nullptr, false);
         if (st != COR_OK) return st;
-        std::lock_guard<std::mutex> lk(g_cache.mu);
-        if (g_cache.items.size() >= 4) {
-            plan_destroy(g_cache.items.front().second, nullptr);
-            g_cache.items.erase(g_cache.items.begin());
-        }
-        g_cache.items.push_back({key, P});
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, s));
-    st = plan_run(P, s);
-    if (st != COR_OK) return st;
-    HIPCHK(hipEventRecord(e1, s));
-    st = plan_info(P, info, s);
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (info) info->device_ms = ms;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e != hipSuccess) st = hip_fail(e, "timing events");
+    if (st == COR_OK) st = plan_run(P, s);
+    if (st == COR_OK) {
+        e = hipEventRecord(e1, s);
+        if (e != hipSuccess) st = hip_fail(e, "timing events");
+    }
+    // plan_info waits for the stream even after a failed launch, so the plan
+    // is idle when it goes back to the cache.
+    const cor_status st_info = plan_info(P, info, s);
+    if (st == COR_OK) st = st_info;
+    if (st == COR_OK && info) {
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        info->device_ms = ms;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    cache_return(key, P, from_cache);
     return st;
 }
 
 void release_all() {
     std::lock_guard<std::mutex> lk(g_cache.mu);
-    for (auto& it : g_cache.items) plan_destroy(it.second, nullptr);
-    g_cache.items.clear();
+    std::vector<Cache::Item> keep;
+    for (auto& it : g_cache.items) {
+        if (it.busy) keep.push_back(it);  // running on another thread: stays cached
+        else plan_destroy(it.plan, nullptr);
+    }
+    g_cache.items.swap(keep);
 }
 
 }  // namespace cor

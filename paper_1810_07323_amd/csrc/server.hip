@@ -120,8 +120,10 @@ static void launch_round(Server* S, std::vector<Request*>& adm) {
             if (e == hipSuccess)
                 e = launch_quantize((const float*)p.A, p.m, p.n, p.lda, COR_BF16, r->conv, nullptr, s);
             if (e != hipSuccess) {
+                // Only the status is recorded here: the request stays in the
+                // round and is retired (done, slot and budget returned) by
+                // finish_round under the server lock.
                 r->st = COR_E_DEVICE;
-                r->done = true;
                 continue;
             }
             p.A = r->conv;
@@ -145,7 +147,7 @@ static void launch_round(Server* S, std::vector<Request*>& adm) {
             (void)hipMemcpyAsync(rec->rep, d.rep, sizeof(rec->rep), hipMemcpyDeviceToHost, s);
         }
     } else {
-        for (Request* r : ok) { r->st = st == COR_OK ? COR_E_DEVICE : st; r->done = true; }
+        for (Request* r : ok) r->st = st == COR_OK ? COR_E_DEVICE : st;
     }
     (void)hipEventCreateWithFlags(&R->done_ev, hipEventDisableTiming);
     (void)hipEventRecord(R->done_ev, s);
@@ -162,7 +164,7 @@ static void finish_round(Server* S, Round* R) {
     for (Request* r : R->reqs) {
         if (r->conv) (void)hipFreeAsync(r->conv, s);
         r->conv = nullptr;
-        if (!r->done || r->st == COR_OK) {
+        if (r->st == COR_OK) {
             const SlotRec* rec = S->slots + r->slot;
             r->info.flags = rec->flags;
             r->info.err_l = rec->rep[0];
