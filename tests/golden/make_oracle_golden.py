@@ -15,7 +15,14 @@ Only the oracle and the seeded input generators are called here.  The device
 builds the same matrix from the same Gaussians (its QR and products differ
 only by rounding); the fingerprint lets a run confirm that.
 
-Run:  python tests/golden/make_oracle_golden.py c3   (and c2)
+With a storage format (bf16 or fp8) the script instead runs the oracle's
+stored-format form of the method (each pass reads A and its skinny operand in
+that format, products exact) on A quantised by the oracle's own quantiser
+(A -> binary32 -> bfloat16, or E4M3 with per-column scales), and records its
+errors against the FP64 A (what a user of that format gets) and against the
+dequantised matrix; <name>_oracle_<fmt>.json.
+
+Run:  python tests/golden/make_oracle_golden.py c3 [bf16|fp8]   (and c2)
 """
 
 import json
@@ -56,6 +63,58 @@ def fingerprint(a):
         "last_row_tail": a[-1, -6:].tolist(),
         "col_sums_head": a[:, :4].sum(axis=0).tolist(),
     }
+
+
+def main_fmt(name, fmt):
+    c = inputs.CONFIGS[name]
+    k, p, q = c["k"], c["p"], c["q"]
+    l = k + p
+    t0 = time.time()
+    a, sig = inputs.config_matrix(name)
+    t_gen = time.time() - t0
+    m, n = a.shape
+    a32 = a.astype(np.float32)
+    t0 = time.time()
+    if fmt == "bf16":
+        h = oracle.quantize_bf16(a32)
+        aq = oracle.bf16_to_f64(h)
+        cs = None
+        deq = aq
+    else:
+        codes, cs = oracle.quantize_fp8(a32)
+        aq = oracle.fp8_to_f64(np.arange(256))[codes]
+        deq = aq * cs.astype(np.float64)[None, :]
+    del a32
+    t_q = time.time() - t0
+    print(f"matrix {a.shape} built in {t_gen:.1f} s, quantised in {t_q:.1f} s", flush=True)
+    om = oracle.omega(OMEGA_SEED[name], n, l)
+    t0 = time.time()
+    r = oracle.cor_utv_fmt(aq, fmt, k, p, q, om, colscale=cs)
+    t_orc = time.time() - t0
+    print(f"stored-format oracle in {t_orc:.1f} s", flush=True)
+    del aq
+    t0 = time.time()
+    met = oracle.metrics(a, r["U"], r["T"], r["V"], k)
+    met_q = oracle.metrics(deq, r["U"], r["T"], r["V"], k)
+    t_met = time.time() - t0
+    print(f"metrics in {t_met:.1f} s: vs A {met}; vs deq(A) {met_q}", flush=True)
+    nrm = float(np.linalg.norm(a))
+    out = {
+        "workload": DESC[name], "format": fmt,
+        "m": m, "n": n, "k": k, "p": p, "q": q, "matrix_seed": c["seed"],
+        "omega_seed": OMEGA_SEED[name],
+        "err_l": met["err_l"], "err_k": met["err_k"],
+        "err_l_vs_stored": met_q["err_l"], "err_k_vs_stored": met_q["err_k"],
+        "orth_u": met["orth_u"], "orth_v": met["orth_v"],
+        "format_error": float(np.linalg.norm(a - deq) / nrm),
+        "T_diag": np.diag(r["T"]).tolist(),
+        "fingerprint": fingerprint(a),
+        "host_seconds": {"generate": t_gen, "quantise": t_q, "oracle": t_orc,
+                         "metrics": t_met},
+    }
+    with open(os.path.join(HERE, f"{name}_oracle_{fmt}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("written", flush=True)
 
 
 def main(name):
@@ -100,4 +159,7 @@ def main(name):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "c3")
+    if len(sys.argv) > 2:
+        main_fmt(sys.argv[1], sys.argv[2])
+    else:
+        main(sys.argv[1] if len(sys.argv) > 1 else "c3")

@@ -1,15 +1,14 @@
-"""GPU parity of the reduced-precision passes, the batched call and the server.
+"""GPU parity of the reduced-precision passes, the batched call, graph replay
+and the server.
 
-Quantised modes (A stored as BF16, or FP8 E4M3 with per-column scales):
-  * against the FP64 matrix the caller quantised (what a user gets), the GPU
-    error may exceed the oracle's only by the format's own floor:
-      eps_gpu <= 1.05 * sqrt(eps_oracle^2 + q^2),  q = ||A - deq(A_q)||_F / ||A||_F
-    (any method that only sees the stored matrix carries q);
-  * against the dequantised matrix the GPU actually read, the oracle run on
-    that same matrix: eps_gpu <= 1.05 * eps_oracle for BF16.  FP8 operands of
-    the skinny factors have a 3-bit mantissa, so there the bound is the
-    oracle's error plus the relative rounding of an E4M3 operand averaged
-    over the contraction (documented, not hidden).
+Quantised modes (A stored as BF16, or FP8 E4M3 with per-column scales); errors
+are measured against the FP64 matrix the caller quantised (what a user gets):
+  * eps_gpu <= 1.05 eps_oracle, the FP64 oracle on the FP64 matrix, wherever
+    the storage noise is far below sigma_l (slowly decaying spectra here; the
+    20000 x 10000 workload in test_gpu_fullsize.py);
+  * always: within 5 % both ways of the oracle's stored-format run (A and the
+    skinny operands in the same storage, products exact), which separates
+    kernel errors from the limits of the format.
 Batched and served results must equal the single call bit for bit: a
 problem's layout, launch shapes and reduction orders depend on its own shape
 only.
@@ -67,8 +66,7 @@ def _quantise(cu, dev, a, fmt):
         out = torch.empty(a.shape, dtype=torch.bfloat16, device=dev)
         cu.check(cu.cor_quantize(A32, cu.COR_BF16, out), "quantize")
         torch.cuda.synchronize()
-        deq = out.float().cpu().numpy().astype(np.float64)
-        return out, None, deq
+        return out, None, None
     out = torch.empty(a.shape, dtype=torch.uint8, device=dev)
     s = torch.empty(a.shape[1], dtype=torch.float32, device=dev)
     cu.check(cu.cor_quantize(A32, cu.COR_FP8, out, s), "quantize")
@@ -76,48 +74,73 @@ def _quantise(cu, dev, a, fmt):
     return out, s, None
 
 
-@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
-def test_quantised_passes_scaled_config3(cu, dev, orc, fmt):
-    a, sig, k, p, q = _c3_scaled()
-    l = k + p
-    Aq, colscale, deq = _quantise(cu, dev, a, fmt)
-    if fmt == "fp8":
-        codes = Aq.cpu().numpy()
-        deq = orc.dequantize_fp8(codes, colscale.cpu().numpy())
-    om = I.gaussian_omega(a.shape[1], l, 11)
-    U, T, V, perm, info = cu.decompose(Aq, k, p, q, omega=om, colscale=colscale)
+def _stored(orc, Aq, colscale, fmt):
+    """Decoded stored values (FP8: codes without the scale) and the
+    dequantised matrix, read back from the device copy."""
+    if fmt == "bf16":
+        aq = Aq.float().cpu().numpy().astype(np.float64)
+        return aq, aq
+    codes = Aq.cpu().numpy()
+    aq = orc.fp8_to_f64(np.arange(256))[codes]
+    return aq, aq * colscale.cpu().numpy().astype(np.float64)[None, :]
+
+
+def _quantised_case(cu, dev, orc, a, k, p, q, fmt, om, tag):
+    """GPU run on the quantised A against (i) the FP64 oracle on the FP64 A and
+    (ii) the oracle's stored-format run (same storage of A and of the skinny
+    operands, exact products).  Returns the error ratios."""
     import torch
 
+    Aq, colscale, _ = _quantise(cu, dev, a, fmt)
+    aq, deq = _stored(orc, Aq, colscale, fmt)
+    U, T, V, perm, info = cu.decompose(Aq, k, p, q, omega=om, colscale=colscale)
     torch.cuda.synchronize()
     U, T, V = U.cpu().numpy(), T.cpu().numpy(), V.cpu().numpy()
-    nrm = np.linalg.norm(a)
-    qerr = np.linalg.norm(a - deq) / nrm
     ref = orc.cor_utv(a, k, p, q, om)
     mo = orc.metrics(a, ref["U"], ref["T"], ref["V"], k)
+    ref_f = orc.cor_utv_fmt(aq, fmt, k, p, q, om,
+                            colscale=None if colscale is None else colscale.cpu().numpy())
+    mf = orc.metrics(a, ref_f["U"], ref_f["T"], ref_f["V"], k)
     mg = orc.metrics(a, U, T, V, k)
-    ref_q = orc.cor_utv(deq, k, p, q, om)
-    mo_q = orc.metrics(deq, ref_q["U"], ref_q["T"], ref_q["V"], k)
-    mg_q = orc.metrics(deq, U, T, V, k)
-    floor = np.sqrt(mo["err_l"] ** 2 + qerr ** 2)
-    print(f"[{fmt}] eps_l vs A: gpu {mg['err_l']:.4e} oracle {mo['err_l']:.4e} "
-          f"(ratio {mg['err_l'] / mo['err_l']:.4f}); format floor q {qerr:.3e} -> "
-          f"{floor:.4e} (ratio {mg['err_l'] / floor:.4f}); vs deq(A): gpu {mg_q['err_l']:.4e} "
-          f"oracle {mo_q['err_l']:.4e} (ratio {mg_q['err_l'] / mo_q['err_l']:.4f}); "
-          f"orth {mg['orth_u']:.1e} {mg['orth_v']:.1e}")
-    # Orthonormal factors and triangular T whatever the pass format.
+    qerr = np.linalg.norm(a - deq) / np.linalg.norm(a)
+    r = dict(fp64=mg["err_l"] / mo["err_l"], stored=mg["err_l"] / mf["err_l"],
+             stored_k=mg["err_k"] / mf["err_k"], fp64_k=mg["err_k"] / mo["err_k"])
+    print(f"[{tag} {fmt}] eps_l gpu {mg['err_l']:.5e}: / FP64 oracle {r['fp64']:.4f}, / "
+          f"stored-format oracle {r['stored']:.4f} (eps_k {r['stored_k']:.4f}); format error "
+          f"{qerr:.2e}; orth {mg['orth_u']:.1e} {mg['orth_v']:.1e}", flush=True)
     assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
     assert np.array_equal(np.tril(T, -1), np.zeros_like(T))
-    # What a user gets, up to the storage format's own floor.
-    assert mg["err_l"] <= 1.05 * np.sqrt(mo["err_l"] ** 2 + qerr ** 2)
-    assert mg["err_k"] <= 1.05 * np.sqrt(mo["err_k"] ** 2 + qerr ** 2)
-    if fmt == "bf16":
-        assert mg_q["err_l"] <= 1.05 * mo_q["err_l"]
-        assert mg_q["err_k"] <= 1.05 * mo_q["err_k"]
-    else:
-        # E4M3 skinny operands: relative rounding 2^-4 per element, averaged
-        # over the l-column factor against the m rows of the contraction.
-        op = 2.0 ** -4 / np.sqrt(3.0) * np.sqrt(l / a.shape[0])
-        assert mg_q["err_l"] <= 1.05 * np.sqrt(mo_q["err_l"] ** 2 + op ** 2)
+    return r
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_quantised_passes_scaled_config3(cu, dev, orc, fmt):
+    """The 20000 x 10000 recipe at 2000 x 1000 (l = 220).  At this size the
+    storage noise of either format is comparable to sigma_220, so the 1.05x
+    rule against the FP64 oracle is checked at the full size (stored oracle
+    results); here the kernels are checked against the oracle's stored-format
+    run, within 5 % both ways."""
+    a, sig, k, p, q = _c3_scaled()
+    om = I.gaussian_omega(a.shape[1], k + p, 11)
+    r = _quantised_case(cu, dev, orc, a, k, p, q, fmt, om, "scaled c3")
+    assert abs(r["stored"] - 1.0) <= 0.05 and abs(r["stored_k"] - 1.0) <= 0.05
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("l", [240, 264])
+def test_quantised_passes_widest_l(cu, dev, orc, fmt, l):
+    """Fifteen to seventeen column tiles (l = 240, 264: the widest sketch
+    instances, the streamed QRCP and a three-block Cholesky) in BF16 and FP8
+    on a slowly decaying spectrum (sigma_i = exp(-i/150)), where the storage
+    noise stays far below sigma_l: the 1.05x rule against the FP64 oracle
+    applies, and the stored-format oracle is matched within 5 % both ways."""
+    m, n = 1100, 900
+    a, _ = I.lowrank(m, n, np.exp(-np.arange(1, n + 1) / 150.0), seed=2400 + l)
+    k, p, q = l - 16, 16, 1
+    om = I.gaussian_omega(n, l, 13)
+    r = _quantised_case(cu, dev, orc, a, k, p, q, fmt, om, f"l={l}")
+    assert abs(r["stored"] - 1.0) <= 0.05 and abs(r["stored_k"] - 1.0) <= 0.05
+    assert r["fp64"] <= 1.05 and r["fp64_k"] <= 1.05
 
 
 def test_f32_l220_matches_oracle(cu, dev, orc):
@@ -185,6 +208,112 @@ def test_batched_equals_single_and_oracle(cu, dev, orc):
               f"orth {mg['orth_u']:.1e}")
         assert abs(mg["err_l"] - mo["err_l"]) <= 1e-12
         assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
+
+
+def test_batched_bf16_recipe_against_oracle(cu, dev, orc):
+    """The batched workload's own recipe in BF16 (m, n ~ U{256..1024},
+    k ~ U{8..64}, l = k + 8, sigma_i = exp(-i/k), q = 1, A stored BF16): each
+    problem within 1.05x of the FP64 oracle on the FP64 matrix and within 5 %
+    of the oracle's stored-format run; the batched call equals the single
+    calls bit for bit."""
+    import torch
+
+    specs = _batch(8, 4040, "bf16")
+    probs, keep = [], []
+    for i, s in enumerate(specs):
+        a, _ = I.lowrank(s["m"], s["n"], I.spectrum("expk", s["rank"], s["k"]), seed=s["seed"])
+        l = s["k"] + s["p"]
+        A16 = torch.from_numpy(a).to(dev).to(torch.bfloat16).contiguous()
+        om = I.gaussian_omega(s["n"], l, 200 + i)
+        omd = torch.from_numpy(om).to(dev)
+        o = _outputs(dev, s["m"], s["n"], l)
+        probs.append(cu.make_problem(A16, s["k"], s["p"], s["q"], 0, *o, omega=omd))
+        keep.append((a, A16, om, omd, o))
+    st, infos = cu.cor_utv_batched(probs, cu.cor_opts(0, 0))
+    cu.check(st, "batched")
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, s in enumerate(specs):
+        a, A16, om, omd, o = keep[i]
+        l = s["k"] + s["p"]
+        o1 = _outputs(dev, s["m"], s["n"], l)
+        pr = cu.make_problem(A16, s["k"], s["p"], s["q"], 0, *o1, omega=omd)
+        cu.check(cu.cor_utv_ex(pr, cu.cor_opts(0, 0))[0], "single")
+        torch.cuda.synchronize()
+        for x, y in zip(o, o1):
+            assert torch.equal(x, y), f"problem {i}: batched differs from the single call"
+        U, T, V = [x.cpu().numpy() for x in o[:3]]
+        aq = A16.float().cpu().numpy().astype(np.float64)
+        ref = orc.cor_utv(a, s["k"], s["p"], s["q"], om)
+        mo = orc.metrics(a, ref["U"], ref["T"], ref["V"], s["k"])
+        ref_f = orc.cor_utv_fmt(aq, "bf16", s["k"], s["p"], s["q"], om)
+        mf = orc.metrics(a, ref_f["U"], ref_f["T"], ref_f["V"], s["k"])
+        mg = orc.metrics(a, U, T, V, s["k"])
+        r64, rf = mg["err_l"] / mo["err_l"], mg["err_l"] / mf["err_l"]
+        worst = max(worst, r64)
+        print(f"[batched bf16 {i}] {s['m']}x{s['n']} l={l}: eps {mg['err_l']:.4e} / FP64 oracle "
+              f"{r64:.5f}, / stored-format {rf:.5f}; orth {mg['orth_u']:.1e} {mg['orth_v']:.1e}")
+        assert r64 <= 1.05 and mg["err_k"] <= 1.05 * mo["err_k"]
+        assert abs(rf - 1.0) <= 0.05
+        assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
+    print(f"[batched bf16] worst ratio to the FP64 oracle {worst:.5f}")
+
+
+def test_graph_replay_equals_eager(cu, dev, orc):
+    """A plan captured into a HIP graph and replayed gives bit for bit the
+    result of the eager run; replays are interleaved with other device work
+    and host synchronisations, and every replay is checked (FP32 and BF16
+    problems in one plan, seeded test matrices, report on)."""
+    import torch
+
+    shapes = [(1300, 900, 40, 8, 1, "f32"), (700, 1100, 20, 5, 2, "bf16"), (600, 500, 9, 3, 0, "f32")]
+    probs, outs, mats = [], [], []
+    for i, (m, n, k, p, q, fmt) in enumerate(shapes):
+        a, _ = I.lowrank(m, n, np.exp(-np.arange(1, min(m, n) + 1) / 30.0), seed=90 + i)
+        A = torch.from_numpy(a).to(dev)
+        A = A.float().contiguous() if fmt == "f32" else A.to(torch.bfloat16).contiguous()
+        o = _outputs(dev, m, n, k + p)
+        probs.append(cu.make_problem(A, k, p, q, 4242 + i, *o))
+        outs.append(o)
+        mats.append((a, A))
+    stream = torch.cuda.Stream()
+    st, plan = cu.cor_plan_create(probs, cu.cor_opts(1, 0))
+    cu.check(st, "plan_create")
+    try:
+        with torch.cuda.stream(stream):
+            cu.check(cu.cor_plan_run(plan, stream), "eager run")
+            st, info_e = cu.cor_plan_info(plan, len(probs), stream)
+            cu.check(st, "info")
+            eager = [[x.clone() for x in o] for o in outs]
+            cu.check(cu.cor_plan_capture(plan, stream), "capture")
+            for rep in range(4):
+                for o in outs:  # scribble over the outputs between replays
+                    for x in o:
+                        x.fill_(-7)
+                junk = torch.randn(512, 512, device=dev) @ torch.randn(512, 512, device=dev)
+                stream.synchronize()
+                cu.check(cu.cor_plan_run(plan, stream), "replay")
+                st, info_r = cu.cor_plan_info(plan, len(probs), stream)
+                cu.check(st, "info")
+                for i, o in enumerate(outs):
+                    for x, y in zip(o, eager[i]):
+                        assert torch.equal(x, y), f"replay {rep}, problem {i} differs from eager"
+                    assert info_r[i].err_l == info_e[i].err_l
+                    assert info_r[i].orth_u == info_e[i].orth_u
+                del junk
+    finally:
+        cu.check(cu.cor_plan_destroy(plan), "destroy")
+    # and the eager result is the method's (seeded test matrices, oracle metric)
+    for i, (m, n, k, p, q, fmt) in enumerate(shapes):
+        a = mats[i][0]
+        U, T, V = [x.cpu().numpy() for x in eager[i][:3]]
+        ref = orc.cor_utv(a, k, p, q, orc.omega(4242 + i, n, k + p))
+        mo = orc.metrics(a, ref["U"], ref["T"], ref["V"], k)
+        mg = orc.metrics(a, U, T, V, k)
+        print(f"[graph {i}] {fmt} eps {mg['err_l']:.6e} oracle {mo['err_l']:.6e}")
+        assert mg["err_l"] <= 1.05 * mo["err_l"]
+        if fmt == "f32":
+            assert abs(mg["err_l"] - mo["err_l"]) <= 1e-5
 
 
 def test_server_mix_equals_single(cu, dev, orc):
