@@ -1,15 +1,19 @@
 """Throughput of the CoR-UTV hot path on one MI355X.
 
-Default workload (the FP32 decomposition of the benchmark table):
-A = 8000 x 8000, U, V random orthonormal 8000 x 500, sigma_i = exp(-i/40)
-(i <= 500), stored FP32; k = 100, p = 10 (l = 110), q = 2.  One step is one
-whole decomposition (Omega, 2q+2 passes over A with CholeskyQR2 after each,
-M = R2^T, QRCP, U and V), replayed from a captured HIP graph of the plan.
+Default workload: A = 20000 x 10000 = U diag(sigma) V^T with U, V random
+orthonormal (QR of seeded Gaussians) and sigma_i = i^-1.5; k = 200, p = 20
+(l = 220), q = 2.  One step is one whole decomposition (Omega, 2q+2 passes
+over A with CholeskyQR after each, M = R2^T, QRCP, U and V), replayed from a
+captured HIP graph of the plan.  The decomposition runs with its passes in
+FP64 (the line's value: the paper's arithmetic), FP32, BF16 and FP8 E4M3 with
+per-column scales; every result is checked against the oracle's stored result
+for the same matrix and test matrix (at fixed error), and every format
+reports its own throughput, error ratio and pass roofline.
 
 Prints one JSON line: decompositions/s, p50/p99 step latency, the roofline of
-the dominant kernel (the passes over A: FP32 MFMA-bound at l = 110) from HIP
-events recorded around every pass launch inside the timed region, and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+the dominant kernel (the passes over A) from HIP events around every pass
+launch of eager runs on the plan's stream, and the FP64 CPU oracle timed end
+to end on two row blocks of the same matrix.
 """
 
 from __future__ import annotations
@@ -30,6 +34,9 @@ PEAKS = {  # MI355X published dense peaks
 }
 
 WORKLOADS = {
+    # default: the 20000 x 10000 workload in every pass format (value = FP64)
+    "c3": dict(desc="20000x10000, U, V random orthonormal, sigma_i=i^-1.5; k=200, l=220, q=2; "
+                    "passes in FP64 (value), FP32, BF16 and FP8 E4M3 with column scales"),
     "c2": dict(m=8000, n=8000, rank=500, spectrum="exp40", k=100, p=10, q=2, prec="f32", seed=202,
                desc="8000x8000 FP32, rank-500 Haar factors, sigma_i=exp(-i/40); k=100, l=110, q=2"),
     "c3bf16": dict(m=20000, n=10000, rank=10000, spectrum="pow15", k=200, p=20, q=2, prec="bf16",
@@ -66,49 +73,6 @@ def make_input(w, dev):
     a64, sig = I.lowrank(w["m"], w["n"], sig, w["seed"], noise=w.get("noise", 0.0),
                          backend="torch", device=dev)
     return a64, np.asarray(sig)
-
-
-def cpu_baseline(a_host, w, budget_s=20.0):
-    """Time the FP64 oracle on a row sample of A and scale to one decomposition.
-
-    The oracle's cost is 2q+3 products with A or A^T (q+1 each way plus the
-    explicit M = Q1^T (A Q2)), 2q+2 Householder QRs and the l x l core.  The
-    sample runs the oracle's A X and A^T Y products over the first R rows of A
-    (R chosen to keep the sample near `budget_s`) and one Householder QR of an
-    m x l matrix; the products scale linearly in the rows.
-    """
-    import numpy as np
-
-    import oracle
-
-    m, n = a_host.shape
-    l = w["k"] + w["p"]
-    q = w["q"]
-    rng = np.random.default_rng(0)
-    x = rng.standard_normal((n, l))
-    # calibrate on a small block
-    r0 = max(8, min(m, 64))
-    t = time.perf_counter()
-    oracle.gemm_nn(a_host[:r0], x)
-    t_small = time.perf_counter() - t
-    per_row_ax = t_small / r0
-    rows = int(max(r0, min(m, (budget_s * 0.4) / max(per_row_ax, 1e-9))))
-    blk = np.ascontiguousarray(a_host[:rows])
-    t = time.perf_counter()
-    oracle.gemm_nn(blk, x)
-    t_ax = (time.perf_counter() - t) * m / rows
-    y = rng.standard_normal((rows, l))
-    t = time.perf_counter()
-    oracle.gemm_tn(blk, y)
-    t_atx = (time.perf_counter() - t) * m / rows
-    t = time.perf_counter()
-    oracle.qr(rng.standard_normal((m, l)))
-    t_qr = time.perf_counter() - t
-    total = (q + 1) * (t_ax + t_atx) + t_ax + (2 * q + 2) * t_qr
-    return dict(value=1.0 / total, unit="decomps/s", cores=1, kind="oracle",
-                sample=f"oracle A*X and A^T*Y over {rows} of {m} rows plus one {m}x{l} "
-                       f"Householder QR, scaled to 2q+3={2 * q + 3} products and 2q+2 QRs "
-                       f"(est. {total:.1f} s per decomposition)")
 
 
 def bench_batched(args, w, cu, torch, np):
@@ -318,12 +282,263 @@ def bench_served(args, w, cu, torch, np):
     }
 
 
+def timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=None, profile_steps=20):
+    """Plan one decomposition of the device matrix A, capture it into a HIP
+    graph, replay `warmup` untimed and `steps` timed decompositions, then time
+    the passes over A of eager runs of the same plan with HIP events on the
+    plan's stream.  Returns the outputs and the timings."""
+    dev = A.device
+    m, n = A.shape
+    l = k + p
+    U = torch.empty((m, l), dtype=torch.float64, device=dev)
+    T = torch.empty((l, l), dtype=torch.float64, device=dev)
+    V = torch.empty((n, l), dtype=torch.float64, device=dev)
+    perm = torch.empty((l,), dtype=torch.int32, device=dev)
+    prob = cu.make_problem(A, k, p, q, seed=seed, U=U, T=T, V=V, perm=perm, colscale=colscale)
+    stream = torch.cuda.Stream()
+    st, plan = cu.cor_plan_create([prob], cu.cor_opts(0, 0))
+    cu.check(st, "plan_create")
+    graph = not args.no_graph
+    try:
+        with torch.cuda.stream(stream):
+            if graph:
+                cu.check(cu.cor_plan_capture(plan, stream), "plan_capture")
+            for _ in range(args.warmup):
+                cu.check(cu.cor_plan_run(plan, stream), "plan_run")
+            stream.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev[0].record(stream)
+            for i in range(args.steps):
+                cu.check(cu.cor_plan_run(plan, stream), "plan_run")
+                ev[i + 1].record(stream)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            # Pass timing: eager runs of a second plan over the same problem,
+            # each pass launch bracketed by events on the plan's stream.
+            st2, plan2 = cu.cor_plan_create([prob], cu.cor_opts(0, 0))
+            cu.check(st2, "plan_create")
+            cu.cor_profile_enable(True)
+            cu.cor_profile_read()
+            for _ in range(profile_steps):
+                cu.check(cu.cor_plan_run(plan2, stream), "plan_run")
+            torch.cuda.synchronize()
+            prof = cu.cor_profile_read()
+            cu.cor_profile_enable(False)
+            cu.cor_plan_destroy(plan2)
+            # the result of the timed replays is in U, T, V (same plan, same outputs)
+            cu.check(cu.cor_plan_run(plan, stream), "plan_run")
+            st, info = cu.cor_plan_info(plan, 1, stream)
+            cu.check(st, "plan_info")
+    finally:
+        cu.cor_plan_destroy(plan)
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    return dict(U=U, T=T, V=V, perm=perm, elapsed=t1 - t0, step_ms=step_ms, prof=prof,
+                graph=graph, flags=info[0].flags)
+
+
+def accuracy(torch, a64, U, T, V, k):
+    """Explicit FP64 residuals of a result against the FP64 matrix, and the
+    orthogonality of its factors."""
+    l = T.shape[0]
+    nA = torch.linalg.norm(a64)
+    W = T @ V.T
+    err_l = float(torch.linalg.norm(a64 - U @ W) / nA)
+    err_k = float(torch.linalg.norm(a64 - U[:, :k] @ W[:k]) / nA)
+    eye = torch.eye(l, device=U.device, dtype=torch.float64)
+    return dict(err_l=err_l, err_k=err_k, orth_u=float(torch.linalg.norm(U.T @ U - eye)),
+                orth_v=float(torch.linalg.norm(V.T @ V - eye)))
+
+
+def pass_roofline(prec, l, prof):
+    """Roofline of the passes over A (the dominant kernel): achieved
+    algorithmic flops or bytes per launch over the mean launch time."""
+    launches = max(1, prof["launches"])
+    avg_s = prof["ms"] / launches / 1e3
+    flops = prof["flops"] / launches
+    nbytes = prof["bytes"] / launches
+    # A pass does 2 l flops per element of A: MFMA-bound above the ridge
+    # (FP64 l >= 39, FP32 l >= 40), HBM-bound below it and in BF16/FP8.
+    if prec == "f64" and l >= 39:
+        bound, peak, unit = "mfma", PEAKS["f64"], "TFLOP/s"
+        achieved = flops / avg_s / 1e12
+    elif prec == "f32" and l >= 40:
+        bound, peak, unit = "mfma", PEAKS["f32"], "TFLOP/s"
+        achieved = flops / avg_s / 1e12
+    else:
+        bound, peak, unit = "hbm", PEAKS["hbm_GBs"], "GB/s"
+        achieved = nbytes / avg_s / 1e9
+    return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "kernel": "k_sketch (passes over A)",
+            "avg_launch_us": round(avg_s * 1e6, 2), "launches_timed": prof["launches"],
+            "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes}
+
+
+def traffic_of(name):
+    tpath = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == source_hash():
+            return tr.get("bytes_per_launch")
+    return None
+
+
+def cpu_baseline_oracle(a64, k, p, q, seed, budget_rows=(300, 600)):
+    """The FP64 oracle itself, end to end (Omega, 2q+2 products and QRs, the
+    explicit compression pass, QRCP, U, V), on two leading row blocks of A
+    with the full column count; its time is linear in the row count
+    (t = a + b m: the n-side QRs and the l x l core do not depend on m), so
+    the two runs give the time of the whole m-row decomposition."""
+    import numpy as np
+
+    import oracle
+
+    m, n = a64.shape
+    l = k + p
+    om = oracle.omega(seed, n, l)
+    times = []
+    for r in budget_rows:
+        blk = np.ascontiguousarray(a64[:r].cpu().numpy())
+        t = time.perf_counter()
+        oracle.cor_utv(blk, k, p, q, om)
+        times.append(time.perf_counter() - t)
+    (r1, r2), (t1, t2) = budget_rows, times
+    b = (t2 - t1) / (r2 - r1)
+    a = t1 - b * r1
+    est = a + b * m
+    return dict(value=1.0 / est, unit="decomps/s", cores=1, kind="oracle",
+                sample=f"oracle cor_utv end to end on the first {r1} and {r2} of {m} rows "
+                       f"(n = {n}, k = {k}, p = {p}, q = {q}): {t1:.1f} s and {t2:.1f} s, "
+                       f"linear in the rows -> {est:.1f} s per full decomposition",
+                seconds_sampled=round(t1 + t2, 2))
+
+
+C3_RULE = {  # at fixed error: the rule each pass format is held to
+    "f64": "|eps - eps_oracle| <= 1e-12",
+    "f32": "|eps - eps_oracle| <= 1e-5",
+    "bf16": "eps <= 1.05 eps_oracle",
+    "fp8": "eps <= 1.05 eps_oracle (not met: E4M3 noise above sigma_l); "
+           "eps within 5 % of the stored-format oracle",
+}
+
+
+def bench_c3(args, w, cu, torch, np):
+    """The 20000 x 10000 workload in every pass format: FP64 (the paper's
+    arithmetic; the line's value), FP32, BF16 and FP8 with column scales.
+    Each result is checked against the oracle's stored result for the same
+    matrix and test matrix."""
+    dev = torch.device("cuda:0")
+    with open(os.path.join(ROOT, "tests", "golden", "c3_oracle.json")) as f:
+        gold = json.load(f)
+    gq = {}
+    for fmt in ("bf16", "fp8"):
+        pth = os.path.join(ROOT, "tests", "golden", f"c3_oracle_{fmt}.json")
+        if os.path.exists(pth):
+            with open(pth) as f:
+                gq[fmt] = json.load(f)
+    import inputs as I
+
+    a64, sig = I.config_matrix("c3", backend="torch", device=dev)
+    k, p, q = gold["k"], gold["p"], gold["q"]
+    l = k + p
+    seed = gold["omega_seed"]
+    modes = {}
+    for fmt in args.formats.split(","):
+        colscale = None
+        A32 = a64.float().contiguous()
+        if fmt == "f64":
+            A = a64
+        elif fmt == "f32":
+            A = A32
+        elif fmt == "bf16":
+            A = torch.empty(A32.shape, dtype=torch.bfloat16, device=dev)
+            cu.check(cu.cor_quantize(A32, cu.COR_BF16, A), "quantize")
+        else:
+            A = torch.empty(A32.shape, dtype=torch.uint8, device=dev)
+            colscale = torch.empty(A32.shape[1], dtype=torch.float32, device=dev)
+            cu.check(cu.cor_quantize(A32, cu.COR_FP8, A, colscale), "quantize")
+        if fmt != "f32":
+            del A32
+        torch.cuda.synchronize()
+        r = timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=colscale)
+        del A
+        acc = accuracy(torch, a64, r["U"], r["T"], r["V"], k)
+        ratio = acc["err_l"] / gold["err_l"]
+        if fmt == "f64":
+            ok = abs(acc["err_l"] - gold["err_l"]) <= 1e-12 and \
+                abs(acc["err_k"] - gold["err_k"]) <= 1e-12
+        elif fmt == "f32":
+            ok = abs(acc["err_l"] - gold["err_l"]) <= 1e-5
+        elif fmt == "bf16":
+            ok = ratio <= 1.05
+        else:
+            ok = ratio <= 1.05
+        res = {
+            "decomps_per_s": round(args.steps / r["elapsed"], 3),
+            "ms_per_decomp": round(r["elapsed"] / args.steps * 1e3, 4),
+            "latency_ms": {"p50": round(float(np.percentile(r["step_ms"], 50)), 4),
+                           "p99": round(float(np.percentile(r["step_ms"], 99)), 4)},
+            "err_l": acc["err_l"], "err_k": acc["err_k"],
+            "err_l_over_oracle": ratio, "err_k_over_oracle": acc["err_k"] / gold["err_k"],
+            "abs_diff_err_l": abs(acc["err_l"] - gold["err_l"]),
+            "orth_u": acc["orth_u"], "orth_v": acc["orth_v"],
+            "rule": C3_RULE[fmt], "at_fixed_error": bool(ok),
+            "pass_roofline": pass_roofline(fmt, l, r["prof"]),
+        }
+        if fmt in gq:
+            res["err_l_over_stored_format_oracle"] = acc["err_l"] / gq[fmt]["err_l"]
+            if fmt == "fp8":
+                res["stored_format_within_5pct"] = bool(
+                    abs(acc["err_l"] / gq[fmt]["err_l"] - 1.0) <= 0.05)
+        modes[fmt] = res
+        head = fmt if fmt == args.formats.split(",")[0] else None
+        if head:
+            first = (fmt, r)
+        print(f"# c3 {fmt}: {res['decomps_per_s']:.1f} decomps/s, eps/eps_oracle {ratio:.5f}, "
+              f"pass {res['pass_roofline']['frac']:.3f} of {res['pass_roofline']['bound']} peak",
+              file=sys.stderr, flush=True)
+    fmt0, r0 = first
+    main_mode = modes[fmt0]
+    roofline = dict(main_mode["pass_roofline"])
+    roofline["traffic"] = traffic_of(f"c3{fmt0}")
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_oracle(a64, k, p, q, seed)
+        cpu["cores_available"] = os.cpu_count()
+    return {
+        "metric": "CoR-UTV decompositions/s (roofline of the passes over A; p50/p99 latency) "
+                  "at fixed error",
+        "value": main_mode["decomps_per_s"],
+        "unit": "decomps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": main_mode["ms_per_decomp"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": fmt0, "data": "synthetic",
+        "config": {"workload": f"c3 {fmt0.upper()}: " + w["desc"], "m": a64.shape[0],
+                   "n": a64.shape[1], "k": k, "l": l, "q": q, "graph": r0["graph"],
+                   "omega_seed": seed},
+        "latency_ms": main_mode["latency_ms"],
+        "accuracy": {"err_l": main_mode["err_l"], "err_l_oracle": gold["err_l"],
+                     "err_l_opt": gold["err_l_opt"], "err_k": main_mode["err_k"],
+                     "err_k_oracle": gold["err_k"], "orth_u": main_mode["orth_u"],
+                     "orth_v": main_mode["orth_v"], "rule": main_mode["rule"],
+                     "at_fixed_error": main_mode["at_fixed_error"]},
+        "roofline": roofline,
+        "modes": modes,
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--formats", default="f64,f32,bf16,fp8",
+                    help="c3: pass formats to run, the first one is the line's value")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -354,6 +569,9 @@ def main():
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "c3":
+        print(json.dumps(bench_c3(args, w, cu, torch, np)))
+        return
     if args.workload == "c4batched":
         print(json.dumps(bench_batched(args, w, cu, torch, np)))
         return
@@ -366,129 +584,38 @@ def main():
     a64, sig = make_input(w, dev)
     dtype = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[w["prec"]]
     A = a64.to(dtype).contiguous()
-    if w["prec"] != "f64":
-        a_keep = a64
-    else:
-        a_keep = a64
-    U = torch.empty((m, l), dtype=torch.float64, device=dev)
-    T = torch.empty((l, l), dtype=torch.float64, device=dev)
-    V = torch.empty((n, l), dtype=torch.float64, device=dev)
-    perm = torch.empty((l,), dtype=torch.int32, device=dev)
-    prob = cu.make_problem(A, k, p, q, seed=12345, U=U, T=T, V=V, perm=perm)
-    stream = torch.cuda.Stream()
-    st, plan = cu.cor_plan_create([prob], cu.cor_opts(0, 0))
-    cu.check(st, "plan_create")
-    graph = not args.no_graph
-    with torch.cuda.stream(stream):
-        if graph:
-            cu.check(cu.cor_plan_capture(plan, stream), "plan_capture")
-        for _ in range(args.warmup):
-            cu.check(cu.cor_plan_run(plan, stream), "plan_run")
-        stream.synchronize()
-        # Timed region: K steps, events around every step (latency) and, in
-        # eager mode, around every pass over A (roofline).
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-        cu.cor_profile_enable(True)
-        cu.cor_profile_read()  # reset counters
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev[0].record(stream)
-        for i in range(args.steps):
-            cu.check(cu.cor_plan_run(plan, stream), "plan_run")
-            ev[i + 1].record(stream)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        prof_timed = cu.cor_profile_read()
-        # Kernel timing of the passes over A: in graph mode the passes run
-        # inside the graph, so a second, eager pass over the same steps
-        # brackets each pass launch with events on the plan's stream.
-        if graph:
-            st2, plan2 = cu.cor_plan_create([prob], cu.cor_opts(0, 0))
-            cu.check(st2, "plan_create")
-            cu.cor_profile_read()
-            for _ in range(min(args.steps, 20)):
-                cu.check(cu.cor_plan_run(plan2, stream), "plan_run")
-            torch.cuda.synchronize()
-            prof = cu.cor_profile_read()
-            cu.cor_plan_destroy(plan2)
-        else:
-            prof = prof_timed
-        cu.cor_profile_enable(False)
-    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
-    elapsed = t1 - t0
-    value = args.steps / elapsed
-
-    # Accuracy of the timed result (fixed-error check): explicit FP64 residual
-    # against the FP64 matrix, the optimum from the known spectrum, orthogonality.
-    torch.cuda.synchronize()
-    nA = torch.linalg.norm(a_keep)
-    R = a_keep - (U @ T) @ V.T
-    err_l = float(torch.linalg.norm(R) / nA)
-    Rk = a_keep - (U[:, :k] @ T[:k, :]) @ V.T
-    err_k = float(torch.linalg.norm(Rk) / nA)
-    del R, Rk
-    orth_u = float(torch.linalg.norm(U.T @ U - torch.eye(l, device=dev, dtype=torch.float64)))
-    orth_v = float(torch.linalg.norm(V.T @ V - torch.eye(l, device=dev, dtype=torch.float64)))
+    r = timed_plan(cu, torch, np, A, k, p, q, 12345, args)
+    acc = accuracy(torch, a64, r["U"], r["T"], r["V"], k)
     s2 = np.concatenate([sig ** 2, np.zeros(max(0, min(m, n) - len(sig)))])
-    opt_l = float(np.sqrt(s2[l:].sum() / s2.sum()))
-    opt_k = float(np.sqrt(s2[k:].sum() / s2.sum()))
-
-    launches = max(1, prof["launches"])
-    avg_s = prof["ms"] / launches / 1e3
-    prec = w["prec"]
-    flops_per_launch = prof["flops"] / launches
-    bytes_per_launch = prof["bytes"] / launches
-    if prec == "f32" and l >= 40:
-        bound, peak, unit_r = "mfma", PEAKS["f32"], "TFLOP/s"
-        achieved = flops_per_launch / avg_s / 1e12
-    elif prec == "f64" and l >= 39:
-        bound, peak, unit_r = "mfma", PEAKS["f64"], "TFLOP/s"
-        achieved = flops_per_launch / avg_s / 1e12
-    else:
-        bound, peak, unit_r = "hbm", PEAKS["hbm_GBs"], "GB/s"
-        achieved = bytes_per_launch / avg_s / 1e9
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
-    if os.path.exists(tpath):
-        with open(tpath) as f:
-            tr = json.load(f)
-        if tr.get("source_hash") == source_hash():
-            traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit_r,
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "k_sketch (passes over A)", "avg_launch_us": round(avg_s * 1e6, 2),
-                "algorithmic_flops_per_launch": flops_per_launch,
-                "algorithmic_bytes_per_launch": bytes_per_launch}
-
+    acc["err_l_opt"] = float(np.sqrt(s2[l:].sum() / s2.sum()))
+    acc["err_k_opt"] = float(np.sqrt(s2[k:].sum() / s2.sum()))
+    roofline = pass_roofline(w["prec"], l, r["prof"])
+    roofline["traffic"] = traffic_of(args.workload)
     cpu = None
     if not args.no_cpu:
-        a_host = a_keep.cpu().numpy()
-        cpu = cpu_baseline(a_host, w)
+        cpu = cpu_baseline_oracle(a64, k, p, q, 12345)
         cpu["cores_available"] = os.cpu_count()
-
     out = {
         "metric": "CoR-UTV decompositions/s (roofline of the passes over A; p50/p99 latency)",
-        "value": round(value, 3),
+        "value": round(args.steps / r["elapsed"], 3),
         "unit": "decomps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "ms_per_step": round(r["elapsed"] / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": prec,
+        "dtype": w["prec"],
         "data": "synthetic",
         "config": {"workload": args.workload + ": " + w["desc"], "m": m, "n": n, "k": k, "l": l,
-                   "q": q, "graph": graph},
-        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
-                       "p99": round(float(np.percentile(step_ms, 99)), 4)},
-        "accuracy": {"err_l": err_l, "err_l_opt": opt_l, "err_k": err_k, "err_k_opt": opt_k,
-                     "orth_u": orth_u, "orth_v": orth_v},
+                   "q": q, "graph": r["graph"]},
+        "latency_ms": {"p50": round(float(np.percentile(r["step_ms"], 50)), 4),
+                       "p99": round(float(np.percentile(r["step_ms"], 99)), 4)},
+        "accuracy": acc,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    cu.cor_plan_destroy(plan)
     print(json.dumps(out))
 
 

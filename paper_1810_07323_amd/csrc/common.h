@@ -17,6 +17,7 @@ enum Prec : int32_t { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_FP8 = 3 };
 constexpr int LMAX = 264;   // largest l = k + p supported
 constexpr int LPMAX = 272;  // LMAX padded to a multiple of 16
 constexpr int NTMAX = 17;   // LPMAX / 16
+constexpr int SCALE_CHUNKS = 64;  // most row chunks of an FP8 operand-scale reduction
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -67,6 +68,10 @@ struct Prob {
     double* tau;   // 2 LMAX: tau[j] of the reflectors, then the column signs of T
     double* rep;   // 16 doubles of report scratch
     int32_t* flags;
+    // FP8: per-chunk column maxima of the factor an operand copy is made from
+    // ([chunks][lp]) and the row chunks of each side.
+    float* scpart;
+    int32_t sch_m, sch_n;
 
     // Outputs.
     double* U;

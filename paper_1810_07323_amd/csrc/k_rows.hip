@@ -182,7 +182,13 @@ hipError_t launch_make_op(const LaunchGroup& g, int side, hipStream_t s) {
 
 // FP8 operand scales: s_c = max_r |F'[r][c]| / 448 (1 if zero), F' = F or
 // diag(colscale) F on the n-side.  One block per problem.
-__global__ __launch_bounds__(256) void k_op_scales(const Prob* __restrict__ probs,
+// FP8 operand scales of an FP64 factor F (rows x l; n-side rows scaled by the
+// column scales of A first): s_c = max_r |F_rc| / 448 (1 for a zero column).
+// Stage 1: a block per row chunk writes the chunk's column maxima, one thread
+// per column (the rows are read as contiguous runs); stage 2: a block per
+// problem takes the maximum over the chunks.  Maxima are exact, so the result
+// does not depend on the chunking.
+__global__ __launch_bounds__(256) void k_op_colmax(const Prob* __restrict__ probs,
                                                    const int32_t* __restrict__ pidx,
                                                    const int32_t* __restrict__ toff, int cnt,
                                                    int side, int iter) {
@@ -190,28 +196,49 @@ __global__ __launch_bounds__(256) void k_op_scales(const Prob* __restrict__ prob
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (P.prec != P_FP8 || iter > P.q) return;
     const int64_t rows = side == SIDE_M ? P.m : P.n;
+    const int nch = side == SIDE_M ? P.sch_m : P.sch_n;
     const double* F = side == SIDE_M ? P.Q1 : P.Q2;
-    float* sc = side == SIDE_M ? P.qscale : P.xscale;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = wave; c < P.lp; c += 4) {
+    const int64_t per = (rows + nch - 1) / nch;
+    const int64_t r0 = (int64_t)local * per;
+    const int64_t r1 = r0 + per < rows ? r0 + per : rows;
+    for (int c = threadIdx.x; c < P.lp; c += 256) {
         float mx = 0.0f;
         if (c < P.l) {
-            for (int64_t r = lane; r < rows; r += 64) {
+            for (int64_t r = r0; r < r1; r++) {
                 double x = F[r * P.l + c];
                 if (side == SIDE_N) x *= (double)P.colscale[r];
                 mx = fmaxf(mx, fabsf((float)x));
             }
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-        if (lane == 0) sc[c] = mx > 0.0f ? mx / 448.0f : 1.0f;
+        P.scpart[(int64_t)local * P.lp + c] = mx;
     }
 }
 
-hipError_t launch_op_scales(const LaunchGroup& g, int side, int iter, hipStream_t s) {
-    if (g.blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_op_scales, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff,
-                       g.count, side, iter);
+__global__ __launch_bounds__(256) void k_op_scales(const Prob* __restrict__ probs,
+                                                   const int32_t* __restrict__ pidx,
+                                                   const int32_t* __restrict__ toff, int cnt,
+                                                   int side, int iter) {
+    int local;
+    const Prob& P = group_prob(probs, pidx, toff, cnt, local);
+    if (P.prec != P_FP8 || iter > P.q) return;
+    const int nch = side == SIDE_M ? P.sch_m : P.sch_n;
+    float* sc = side == SIDE_M ? P.qscale : P.xscale;
+    for (int c = threadIdx.x; c < P.lp; c += 256) {
+        float mx = 0.0f;
+        for (int ch = 0; ch < nch; ch++) mx = fmaxf(mx, P.scpart[(int64_t)ch * P.lp + c]);
+        sc[c] = mx > 0.0f ? mx / 448.0f : 1.0f;
+    }
+}
+
+hipError_t launch_op_scales(const LaunchGroup& chunks, const LaunchGroup& one, int side, int iter,
+                            hipStream_t s) {
+    if (chunks.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_op_colmax, dim3(chunks.blocks), dim3(256), 0, s, chunks.probs,
+                       chunks.pidx, chunks.toff, chunks.count, side, iter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_op_scales, dim3(one.blocks), dim3(256), 0, s, one.probs, one.pidx,
+                       one.toff, one.count, side, iter);
     return hipGetLastError();
 }
 

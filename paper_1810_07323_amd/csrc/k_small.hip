@@ -1510,13 +1510,23 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ a, in
     out[idx] = f32_to_bf16(a[r * lda + c]);
 }
 
+// Column scales of cor_quantize: a block takes 64 columns, its four waves
+// stride over the rows (each wave reads 64 consecutive floats of a row), and
+// the four partial maxima meet in LDS.
 __global__ __launch_bounds__(256) void k_colscale(const float* __restrict__ a, int64_t m, int64_t n,
                                                   int64_t lda, float* __restrict__ s) {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= n) return;
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
     float mx = 0.0f;
-    for (int64_t r = 0; r < m; r++) mx = fmaxf(mx, fabsf(a[r * lda + c]));
-    s[c] = mx > 0.0f ? mx / 448.0f : 1.0f;
+    if (c < n)
+        for (int64_t r = wave; r < m; r += 4) mx = fmaxf(mx, fabsf(a[r * lda + c]));
+    part[wave][lane] = mx;
+    __syncthreads();
+    if (wave == 0 && c < n) {
+        mx = fmaxf(fmaxf(part[0][lane], part[1][lane]), fmaxf(part[2][lane], part[3][lane]));
+        s[c] = mx > 0.0f ? mx / 448.0f : 1.0f;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_to_fp8(const float* __restrict__ a, int64_t m, int64_t n,
@@ -1538,7 +1548,7 @@ hipError_t launch_quantize(const float* a32, int64_t m, int64_t n, int64_t lda, 
                            reinterpret_cast<uint16_t*>(out));
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_colscale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a32, m, n,
+    hipLaunchKernelGGL(k_colscale, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, a32, m, n,
                        lda, colscale);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

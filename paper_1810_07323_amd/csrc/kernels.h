@@ -49,8 +49,11 @@ enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2,
 hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int iter,
                         hipStream_t s);
 hipError_t launch_gather_v(const LaunchGroup& g, hipStream_t s);  // blocks: ceil(n*l/256)
-// Column maxima of the FP64 factor and FP8 operand scales.
-hipError_t launch_op_scales(const LaunchGroup& g, int side, int iter, hipStream_t s);
+// Column maxima of the FP64 factor and FP8 operand scales: per row chunk
+// (`chunks`: blocks per problem = its chunk count), then per problem (`one`:
+// one block per problem).
+hipError_t launch_op_scales(const LaunchGroup& chunks, const LaunchGroup& one, int side, int iter,
+                            hipStream_t s);
 
 // One block per problem.
 enum CholMode : int32_t { CHOL_FIRST = 0, CHOL_SECOND = 1 };

@@ -101,7 +101,7 @@ struct Layout {
 
 enum {
     O_XOP, O_QOP, O_XSC, O_QSC, O_YPART, O_Y, O_QA, O_Q1, O_Q2, O_GPART, O_G, O_R, O_RINV,
-    O_RACC, O_R2, O_QT, O_TAU, O_REP, O_FLAGS, O_PERM, O_COUNT
+    O_RACC, O_R2, O_QT, O_TAU, O_REP, O_FLAGS, O_PERM, O_SCPART, O_COUNT
 };
 
 // K splits of a pass: about `target` blocks in all (row blocks x splits, never
@@ -122,6 +122,11 @@ static void split_k(int64_t rows, int64_t K, int bk, int target, int prec, int n
     int64_t c = roundup(cdiv(K, sp), bk);
     *kc = c;
     *s = (int32_t)cdiv(K, c);
+}
+
+// Row chunks of the FP8 operand-scale column maxima (at least 128 rows each).
+static int32_t scale_chunks(int64_t rows) {
+    return (int32_t)std::min<int64_t>(SCALE_CHUNKS, std::max<int64_t>(1, cdiv(rows, 128)));
 }
 
 static int gram_groups(int lp) {  // blocks per row chunk: the upper 16 x 16 tiles
@@ -195,6 +200,7 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
     sizes[O_REP] = 128 * 8;
     sizes[O_FLAGS] = 64;
     sizes[O_PERM] = (size_t)l * 4;
+    sizes[O_SCPART] = prec == P_FP8 ? (size_t)SCALE_CHUNKS * L.lp * 4 : 0;
     size_t off = 0;
     for (int i = 0; i < O_COUNT; i++) {
         L.off[i] = off;
@@ -244,6 +250,7 @@ struct Plan {
         double bytes = 0, flops = 0;  // algorithmic cost of one launch
     };
     Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, applyM, applyN, vg, r2, norm;
+    Grp scM, scN;  // FP8 operand scales: row chunks of the column maxima
     std::vector<Grp> skAX, skATX;  // per (precision, column tiles)
     std::vector<Grp> formU;        // per register-tile class of l (nt holds l)
     Grp applyU;                    // U = Q1 Qs for the problems with u_via_qs
@@ -337,6 +344,8 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     auto R_vg = per([&](int i) { return cdiv(probs[i].n * P->lay[i].l, 256); });
     auto R_r2 = per([&](int i) { return (int64_t)P->lay[i].nt * P->lay[i].nt; });
     auto R_norm = per([&](int) { return (int64_t)64; });
+    auto R_scM = per([&](int i) { return probs[i].prec == COR_FP8 ? (int64_t)scale_chunks(probs[i].m) : 0; });
+    auto R_scN = per([&](int i) { return probs[i].prec == COR_FP8 ? (int64_t)scale_chunks(probs[i].n) : 0; });
     // Sketch tables: one per (precision, column-tile count) class.
     std::map<std::pair<int, int>, std::vector<int>> classes;
     for (int i = 0; i < count; i++) classes[{probs[i].prec, P->lay[i].nt}].push_back(i);
@@ -455,6 +464,9 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         d.tau = (double*)(w + L.off[O_TAU]);
         d.rep = (double*)(w + L.off[O_REP]);
         d.flags = (int32_t*)(w + L.off[O_FLAGS]);
+        d.scpart = (float*)(w + L.off[O_SCPART]);
+        d.sch_m = scale_chunks(q.m);
+        d.sch_n = scale_chunks(q.n);
         d.U = q.U; d.T = q.T; d.V = q.V;
         d.perm = q.perm ? q.perm : (int32_t*)(w + L.off[O_PERM]);
         d.omega = q.omega;
@@ -509,6 +521,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->small = mk(R_small);
     P->applyM = mk(R_applyM); P->applyN = mk(R_applyN); P->applyU = mk(R_applyU);
     P->vg = mk(R_vg); P->r2 = mk(R_r2); P->norm = mk(R_norm);
+    P->scM = mk(R_scM); P->scN = mk(R_scN);
     for (auto& u : urefs) {
         Plan::Grp g = mk(u.r);
         g.nt = u.lmax;
@@ -549,7 +562,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
     const bool fp8 = (P->prec_mix >> P_FP8) & 1;
     if (P->report) E(launch_normA(P->norm.g, s));
     E(launch_omega(P->omega.g, s));  // Q2 <- Omega (FP64)
-    if (fp8) E(launch_op_scales(P->small.g, SIDE_N, 0, s));
+    if (fp8) E(launch_op_scales(P->scN.g, P->small.g, SIDE_N, 0, s));
     E(launch_make_op(P->opN.g, SIDE_N, s));  // X <- Omega in the pass format
     for (int it = 0; it <= P->max_q; it++) {
         // Y1 = A X, Q1 R1 = Y1 (CholeskyQR2)
@@ -566,7 +579,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
             E(launch_apply(P->applyM.g, SIDE_M, AP_QA_RINV_Q, P->lmax, it, s));
         }
         if (fp8) {
-            E(launch_op_scales(P->small.g, SIDE_M, it, s));
+            E(launch_op_scales(P->scM.g, P->small.g, SIDE_M, it, s));
             E(launch_make_op(P->opM.g, SIDE_M, s));
         }
         // Y2 = A^T Q1, Q2 R2 = Y2 (CholeskyQR2); X <- Q2
@@ -584,7 +597,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         if (P->last[it]) E(launch_r2(P->r2.g, it, s));
         if (P->second[it]) E(launch_apply(P->applyN.g, SIDE_N, AP_QA_RINV_Q, P->lmax, it, s));
         if (fp8 && it < P->max_q) {
-            E(launch_op_scales(P->small.g, SIDE_N, it, s));
+            E(launch_op_scales(P->scN.g, P->small.g, SIDE_N, it, s));
             E(launch_make_op(P->opN.g, SIDE_N, s));
         }
     }
