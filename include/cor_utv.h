@@ -131,6 +131,27 @@ cor_status cor_utv_batched(const cor_problem* probs, int32_t count, const cor_op
                            cor_info* infos, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation): the
+ * decomposition of cor_utv_ex run entirely inside a fixed array of
+ * COR_NOALLOC_SCRATCH_BYTES of device memory that the library holds per
+ * device from the time its code is loaded until the process ends.  Same
+ * arguments, kernels and results (bit for bit) as cor_utv_ex; device_ms is
+ * not measured (0).  The plan (descriptor, launch tables, workspace) must fit
+ * the array: cor_workspace_bytes(m, n, l, prec) <= COR_NOALLOC_SCRATCH_BYTES,
+ * else COR_E_INVAL with the sizes in cor_last_error().  No hipMalloc, hipFree
+ * or other allocating device call is made.  Returns after the work on
+ * `stream` has completed.  All calls on one device share that device's
+ * array, which keeps the last call's contents (each call clears what must
+ * start at zero): calls from several threads of one process are serialised
+ * by the library; work that overlaps a call on the same device and touches
+ * the array by other means races with it.
+ * ------------------------------------------------------------------------- */
+#define COR_NOALLOC_SCRATCH_BYTES (64u << 20)
+cor_status cor_utv_ex_noalloc(const cor_problem* prob, const cor_opts* opts, cor_info* info,
+                              void* stream);
+
+/* ---------------------------------------------------------------------------
  * Plans: the executor behind the calls above, exposed for callers that replay
  * the same decomposition(s) many times.  A plan owns its workspace and
  * device-side descriptors; cor_plan_run() only enqueues kernels on `stream`

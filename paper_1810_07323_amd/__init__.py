@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcorutv.so")
 COR_OK, COR_E_INVAL, COR_E_NOMEM, COR_E_DEVICE, COR_E_NUMERIC, COR_E_BUSY, COR_E_NOTFOUND = range(7)
 COR_F64, COR_F32, COR_BF16, COR_FP8 = range(4)
 COR_FLAG_RANK_DEFICIENT, COR_FLAG_NONFINITE = 2, 4
+COR_NOALLOC_SCRATCH_BYTES = 64 << 20
 PREC = {"f64": COR_F64, "f32": COR_F32, "bf16": COR_BF16, "fp8": COR_FP8}
 
 
@@ -62,6 +63,8 @@ _SIGS = {
     "cor_utv": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
                           C.c_int32, _P, _P, _P, C.POINTER(cor_info), _P]),
     "cor_utv_ex": (C.c_int, [C.POINTER(cor_problem), C.POINTER(cor_opts), C.POINTER(cor_info), _P]),
+    "cor_utv_ex_noalloc": (C.c_int, [C.POINTER(cor_problem), C.POINTER(cor_opts),
+                                     C.POINTER(cor_info), _P]),
     "cor_utv_batched": (C.c_int, [C.POINTER(cor_problem), C.c_int32, C.POINTER(cor_opts),
                                   C.POINTER(cor_info), _P]),
     "cor_plan_create": (C.c_int, [C.POINTER(cor_problem), C.c_int32, C.POINTER(cor_opts),
@@ -177,6 +180,13 @@ def cor_utv_ex(problem, opts=None, stream=None):
     info = cor_info()
     st = lib().cor_utv_ex(C.byref(problem), C.byref(opts) if opts is not None else None,
                           C.byref(info), stream_handle(stream))
+    return st, info
+
+
+def cor_utv_ex_noalloc(problem, opts=None, stream=None):
+    info = cor_info()
+    st = lib().cor_utv_ex_noalloc(C.byref(problem), C.byref(opts) if opts is not None else None,
+                                  C.byref(info), stream_handle(stream))
     return st, info
 
 
