@@ -86,6 +86,8 @@ typedef struct {
     double device_ms; /* device time of the call, or submit-to-completion for served requests    */
     int32_t flags;    /* COR_FLAG_*                                                               */
     int32_t l;        /* k + p                                                                    */
+    double m_check;   /* COR_M_EXPLICIT / COR_M_APPROX with report: ||M - R2^T||_F / ||M||_F,   */
+                      /* the compressed matrix against the identity M = R2^T (0 otherwise)      */
 } cor_info;
 
 /* One decomposition request. */
@@ -103,11 +105,35 @@ typedef struct {
     int32_t* perm;         /* optional device out, l int32                                        */
 } cor_problem;
 
+/* Compression of A to the l x l core M (cor_opts.compress):
+ *   COR_M_R2T      (default) M = Q1^T A Q2 = R2^T: no further pass over A, since
+ *                  A^T Q1 = Q2 R2 (eq. (14) without its product);
+ *   COR_M_EXPLICIT M = Q1^T (A Q2) as eq. (14) prints it: one more pass over A
+ *                  (a check of the identity, reported as cor_info.m_check);
+ *   COR_M_APPROX   M = Q1^T Y1 (Q2^T X)^+ = R1 (Q2^T X)^-1, eq. (18), with Y1 = A X
+ *                  the last power step's sketch (X = Omega when q = 0, else the
+ *                  previous Q2; the non-updated C2 of Alg. 3): no further pass,
+ *                  an l x l solve (Gauss-Jordan, partial pivoting) instead.
+ * Orientation (cor_opts.orient): COR_URV (default) returns T upper triangular
+ * for every shape; COR_ULV returns A ~ U L V^T with L lower triangular
+ * (Sec. III: the other orientation, for m < n), computed as the URV of A^T
+ * (a transposed copy of A in the workspace; not available for COR_FP8):
+ * U = V', L = T'^T, V = U'.  For ULV the optional test matrix `omega` is
+ * m x l, perm permutes the columns of U (U[:, j] = Q[:, perm[j]] for the
+ * row-space basis Q), and the rank-k truncation is U L[:, :k] V[:, :k]^T. */
+#define COR_M_R2T 0
+#define COR_M_EXPLICIT 1
+#define COR_M_APPROX 2
+#define COR_URV 0
+#define COR_ULV 1
+
 typedef struct {
     int32_t report;      /* 0: nothing; 1: fill err_l, err_k, orth_u, orth_v of cor_info         */
     int32_t cholqr2_all; /* 0 (default): one CholeskyQR pass after each product inside the power  */
                          /*   loop and two for the final pair (the spans are the same in exact    */
                          /*   arithmetic); 1: two passes after every product                      */
+    int32_t compress;    /* COR_M_R2T (0, default), COR_M_EXPLICIT, COR_M_APPROX                 */
+    int32_t orient;      /* COR_URV (0, default) or COR_ULV                                       */
 } cor_opts;
 
 /* ---------------------------------------------------------------------------

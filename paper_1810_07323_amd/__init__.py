@@ -19,13 +19,15 @@ COR_OK, COR_E_INVAL, COR_E_NOMEM, COR_E_DEVICE, COR_E_NUMERIC, COR_E_BUSY, COR_E
 COR_F64, COR_F32, COR_BF16, COR_FP8 = range(4)
 COR_FLAG_RANK_DEFICIENT, COR_FLAG_NONFINITE = 2, 4
 COR_NOALLOC_SCRATCH_BYTES = 64 << 20
+COR_M_R2T, COR_M_EXPLICIT, COR_M_APPROX = 0, 1, 2
+COR_URV, COR_ULV = 0, 1
 PREC = {"f64": COR_F64, "f32": COR_F32, "bf16": COR_BF16, "fp8": COR_FP8}
 
 
 class cor_info(C.Structure):
     _fields_ = [("err_l", C.c_double), ("err_k", C.c_double), ("orth_u", C.c_double),
                 ("orth_v", C.c_double), ("device_ms", C.c_double), ("flags", C.c_int32),
-                ("l", C.c_int32)]
+                ("l", C.c_int32), ("m_check", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -39,7 +41,8 @@ class cor_problem(C.Structure):
 
 
 class cor_opts(C.Structure):
-    _fields_ = [("report", C.c_int32), ("cholqr2_all", C.c_int32)]
+    _fields_ = [("report", C.c_int32), ("cholqr2_all", C.c_int32), ("compress", C.c_int32),
+                ("orient", C.c_int32)]
 
 
 class cor_server_cfg(C.Structure):
@@ -299,7 +302,8 @@ def cor_release():
 # ---------------------------------------------------------------------------
 # Convenience: allocate outputs with torch and run one decomposition.
 # ---------------------------------------------------------------------------
-def decompose(A, k, p, q, seed=0, omega=None, colscale=None, report=False, stream=None):
+def decompose(A, k, p, q, seed=0, omega=None, colscale=None, report=False, stream=None,
+              compress=COR_M_R2T, orient=COR_URV):
     """Return (U, T, V, perm, info) for device matrix A (torch tensor on cuda)."""
     import torch
 
@@ -314,6 +318,6 @@ def decompose(A, k, p, q, seed=0, omega=None, colscale=None, report=False, strea
     if omega is not None:
         om = torch.as_tensor(omega, dtype=torch.float64, device=dev).contiguous()
     pr = make_problem(A, k, p, q, seed, U, T, V, perm, om, colscale)
-    st, info = cor_utv_ex(pr, cor_opts(1 if report else 0, 0), stream)
+    st, info = cor_utv_ex(pr, cor_opts(1 if report else 0, 0, compress, orient), stream)
     check(st, "cor_utv_ex")
     return U, T, V, perm, info

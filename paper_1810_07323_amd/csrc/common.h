@@ -81,6 +81,24 @@ struct Prob {
 
     const double* omega;  // optional caller test matrix (n x l FP64)
     uint64_t seed;
+
+    // Compression (eq. (14) / eq. (18)) and orientation options.
+    int32_t mmode;       // M_R2T, M_EXPLICIT or M_APPROX
+    int32_t ulv;         // 1: this is the URV of A^T behind a ULV request
+    const double* msrc;  // l x l, msrc[c][i] = M[i][c]: R2 (M = R2^T) or Mx
+    double* Mx;          // l x l: M^T from the explicit product or eq. (18)
+    double* R1;          // l x l: R factor of the last Y1 (eq. (18))
+    double* Xk;          // n x l: the last power step's input X (eq. (18))
+    double* Tout;        // ULV: the caller's T, written as the transpose of T
+    const void* ulv_src; // ULV: the caller's A (m_caller = n rows, leading dimension ulv_lda)
+    int64_t ulv_lda;
+};
+
+// Compression of A to the l x l core.
+enum MMode : int32_t {
+    M_R2T = 0,       // M = Q1^T A Q2 = R2^T, no pass over A
+    M_EXPLICIT = 1,  // M = Q1^T (A Q2), one more pass over A (eq. (14) as printed)
+    M_APPROX = 2     // M = Q1^T Y1 (Q2^T X)^+ = R1 (Q2^T X)^-1 (eq. (18))
 };
 
 // Whether the orthonormalisation of this iteration takes the second

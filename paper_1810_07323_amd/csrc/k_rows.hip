@@ -255,6 +255,7 @@ __global__ __launch_bounds__(256) void k_sum(const Prob* __restrict__ probs,
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter > P.q) return;
+    if (iter < 0 && P.mmode != M_EXPLICIT) return;  // the pass A Q2 of eq. (14)
     const int64_t rows = side == SIDE_M ? P.m : P.n;
     const int S = side == SIDE_M ? P.s_ax : P.s_atx;
     const int l = P.l, lp = P.lp, nq = lp / 4;
@@ -342,11 +343,14 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     __shared__ double part[3][4][64];
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
+    constexpr bool CROSS = SRC == GSRC_XM || SRC == GSRC_XA;
     if (iter >= 0 && iter > P.q) return;
     if (SRC == GSRC_QA && !second_pass(P, iter)) return;
+    if (CROSS && P.mmode != (SRC == GSRC_XM ? M_EXPLICIT : M_APPROX)) return;
     const int l = P.l, lp = P.lp;
     const int nt = lp / 16;
-    const int ntu = nt * (nt + 1) / 2;
+    // symmetric Grams: the upper tiles; cross products Z1^T Z2: every tile
+    const int ntu = CROSS ? nt * nt : nt * (nt + 1) / 2;
     const int gb = side == SIDE_M ? P.gb_m : P.gb_n;
     // Blocks are handed to the eight XCDs in turn (block b to XCD b mod 8),
     // each with its own L2: with a multiple of 8 chunks, chunk c's tiles all
@@ -364,7 +368,11 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     const int rb = side == SIDE_M ? P.rb_m : P.rb_n;
     const int64_t c0 = (int64_t)chunk * rb;
     const int64_t c1 = min(rows, c0 + rb);
-    const double* __restrict__ Z = SRC == GSRC_Y ? P.Y : SRC == GSRC_QA ? P.Qa : SRC == GSRC_U ? P.U : P.V;
+    const double* __restrict__ Z = SRC == GSRC_Y ? P.Y : SRC == GSRC_QA ? P.Qa : SRC == GSRC_U ? P.U
+                                 : SRC == GSRC_V ? P.V : SRC == GSRC_XM ? P.Q1 : P.Q2;
+    // second operand: Z itself, or A Q2 (in Y) for M = Q1^T A Q2, or the last
+    // power step's input X for Q2^T X
+    const double* __restrict__ Z2 = SRC == GSRC_XM ? P.Y : SRC == GSRC_XA ? P.Xk : Z;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -373,7 +381,12 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     const int64_t r0 = c0 + wave * qr;
     const int64_t r1 = min(c1, r0 + qr);
     int ta, tb;
-    tile_of(tt, nt, ta, tb);
+    if (CROSS) {
+        ta = tt / nt;
+        tb = tt - ta * nt;
+    } else {
+        tile_of(tt, nt, ta, tb);
+    }
     const int ca = 16 * ta + li, cb = 16 * tb + li;
     const bool okb = cb < l;
     // MFMA K slot g of step s is row rs + 4 s + g; U steps per batch, the next
@@ -387,15 +400,15 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     // older batch while the newer one is in flight.
     const int cac = min(ca, l - 1), cbc = min(cb, l - 1);
     gdouble* Zg = as_global(Z);
+    gdouble* Z2g = as_global(Z2);
     gdouble* zw = as_global(g_zero_word);
     auto load = [&](int64_t rs, double (&va)[U], double (&vb)[U]) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int64_t r = rs + 4 * u + lg;
             const bool okr = r < r1;
-            gdouble* zr = Zg + r * l;
-            va[u] = *(okr ? zr + cac : zw);
-            vb[u] = *(okr ? zr + cbc : zw);
+            va[u] = *(okr ? Zg + r * l + cac : zw);
+            vb[u] = *(okr ? Z2g + r * l + cbc : zw);
         }
     };
     load(r0, xa, xb);
@@ -435,8 +448,79 @@ hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStr
         case GSRC_QA: return launch_gram_t<GSRC_QA>(g, side, iter, s);
         case GSRC_U: return launch_gram_t<GSRC_U>(g, side, iter, s);
         case GSRC_V: return launch_gram_t<GSRC_V>(g, side, iter, s);
+        case GSRC_XM: return launch_gram_t<GSRC_XM>(g, side, iter, s);
+        case GSRC_XA: return launch_gram_t<GSRC_XA>(g, side, iter, s);
     }
     return hipErrorInvalidValue;
+}
+
+// Cross products Z1^T Z2 (every entry, no mirroring) from the partial sums,
+// in the same fixed order as k_gram_reduce.  M = Q1^T (A Q2) is stored
+// transposed into Mx (Mx[b][a] = M[a][b], the layout in which the QRCP reads
+// R2 for M = R2^T); Q2^T X goes to G as it is.
+__global__ __launch_bounds__(256) void k_xreduce(const Prob* __restrict__ probs,
+                                                 const int32_t* __restrict__ pidx,
+                                                 const int32_t* __restrict__ toff, int cnt,
+                                                 int src) {
+    __shared__ double part[4][64];
+    int local;
+    const Prob& P = group_prob(probs, pidx, toff, cnt, local);
+    if (P.mmode != (src == GSRC_XM ? M_EXPLICIT : M_APPROX)) return;
+    const int l = P.l;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e = local * 64 + lane;
+    const int nb = src == GSRC_XM ? P.gb_m : P.gb_n;
+    const bool in = e < l * l;
+    double s = 0.0;
+    if (in) {
+        const int64_t ll = (int64_t)l * l;
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int c = wave;
+        for (; c + 12 < nb; c += 16) {
+            s += P.gpart[c * ll + e];
+            s1 += P.gpart[(c + 4) * ll + e];
+            s2 += P.gpart[(c + 8) * ll + e];
+            s3 += P.gpart[(c + 12) * ll + e];
+        }
+        for (; c < nb; c += 4) s += P.gpart[c * ll + e];
+        s = (s + s1) + (s2 + s3);
+    }
+    part[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && in) {
+        const double g = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        const int a = e / l, b = e - (e / l) * l;
+        if (src == GSRC_XM) P.Mx[(int64_t)b * l + a] = g;
+        else P.G[e] = g;
+        if (!isfinite(g)) atomicOr(P.flags, FLAG_NONFINITE);
+    }
+}
+
+hipError_t launch_xreduce(const LaunchGroup& g, int src, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xreduce, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff,
+                       g.count, src);
+    return hipGetLastError();
+}
+
+// The last power step's input X (Q2 of the previous step, or Omega) kept
+// for eq. (18) before the step's n-side orthonormalisation overwrites it.
+__global__ __launch_bounds__(256) void k_keep_x(const Prob* __restrict__ probs,
+                                                const int32_t* __restrict__ pidx,
+                                                const int32_t* __restrict__ toff, int cnt,
+                                                int iter) {
+    int local;
+    const Prob& P = group_prob(probs, pidx, toff, cnt, local);
+    if (P.mmode != M_APPROX || iter != P.q) return;
+    const int64_t e = (int64_t)local * 256 + threadIdx.x;
+    if (e < P.n * P.l) P.Xk[e] = P.Q2[e];
+}
+
+hipError_t launch_keep_x(const LaunchGroup& g, int iter, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keep_x, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff,
+                       g.count, iter);
+    return hipGetLastError();
 }
 
 // G[a][b] = G[b][a] = sum over chunks of gpart[chunk][min][max].  A block

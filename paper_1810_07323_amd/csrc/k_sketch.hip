@@ -137,6 +137,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
     const int j = find_group(toff, cnt, blockIdx.x);
     const Prob& P = probs[pidx[j]];
     if (iter > P.q) return;
+    if (iter < 0 && P.mmode != M_EXPLICIT) return;  // the pass A Q2 of eq. (14)
     const int local = blockIdx.x - toff[j];
 
     const int64_t rows = TRANS ? P.n : P.m;    // output rows

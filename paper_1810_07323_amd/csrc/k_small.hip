@@ -569,13 +569,17 @@ hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipSt
 }
 
 // R2 = R' R (both upper triangular): the R factor of Y2 after both
-// CholeskyQR passes.  One block per 16 x 16 output tile.
+// CholeskyQR passes (dst 0), or R1 of the last Y1 for eq. (18) (dst 1).  One
+// block per 16 x 16 output tile.
 __global__ __launch_bounds__(256) void k_r2(const Prob* __restrict__ probs,
                                             const int32_t* __restrict__ pidx,
-                                            const int32_t* __restrict__ toff, int cnt, int iter) {
+                                            const int32_t* __restrict__ toff, int cnt, int iter,
+                                            int dst) {
     int local;
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
-    if (iter != P.q) return;  // only the R factor of the last Y2 is used
+    if (iter != P.q) return;  // only the R factors of the last Y1, Y2 are used
+    if (dst == 1 && P.mmode != M_APPROX) return;
+    double* const out = dst == 1 ? P.R1 : P.R2;
     // Rows 16 ta .. 16 ta + 15 of R and columns 16 tb .. 16 tb + 15 of Racc
     // through LDS: every load of the block is in flight at once.
     __shared__ double sa[16][LPMAX + 1];
@@ -604,12 +608,85 @@ __global__ __launch_bounds__(256) void k_r2(const Prob* __restrict__ probs,
         s3 += Ra[t + 3] * sb[t + 3][jb];
     }
     for (; t <= b; t++) s0 += Ra[t] * sb[t][jb];
-    P.R2[a * l + b] = (s0 + s1) + (s2 + s3);
+    out[a * l + b] = (s0 + s1) + (s2 + s3);
 }
 
-hipError_t launch_r2(const LaunchGroup& g, int iter, hipStream_t s) {
+hipError_t launch_r2(const LaunchGroup& g, int iter, int dst, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_r2, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff, g.count, iter);
+    hipLaunchKernelGGL(k_r2, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff, g.count, iter,
+                       dst);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (18): D = Q1^T Y1 (Q2^T X)^+ = R1 G^-1 with G = Q2^T X (l x l, full
+// rank for a full-rank sketch).  The QRCP reads M^T, so the kernel solves
+// G^T D^T = R1^T: Gauss-Jordan elimination with partial pivoting (largest
+// |entry| of the column, lowest row on ties) on [G^T | R1^T], one block per
+// problem, the l x 2l work matrix in the problem's Gram partials (L2).  The
+// result D^T goes to Mx.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_dapprox(const Prob* __restrict__ probs,
+                                                  const int32_t* __restrict__ pidx,
+                                                  const int32_t* __restrict__ toff, int cnt) {
+    __shared__ unsigned long long s_key;
+    __shared__ double s_prow[2 * LMAX];
+    int local;
+    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
+    if (P.mmode != M_APPROX) return;
+    const int l = P.l, w2 = 2 * l, tid = threadIdx.x;
+    double* __restrict__ W = P.gpart;  // [l][2l]
+    for (int e = tid; e < l * w2; e += blockDim.x) {
+        const int r = e / w2, c = e - r * w2;
+        W[e] = c < l ? P.G[c * l + r] : P.R1[(c - l) * l + r];  // G^T | R1^T
+    }
+    __syncthreads();
+    for (int j = 0; j < l; j++) {
+        if (tid == 0) s_key = 0ull;
+        __syncthreads();
+        // pivot: largest |W[i][j]| over rows i >= j, lowest row on ties
+        for (int i = j + tid; i < l; i += blockDim.x) {
+            const double v = fabs(W[i * w2 + j]);
+            const unsigned long long key =
+                ((unsigned long long)__double_as_longlong(v) & ~0x3FFull) | (unsigned long long)(1023 - i);
+            atomicMax(&s_key, key);
+        }
+        __syncthreads();
+        const int pr = 1023 - (int)(s_key & 0x3FFull);
+        // swap rows j and pr, scale the pivot row
+        const double piv = W[pr * w2 + j];
+        const double inv = piv != 0.0 ? 1.0 / piv : 0.0;
+        for (int c = tid; c < w2; c += blockDim.x) {
+            const double a = W[pr * w2 + c], b = W[j * w2 + c];
+            const double sa = a * inv;
+            s_prow[c] = sa;
+            W[pr * w2 + c] = b;
+            W[j * w2 + c] = sa;
+        }
+        __syncthreads();
+        // eliminate column j from every other row
+        for (int e = tid; e < l * w2; e += blockDim.x) {
+            const int r = e / w2, c = e - r * w2;
+            if (r == j || c < j) continue;
+            const double f = W[r * w2 + j];
+            if (c == j) continue;
+            W[e] = fma(-f, s_prow[c], W[e]);
+        }
+        __syncthreads();
+        for (int r = tid; r < l; r += blockDim.x)
+            if (r != j) W[r * w2 + j] = 0.0;
+        __syncthreads();
+    }
+    for (int e = tid; e < l * l; e += blockDim.x) {
+        const int r = e / l, c = e - r * l;
+        P.Mx[e] = W[r * w2 + l + c];  // D^T
+    }
+}
+
+hipError_t launch_dapprox(const LaunchGroup& g, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dapprox, dim3(g.blocks), dim3(1024), 0, s, g.probs, g.pidx, g.toff,
+                       g.count);
     return hipGetLastError();
 }
 
@@ -672,7 +749,7 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
     const int rpt = (l + 3) >> 2;       // rows per lane
     const int nb = (rpt + UB - 1) / UB; // batches per lane
     double* __restrict__ W = P.R;
-    const double* __restrict__ R2 = P.R2;
+    const double* __restrict__ R2 = P.msrc;  // M^T: R2 (M = R2^T), or Mx
 
     // W = M = R2^T, and the squared column norms
     if (tid < 2) s_key[tid] = 0ull;
@@ -843,7 +920,7 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
     // archive: column j = raw pivot column of step j (global address space, so
     // that its stores do not hold up the LDS waits)
     gdouble_rw* __restrict__ arc = (gdouble_rw*)P.R;
-    gdouble* __restrict__ R2 = as_global(P.R2);
+    gdouble* __restrict__ R2 = as_global(P.msrc);  // M^T: R2 (M = R2^T), or Mx
 
     // rows past l are zero and stay zero (the pivot column is zero there)
     double col[RR];
@@ -1094,7 +1171,7 @@ __global__ __launch_bounds__(LPC * LPC * RPT) void k_qrcp_rt(const Prob* __restr
     const int tid = threadIdx.x;
     const int c = tid >> LSH, t = tid & (LPC - 1);
     const bool incol = c < l;
-    const double* __restrict__ R2 = P.R2;
+    const double* __restrict__ R2 = P.msrc;  // M^T: R2 (M = R2^T), or Mx
 
     double col[RPT];
 #pragma unroll
@@ -1483,12 +1560,24 @@ __global__ __launch_bounds__(256) void k_report(const Prob* __restrict__ probs,
     }
     t2 = block_sum256(t2, red);
     tk2 = block_sum256(tk2, red);
+    // explicit or eq. (18) compression: ||M - R2^T||_F / ||M||_F (Mx and R2
+    // both hold transposes)
+    double dm = 0.0, mm = 0.0;
+    if (P.mmode != M_R2T)
+        for (int e = threadIdx.x; e < l * l; e += 256) {
+            const double v = P.Mx[e], d = v - P.R2[e];
+            dm += d * d;
+            mm += v * v;
+        }
+    dm = block_sum256(dm, red);
+    mm = block_sum256(mm, red);
     if (threadIdx.x == 0) {
         double na = 0.0;
         for (int b = 0; b < NORM_BLOCKS; b++) na += P.rep[32 + b];
         P.rep[4] = na;
         P.rep[0] = na > 0.0 ? sqrt(fmax(0.0, 1.0 - t2 / na)) : 0.0;
         P.rep[1] = na > 0.0 ? sqrt(fmax(0.0, 1.0 - tk2 / na)) : 0.0;
+        P.rep[5] = mm > 0.0 ? sqrt(dm / mm) : 0.0;
     }
 }
 
@@ -1496,6 +1585,81 @@ hipError_t launch_report(const LaunchGroup& g, int phase, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_report, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff, g.count,
                        phase);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ULV requests run as the URV of A^T: the transposed copy At (n x m, leading
+// dimension P.lda) of the caller's A (m x n, leading dimension P.ulv_lda),
+// 32 x 32 tiles through LDS so that both sides are read and written in
+// contiguous runs; and at the end T = T'^T (lower triangular).  P.m, P.n are
+// the dimensions of A^T.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void transpose_tile(const T* __restrict__ a, int64_t m, int64_t n, int64_t lda,
+                               T* __restrict__ at, int64_t ldt, int64_t tr, int64_t tc) {
+    __shared__ T tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows per pass
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = tr + r, j = tc + tx;
+        if (i < m && j < n) tile[r][tx] = a[i * lda + j];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t j = tc + r, i = tr + tx;  // At[j][i] = A[i][j]
+        if (i < m && j < n) at[j * ldt + i] = tile[tx][r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_transpose_a(const Prob* __restrict__ probs,
+                                                     const int32_t* __restrict__ pidx,
+                                                     const int32_t* __restrict__ toff, int cnt) {
+    int local;
+    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
+    if (!P.ulv) return;
+    const int64_t m = P.n, n = P.m;  // the caller's matrix
+    const int64_t tcs = (n + 31) / 32;
+    const int64_t tr = (int64_t)(local / tcs) * 32, tc = (int64_t)(local % tcs) * 32;
+    switch (P.prec) {
+        case P_F64:
+            transpose_tile<double>(reinterpret_cast<const double*>(P.ulv_src), m, n, P.ulv_lda,
+                                   reinterpret_cast<double*>(const_cast<void*>(P.A)), P.lda, tr, tc);
+            break;
+        case P_F32:
+            transpose_tile<float>(reinterpret_cast<const float*>(P.ulv_src), m, n, P.ulv_lda,
+                                  reinterpret_cast<float*>(const_cast<void*>(P.A)), P.lda, tr, tc);
+            break;
+        default:
+            transpose_tile<uint16_t>(reinterpret_cast<const uint16_t*>(P.ulv_src), m, n, P.ulv_lda,
+                                     reinterpret_cast<uint16_t*>(const_cast<void*>(P.A)), P.lda, tr,
+                                     tc);
+            break;
+    }
+}
+
+hipError_t launch_transpose_a(const LaunchGroup& g, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_transpose_a, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff,
+                       g.count);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_ulv_t(const Prob* __restrict__ probs,
+                                               const int32_t* __restrict__ pidx,
+                                               const int32_t* __restrict__ toff, int cnt) {
+    int local;
+    const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
+    if (!P.ulv) return;
+    const int l = P.l;
+    const int e = local * 256 + threadIdx.x;
+    if (e >= l * l) return;
+    const int a = e / l, b = e - (e / l) * l;
+    P.Tout[e] = P.T[b * l + a];
+}
+
+hipError_t launch_ulv_t(const LaunchGroup& g, hipStream_t s) {
+    if (g.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ulv_t, dim3(g.blocks), dim3(256), 0, s, g.probs, g.pidx, g.toff, g.count);
     return hipGetLastError();
 }
 

@@ -31,13 +31,19 @@ hipError_t launch_omega(const LaunchGroup& g, hipStream_t s);          // blocks
 hipError_t launch_make_op(const LaunchGroup& g, int side, hipStream_t s);  // blocks: ceil(lp*ld/256)
 hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s);  // ceil(rows*lp/4/256)
 // Gram partial sums of a row-major rows x l FP64 matrix picked by `src`.
-enum GramSrc : int32_t { GSRC_Y = 0, GSRC_QA = 1, GSRC_U = 2, GSRC_V = 3 };
+enum GramSrc : int32_t { GSRC_Y = 0, GSRC_QA = 1, GSRC_U = 2, GSRC_V = 3,
+                         GSRC_XM = 4,   // Q1^T (A Q2): every tile (compression of eq. (14))
+                         GSRC_XA = 5 }; // Q2^T X: every tile (eq. (18))
 constexpr int GRAM_THREADS = 256;
 // One upper 16 x 16 tile of the l x l Gram matrix per block (four waves
 // split the chunk's rows); a launch covers (row chunks) x (upper tiles) blocks.
 hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStream_t s);
 hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int iter,
                               hipStream_t s);
+// Cross products of GSRC_XM (into Mx, transposed) or GSRC_XA (into G); blocks ceil(l*l/64).
+hipError_t launch_xreduce(const LaunchGroup& g, int src, hipStream_t s);
+// Xk = Q2 at the last power step (eq. (18) problems); blocks ceil(n*l/256).
+hipError_t launch_keep_x(const LaunchGroup& g, int iter, hipStream_t s);
 // Operand copies: tiles of MO_ROWS rows x MO_COLS columns per block, blocks
 // per problem ceil(ld / MO_ROWS) * (lp / MO_COLS).
 constexpr int MO_ROWS = 64;
@@ -59,7 +65,15 @@ hipError_t launch_op_scales(const LaunchGroup& chunks, const LaunchGroup& one, i
 enum CholMode : int32_t { CHOL_FIRST = 0, CHOL_SECOND = 1 };
 hipError_t launch_chol(const LaunchGroup& g, int mode, int lmax, int iter, hipStream_t s);
 hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s);
-hipError_t launch_r2(const LaunchGroup& g, int iter, hipStream_t s);  // blocks: nt*nt
+// R2 = R' R of the last Y2 (dst 0) or R1 of the last Y1 (dst 1, eq. (18)); blocks: nt*nt
+hipError_t launch_r2(const LaunchGroup& g, int iter, int dst, hipStream_t s);
+// Eq. (18): Mx = (R1 G^-1)^T with G = Q2^T X; one block per problem.
+hipError_t launch_dapprox(const LaunchGroup& g, hipStream_t s);
+// ULV requests: the transposed copy of A (tiles of 32 x 32; blocks
+// ceil(m/32) * ceil(n/32) of the caller's matrix) and T = T'^T at the end
+// (blocks ceil(l*l/256)).
+hipError_t launch_transpose_a(const LaunchGroup& g, hipStream_t s);
+hipError_t launch_ulv_t(const LaunchGroup& g, hipStream_t s);
 // Reflectors applied to rows of the identity (u_via_qs: Qs into G, blocks
 // ceil(l/32)) or of Q1 (U, blocks ceil(m/32)).
 hipError_t launch_form_qs(const LaunchGroup& g, int l, hipStream_t s);

@@ -29,6 +29,7 @@ size_t plan_bytes(const Plan* P);
 const Prob& plan_desc(const Plan* P, int i);
 int plan_count(const Plan* P);
 int plan_report(const Plan* P);
-size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec);
+// Device workspace of one decomposition with the given options (NULL: defaults).
+size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec, const cor_opts* opts = nullptr);
 
 }  // namespace cor

@@ -88,6 +88,12 @@ static int64_t roundup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static int prec_size(int p) { return p == P_F64 ? 8 : p == P_F32 ? 4 : p == P_BF16 ? 2 : 1; }
 
+enum {
+    O_XOP, O_QOP, O_XSC, O_QSC, O_YPART, O_Y, O_QA, O_Q1, O_Q2, O_GPART, O_G, O_R, O_RINV,
+    O_RACC, O_R2, O_QT, O_TAU, O_REP, O_FLAGS, O_PERM, O_SCPART, O_MX, O_R1, O_XK, O_AT, O_TT,
+    O_COUNT
+};
+
 struct Layout {
     // per-problem sizes
     int32_t l, lp, nt;
@@ -95,14 +101,10 @@ struct Layout {
     int32_t s_ax, s_atx;
     int64_t kc_ax, kc_atx;
     int32_t rb_m, rb_n, gb_m, gb_n;
-    size_t off[24];
+    size_t off[O_COUNT];
     size_t total;
 };
 
-enum {
-    O_XOP, O_QOP, O_XSC, O_QSC, O_YPART, O_Y, O_QA, O_Q1, O_Q2, O_GPART, O_G, O_R, O_RINV,
-    O_RACC, O_R2, O_QT, O_TAU, O_REP, O_FLAGS, O_PERM, O_SCPART, O_COUNT
-};
 
 // K splits of a pass: about `target` blocks in all (row blocks x splits, never
 // more), at most 8 splits, each split at least 16 K tiles long in BF16 and FP8
@@ -162,8 +164,13 @@ static int sketch_block_target() {
     return t;
 }
 
+// Leading dimension (elements) of the transposed copy of A behind a ULV
+// request: rows of 16-byte multiples.
+static int64_t at_ld(int64_t n, int prec) { return roundup(n, 16); }
+
+// m, n are the dimensions of the matrix the passes read (A^T for ULV).
 static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_target,
-                          int gram_target) {
+                          int gram_target, int mmode = M_R2T, int ulv = 0) {
     Layout L;
     L.l = l;
     L.lp = (int32_t)roundup(l, 16);
@@ -193,7 +200,8 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
     sizes[O_QA] = (size_t)mx * l * 8;
     sizes[O_Q1] = (size_t)m * l * 8;
     sizes[O_Q2] = (size_t)n * l * 8;
-    sizes[O_GPART] = (size_t)std::max(L.gb_m, L.gb_n) * l * l * 8;
+    // Gram partials; eq. (18) also solves in them (an l x 2l work matrix)
+    sizes[O_GPART] = (size_t)std::max(std::max(L.gb_m, L.gb_n), mmode == M_APPROX ? 2 : 1) * l * l * 8;
     sizes[O_G] = sizes[O_R] = sizes[O_RINV] = sizes[O_RACC] = sizes[O_R2] = sizes[O_QT] =
         (size_t)l * l * 8;
     sizes[O_TAU] = 2 * LMAX * 8;
@@ -201,6 +209,11 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
     sizes[O_FLAGS] = 64;
     sizes[O_PERM] = (size_t)l * 4;
     sizes[O_SCPART] = prec == P_FP8 ? (size_t)SCALE_CHUNKS * L.lp * 4 : 0;
+    sizes[O_MX] = mmode != M_R2T ? (size_t)l * l * 8 : 0;
+    sizes[O_R1] = mmode == M_APPROX ? (size_t)l * l * 8 : 0;
+    sizes[O_XK] = mmode == M_APPROX ? (size_t)n * l * 8 : 0;
+    sizes[O_AT] = ulv ? (size_t)m * at_ld(n, prec) * sz : 0;
+    sizes[O_TT] = ulv ? (size_t)l * l * 8 : 0;
     size_t off = 0;
     for (int i = 0; i < O_COUNT; i++) {
         L.off[i] = off;
@@ -211,6 +224,16 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
 }
 
 static bool valid_prec(int p) { return p >= COR_F64 && p <= COR_FP8; }
+
+static cor_status validate_opts(const cor_opts* o, const cor_problem& p) {
+    if (!o) return COR_OK;
+    if (o->compress < COR_M_R2T || o->compress > COR_M_APPROX)
+        return fail(COR_E_INVAL, "unknown compression mode");
+    if (o->orient != COR_URV && o->orient != COR_ULV) return fail(COR_E_INVAL, "unknown orientation");
+    if (o->orient == COR_ULV && p.prec == COR_FP8)
+        return fail(COR_E_INVAL, "ULV needs A^T in the storage format: not available for COR_FP8");
+    return COR_OK;
+}
 
 static cor_status validate(const cor_problem& p) {
     const int64_t l = (int64_t)p.k + p.p;
@@ -234,6 +257,7 @@ struct Plan {
     int max_q = 0;
     int report = 0;
     int prec_mix = 0;  // bitmask of precisions present
+    bool has_explicit = false, has_approx = false, has_ulv = false;
     int nj = 1;        // ceil(max l / 64): column tiles of the row-block products
     int lmax = 0;      // largest l of the plan
     std::vector<cor_problem> reqs;
@@ -251,6 +275,7 @@ struct Plan {
     };
     Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, applyM, applyN, vg, r2, norm;
     Grp scM, scN;  // FP8 operand scales: row chunks of the column maxima
+    Grp xgM, xgN, xred, keepx, tra, ulvt;  // compression modes and ULV
     std::vector<Grp> skAX, skATX;  // per (precision, column tiles)
     std::vector<Grp> formU;        // per register-tile class of l (nt holds l)
     Grp applyU;                    // U = Q1 Qs for the problems with u_via_qs
@@ -292,20 +317,34 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     if (!probs || count < 1 || !out) return fail(COR_E_INVAL, "no problems");
     for (int i = 0; i < count; i++) {
         cor_status st = validate(probs[i]);
+        if (st == COR_OK) st = validate_opts(opts, probs[i]);
         if (st != COR_OK) return st;
     }
+    const int mmode = opts ? opts->compress : M_R2T;
+    const int ulv = (opts && opts->orient == COR_ULV) ? 1 : 0;
+    // A ULV request is run as the URV of A^T (an n x m matrix in the
+    // workspace): the problem the stages see has m and n, U and V swapped.
+    const cor_problem* const caller = probs;
+    std::vector<cor_problem> iprobs(probs, probs + count);
+    if (ulv)
+        for (auto& q : iprobs) {
+            std::swap(q.m, q.n);
+            std::swap(q.U, q.V);
+            q.lda = at_ld(q.n, q.prec);
+        }
+    probs = iprobs.data();
     Plan* P = new Plan();
     HIPCHK(hipGetDevice(&P->device));
     P->count = count;
     P->report = opts ? opts->report : 0;
-    P->reqs.assign(probs, probs + count);
+    P->reqs.assign(caller, caller + count);  // the caller's requests (before the ULV swap)
     const int sk_target = sketch_block_target();
     const int gr_target = 1024;
     size_t ws = 0;
     std::vector<size_t> base(count);
     for (int i = 0; i < count; i++) {
         const cor_problem& q = probs[i];
-        P->lay.push_back(make_layout(q.m, q.n, q.k + q.p, q.prec, sk_target, gr_target));
+        P->lay.push_back(make_layout(q.m, q.n, q.k + q.p, q.prec, sk_target, gr_target, mmode, ulv));
         base[i] = ws;
         ws += P->lay.back().total;
         P->max_q = std::max(P->max_q, (int)q.q);
@@ -313,6 +352,9 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         P->nj = std::max(P->nj, (int)((q.k + q.p + 63) / 64));
         P->lmax = std::max(P->lmax, (int)(q.k + q.p));
     }
+    P->has_explicit = mmode == M_EXPLICIT;
+    P->has_approx = mmode == M_APPROX;
+    P->has_ulv = ulv != 0;
     P->second.assign(P->max_q + 1, 0);
     P->last.assign(P->max_q + 1, 0);
     for (int i = 0; i < count; i++)
@@ -344,6 +386,17 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     auto R_vg = per([&](int i) { return cdiv(probs[i].n * P->lay[i].l, 256); });
     auto R_r2 = per([&](int i) { return (int64_t)P->lay[i].nt * P->lay[i].nt; });
     auto R_norm = per([&](int) { return (int64_t)64; });
+    auto R_xgM = per([&](int i) {
+        return mmode == M_EXPLICIT ? (int64_t)P->lay[i].gb_m * P->lay[i].nt * P->lay[i].nt : 0; });
+    auto R_xgN = per([&](int i) {
+        return mmode == M_APPROX ? (int64_t)P->lay[i].gb_n * P->lay[i].nt * P->lay[i].nt : 0; });
+    auto R_xred = per([&](int i) {
+        return mmode != M_R2T ? cdiv((int64_t)P->lay[i].l * P->lay[i].l, 64) : 0; });
+    auto R_keepx = per([&](int i) {
+        return mmode == M_APPROX ? cdiv(probs[i].n * P->lay[i].l, 256) : 0; });
+    auto R_tra = per([&](int i) { return ulv ? cdiv(probs[i].n, 32) * cdiv(probs[i].m, 32) : 0; });
+    auto R_ulvt = per([&](int i) {
+        return ulv ? cdiv((int64_t)P->lay[i].l * P->lay[i].l, 256) : 0; });
     auto R_scM = per([&](int i) { return probs[i].prec == COR_FP8 ? (int64_t)scale_chunks(probs[i].m) : 0; });
     auto R_scN = per([&](int i) { return probs[i].prec == COR_FP8 ? (int64_t)scale_chunks(probs[i].n) : 0; });
     // Sketch tables: one per (precision, column-tile count) class.
@@ -433,7 +486,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         char* w = d_ws + base[i];
         Prob& d = P->hp[i];
         memset(&d, 0, sizeof(Prob));
-        d.A = q.A;
+        d.A = ulv ? (const void*)(w + L.off[O_AT]) : q.A;
         d.colscale = q.colscale;
         d.m = q.m; d.n = q.n; d.lda = q.lda;
         d.k = q.k; d.l = L.l; d.lp = L.lp; d.q = q.q;
@@ -467,7 +520,16 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         d.scpart = (float*)(w + L.off[O_SCPART]);
         d.sch_m = scale_chunks(q.m);
         d.sch_n = scale_chunks(q.n);
-        d.U = q.U; d.T = q.T; d.V = q.V;
+        d.U = q.U; d.T = ulv ? (double*)(w + L.off[O_TT]) : q.T; d.V = q.V;
+        d.mmode = mmode;
+        d.ulv = ulv;
+        d.Mx = (double*)(w + L.off[O_MX]);
+        d.R1 = (double*)(w + L.off[O_R1]);
+        d.Xk = (double*)(w + L.off[O_XK]);
+        d.msrc = mmode == M_R2T ? d.R2 : d.Mx;
+        d.Tout = caller[i].T;
+        d.ulv_src = caller[i].A;
+        d.ulv_lda = caller[i].lda;
         d.perm = q.perm ? q.perm : (int32_t*)(w + L.off[O_PERM]);
         d.omega = q.omega;
         d.seed = q.seed;
@@ -522,6 +584,8 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     P->applyM = mk(R_applyM); P->applyN = mk(R_applyN); P->applyU = mk(R_applyU);
     P->vg = mk(R_vg); P->r2 = mk(R_r2); P->norm = mk(R_norm);
     P->scM = mk(R_scM); P->scN = mk(R_scN);
+    P->xgM = mk(R_xgM); P->xgN = mk(R_xgN); P->xred = mk(R_xred); P->keepx = mk(R_keepx);
+    P->tra = mk(R_tra); P->ulvt = mk(R_ulvt);
     for (auto& u : urefs) {
         Plan::Grp g = mk(u.r);
         g.nt = u.lmax;
@@ -560,6 +624,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         if (e_ != hipSuccess) return e_;       \
     } while (0)
     const bool fp8 = (P->prec_mix >> P_FP8) & 1;
+    if (P->has_ulv) E(launch_transpose_a(P->tra.g, s));  // A^T for the ULV requests
     if (P->report) E(launch_normA(P->norm.g, s));
     E(launch_omega(P->omega.g, s));  // Q2 <- Omega (FP64)
     if (fp8) E(launch_op_scales(P->scN.g, P->small.g, SIDE_N, 0, s));
@@ -576,12 +641,16 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
             E(launch_gram(P->gramM.g, SIDE_M, GSRC_QA, it, s));
             E(launch_gram_reduce(P->redM.g, SIDE_M, 1, it, s));
             E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
+            // eq. (18): R1 = R' R of the last Y1
+            if (P->has_approx && P->last[it]) E(launch_r2(P->r2.g, it, 1, s));
             E(launch_apply(P->applyM.g, SIDE_M, AP_QA_RINV_Q, P->lmax, it, s));
         }
         if (fp8) {
             E(launch_op_scales(P->scM.g, P->small.g, SIDE_M, it, s));
             E(launch_make_op(P->opM.g, SIDE_M, s));
         }
+        // eq. (18) keeps the last step's input X before Q2 is overwritten
+        if (P->has_approx && P->last[it]) E(launch_keep_x(P->keepx.g, it, s));
         // Y2 = A^T Q1, Q2 R2 = Y2 (CholeskyQR2); X <- Q2
         E(run_sketch(P->skATX, true, it, s));
         E(launch_sum(P->sumN.g, SIDE_N, it, s));
@@ -594,14 +663,31 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
             E(launch_gram_reduce(P->redN.g, SIDE_N, 1, it, s));
             E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
         }
-        if (P->last[it]) E(launch_r2(P->r2.g, it, s));
+        if (P->last[it]) E(launch_r2(P->r2.g, it, 0, s));
         if (P->second[it]) E(launch_apply(P->applyN.g, SIDE_N, AP_QA_RINV_Q, P->lmax, it, s));
         if (fp8 && it < P->max_q) {
             E(launch_op_scales(P->scN.g, P->small.g, SIDE_N, it, s));
             E(launch_make_op(P->opN.g, SIDE_N, s));
         }
     }
-    // M = Q1^T A Q2 = R2^T; M P = Qt T; U = Q1 Qs (Qs = Qt diag(sign)), V = Q2 P.
+    // M = Q1^T A Q2 = R2^T (default); or explicitly, one more pass over A
+    // (eq. (14) as printed); or eq. (18) from R1 and Q2^T X.
+    if (P->has_explicit) {
+        if (fp8) {  // the FP8 operand copy of the final Q2
+            E(launch_op_scales(P->scN.g, P->small.g, SIDE_N, P->max_q, s));
+            E(launch_make_op(P->opN.g, SIDE_N, s));
+        }
+        E(run_sketch(P->skAX, false, -1, s));  // Y = A Q2
+        E(launch_sum(P->sumM.g, SIDE_M, -1, s));
+        E(launch_gram(P->xgM.g, SIDE_M, GSRC_XM, -1, s));  // Q1^T Y
+        E(launch_xreduce(P->xred.g, GSRC_XM, s));
+    }
+    if (P->has_approx) {
+        E(launch_gram(P->xgN.g, SIDE_N, GSRC_XA, -1, s));  // G = Q2^T X
+        E(launch_xreduce(P->xred.g, GSRC_XA, s));
+        E(launch_dapprox(P->small.g, s));  // M = R1 G^-1
+    }
+    // M P = Qt T; U = Q1 Qs (Qs = Qt diag(sign)), V = Q2 P.
     E(launch_qrcp(P->small.g, P->lmax, s));
     for (const auto& ug : P->formU) E(launch_form_qs(ug.g, ug.nt, s));
     E(launch_apply(P->applyU.g, SIDE_M, AP_Q1_QS_U, P->lmax, -1, s));
@@ -615,6 +701,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         E(launch_report(P->small.g, 2, s));
         E(launch_report(P->small.g, 3, s));
     }
+    if (P->has_ulv) E(launch_ulv_t(P->ulvt.g, s));  // T = T'^T (lower triangular)
     return hipSuccess;
 #undef E
 }
@@ -656,15 +743,16 @@ cor_status plan_info(Plan* P, cor_info* infos, hipStream_t s) {
     for (int i = 0; i < P->count; i++) {
         const Prob& d = P->hp[i];
         int32_t flags = 0;
-        double rep[5] = {0, 0, 0, 0, 0};
+        double rep[6] = {0, 0, 0, 0, 0, 0};
         HIPCHK(hipMemcpy(&flags, d.flags, sizeof(int32_t), hipMemcpyDeviceToHost));
         if (P->report) HIPCHK(hipMemcpy(rep, d.rep, sizeof(rep), hipMemcpyDeviceToHost));
         if (infos) {
             cor_info& f = infos[i];
             f.err_l = rep[0];
             f.err_k = rep[1];
-            f.orth_u = rep[2];
-            f.orth_v = rep[3];
+            f.orth_u = d.ulv ? rep[3] : rep[2];  // a ULV request's U is the V of A^T
+            f.orth_v = d.ulv ? rep[2] : rep[3];
+            f.m_check = rep[5];
             f.flags = flags;
             f.l = d.l;
         }
@@ -692,8 +780,11 @@ int plan_report(const Plan* P) { return P->report; }
 
 size_t plan_bytes(const Plan* P) { return P->mem_bytes; }
 
-size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec) {
-    Layout L = make_layout(m, n, l, prec, sketch_block_target(), 1024);
+size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec, const cor_opts* opts) {
+    const int mmode = opts ? opts->compress : M_R2T;
+    const int ulv = (opts && opts->orient == COR_ULV) ? 1 : 0;
+    Layout L = ulv ? make_layout(n, m, l, prec, sketch_block_target(), 1024, mmode, 1)
+                   : make_layout(m, n, l, prec, sketch_block_target(), 1024, mmode, 0);
     return L.total + 256 + 1024;
 }
 

@@ -86,9 +86,9 @@ struct Server {
     int64_t completed = 0, rejected = 0;
 };
 
-static size_t request_footprint(const cor_problem& p, bool convert) {
+static size_t request_footprint(const cor_problem& p, const cor_opts& o, bool convert) {
     const int prec = convert ? COR_BF16 : p.prec;
-    size_t b = workspace_bytes(p.m, p.n, p.k + p.p, prec);
+    size_t b = workspace_bytes(p.m, p.n, p.k + p.p, prec, &o);
     if (convert) b += (size_t)p.m * p.n * 2 + 256;
     return b;
 }
@@ -135,7 +135,11 @@ static void launch_round(Server* S, std::vector<Request*>& adm) {
     }
     cor_opts o{};
     for (Request* r : ok) o.report = std::max(o.report, r->opts.report);
-    o.cholqr2_all = ok.empty() ? 0 : ok[0]->opts.cholqr2_all;  // uniform within a round
+    if (!ok.empty()) {  // uniform within a round
+        o.cholqr2_all = ok[0]->opts.cholqr2_all;
+        o.compress = ok[0]->opts.compress;
+        o.orient = ok[0]->opts.orient;
+    }
     cor_status st = COR_OK;
     if (!ok.empty()) st = plan_create(probs.data(), (int32_t)probs.size(), &o, &R->plan, s, true);
     if (st == COR_OK && R->plan) st = plan_run(R->plan, s);
@@ -212,12 +216,14 @@ static void server_loop(Server* S) {
             S->high_water = std::max(S->high_water, S->in_use);
         }
         if (!adm.empty()) {
-            // one round per orthonormalisation option (the other options do
-            // not change the results)
-            std::vector<Request*> part[2];
-            for (Request* r : adm) part[r->opts.cholqr2_all ? 1 : 0].push_back(r);
-            for (auto& v : part)
-                if (!v.empty()) launch_round(S, v);
+            // one round per combination of the options that change the
+            // stage sequence (orthonormalisation, compression, orientation);
+            // the report option does not change the results
+            std::map<int, std::vector<Request*>> part;
+            for (Request* r : adm)
+                part[(r->opts.cholqr2_all ? 1 : 0) + 2 * r->opts.compress + 8 * r->opts.orient]
+                    .push_back(r);
+            for (auto& kv : part) launch_round(S, kv.second);
         }
         bool progressed = !adm.empty();
         for (size_t i = 0; i < S->active.size();) {
@@ -275,7 +281,10 @@ cor_status cor_server_submit(cor_server* server, const cor_problem* prob, const 
     const int64_t l = (int64_t)p.k + p.p;
     if (!p.A || !p.U || !p.T || !p.V || p.k < 1 || p.p < 0 || p.q < 0 || p.q > 16 || l < 2 ||
         l >= std::min(p.m, p.n) || l > LMAX || p.lda < p.n || p.prec < COR_F64 ||
-        p.prec > COR_FP8 || (p.prec == COR_FP8 && !p.colscale)) {
+        p.prec > COR_FP8 || (p.prec == COR_FP8 && !p.colscale) ||
+        (opts && (opts->compress < COR_M_R2T || opts->compress > COR_M_APPROX ||
+                  (opts->orient != COR_URV && opts->orient != COR_ULV) ||
+                  (opts->orient == COR_ULV && p.prec == COR_FP8)))) {
         std::lock_guard<std::mutex> lk(S->mu);
         S->rejected++;
         return fail(COR_E_INVAL, "malformed request");
@@ -284,7 +293,7 @@ cor_status cor_server_submit(cor_server* server, const cor_problem* prob, const 
     r->prob = p;
     if (opts) r->opts = *opts;
     r->convert = (S->cfg.convert_f32_to == COR_BF16 && p.prec == COR_F32);
-    r->footprint = request_footprint(p, r->convert);
+    r->footprint = request_footprint(p, r->opts, r->convert);
     if (r->footprint > S->cfg.hbm_budget) {
         delete r;
         std::lock_guard<std::mutex> lk(S->mu);
