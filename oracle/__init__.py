@@ -244,3 +244,68 @@ def bf16_to_f64(h) -> np.ndarray:
 def dequantize_fp8(codes, colscale) -> np.ndarray:
     table = fp8_to_f64(np.arange(256))
     return table[np.asarray(codes, dtype=np.uint8)] * np.asarray(colscale, dtype=np.float64)[None, :]
+
+
+def rpca_alm(M, k: int, p: int, q: int, omega_seed: int, lam=None, rho: float = 1.5,
+             mubar_ratio: float = 1e7, tol: float = 1e-5, max_iter: int = 100):
+    """Robust PCA by ALM with CoR-UTV as the low-rank step (Sec. V, the
+    ALM-CoRUTV algorithm; termination and tests of Sec. VI-D), in plain FP64
+    numpy around the oracle's CoR-UTV.
+
+    Iteration j (mu_j the penalty):
+      B      = M - S_j + Y_j / mu_j
+      U T V  = CoR-UTV(B)  (k, l = k + p, q; the same Gaussian test matrix
+               every iteration, from the documented stream at omega_seed)
+      r      = number of diagonal entries of T greater than delta = 1 / mu_j
+      L_j+1  = U[:, :r] (T[:r, :] - delta [I_r 0]) V^T  (the operator C_delta)
+      S_j+1  = shrink(M - L_j+1 + Y_j / mu_j, lam / mu_j),
+               shrink(x, d) = sgn(x) max(|x| - d, 0)
+      Y_j+1  = Y_j + mu_j (M - L_j+1 - S_j+1)
+      mu_j+1 = min(rho mu_j, mu_bar)
+    until zeta = ||M - L - S||_F / ||M||_F < tol.  Readings (the paper leaves
+    them to a cited reference or prints them garbled): C_delta shrinks the r
+    kept diagonal entries of T by delta, as the singular value thresholding
+    it stands in for shrinks the singular values (the printed form keeps
+    U[:, :r] T[:r, :] V^T unshrunk, which on the synthetic L + S matrices
+    stalls at a wrong rank); lam = 1/sqrt(max(m, n));
+    mu_0 = 1.25 / ||M||_2 with ||M||_2 taken as T_11 of the first
+    decomposition (whose input is M itself, S_0 = Y_0 = 0); mu_bar = 1e7 mu_0;
+    rho = 1.5; the penalty grows to its cap (the printed max(rho mu_j, mu_bar)
+    would jump to the cap at once); the S step uses Y_j.
+    Returns dict(L, S, iters, rank, zeta, ranks)."""
+    M = _f64(M)
+    m, n = M.shape
+    l = k + p
+    lam = 1.0 / np.sqrt(max(m, n)) if lam is None else lam
+    om = omega(omega_seed, n, l)
+    nM = np.linalg.norm(M)
+    S = np.zeros_like(M)
+    Y = np.zeros_like(M)
+    mu = None
+    mubar = None
+    ranks = []
+    it = 0
+    while True:
+        B = M if mu is None else M - S + Y / mu
+        out = cor_utv(B, k, p, q, om)
+        T = out["T"]
+        if mu is None:
+            mu = 1.25 / T[0, 0]
+            mubar = mu * mubar_ratio
+        delta = 1.0 / mu
+        r = int(np.sum(np.diag(T) > delta))
+        Tr = T[:r, :].copy()
+        Tr[np.arange(r), np.arange(r)] -= delta
+        L = out["U"][:, :r] @ (Tr @ out["V"].T)
+        Z = M - L + Y / mu
+        d = lam / mu
+        S = np.sign(Z) * np.maximum(np.abs(Z) - d, 0.0)
+        R = M - L - S
+        Y = Y + mu * R
+        zeta = np.linalg.norm(R) / nM
+        ranks.append(r)
+        it += 1
+        mu = min(rho * mu, mubar)
+        if zeta < tol or it >= max_iter:
+            break
+    return dict(L=L, S=S, iters=it, rank=r, zeta=zeta, ranks=ranks)
