@@ -178,6 +178,48 @@ cor_status cor_utv_ex_noalloc(const cor_problem* prob, const cor_opts* opts, cor
                               void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Robust PCA, M = L + S with L of low rank and S sparse, by the augmented
+ * Lagrange multiplier method with CoR-UTV as its low-rank step (Sec. V,
+ * ALM-CoRUTV).  Iteration j, penalty mu_j, delta = 1 / mu_j:
+ *   B = M - S_j + Y_j / mu_j (B_0 = M);  U T V = CoR-UTV(B) with k, p, q, the
+ *   same Gaussian test matrix (seed) every iteration;  r = #{i : T_ii > delta};
+ *   L_j+1 = U[:, :r] (T[:r, :] - delta [I_r 0]) V^T;
+ *   S_j+1 = shrink(M - L_j+1 + Y_j / mu_j, lambda / mu_j) with
+ *   shrink(x, d) = sgn(x) max(|x| - d, 0);  Y_j+1 = Y_j + mu_j (M - L_j+1 - S_j+1);
+ *   mu_j+1 = min(rho mu_j, mu_bar),
+ * until zeta = ||M - L - S||_F / ||M||_F < tol or max_iter iterations.
+ * mu_0 = 1.25 / T_11 of the first decomposition (an estimate of ||M||_2),
+ * mu_bar = mu_bar_ratio mu_0.  Fields <= 0 take the defaults named below.
+ * M: device, m x n FP64 row-major, leading dimension ldm >= n (read only).
+ * L, S: device out, m x n FP64 with leading dimension n (the last iterate).
+ * The library allocates its workspace (Y, B in `prec`, the factors; about
+ * (16 + 8 or 4) m n bytes) for the call and frees it before returning.
+ * Returns after the work on `stream` has completed (the host reads zeta and
+ * r back after every iteration).  COR_E_INVAL for bad shapes or rank
+ * parameters (as cor_utv), COR_E_NUMERIC if M is zero or not finite.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t k, p, q;      /* rank parameters of the CoR-UTV step (as cor_problem)              */
+    int32_t prec;         /* COR_F64 or COR_F32: format of B and of the passes over it           */
+    uint64_t seed;        /* Gaussian test matrix (cor_omega's stream)                           */
+    double lambda;        /* sparsity weight (<= 0: 1 / sqrt(max(m, n)))                          */
+    double rho;           /* penalty growth (<= 0: 1.5)                                           */
+    double mu_bar_ratio;  /* penalty cap over mu_0 (<= 0: 1e7)                                    */
+    double tol;           /* stop when zeta < tol (<= 0: 1e-5)                                    */
+    int32_t max_iter;     /* iteration cap (<= 0: 100)                                            */
+} cor_rpca_opts;
+typedef struct {
+    int32_t iters;        /* iterations run                                                       */
+    int32_t rank;         /* r of the last iteration (the rank of L)                              */
+    double zeta;          /* ||M - L - S||_F / ||M||_F after the last iteration                   */
+    double mu;            /* penalty of the last iteration                                        */
+    double ms;            /* host wall time of the call                                           */
+} cor_rpca_info;
+cor_status cor_rpca_alm(const double* M, int64_t m, int64_t n, int64_t ldm,
+                        const cor_rpca_opts* opts, double* L, double* S, cor_rpca_info* info,
+                        void* stream);
+
+/* ---------------------------------------------------------------------------
  * Plans: the executor behind the calls above, exposed for callers that replay
  * the same decomposition(s) many times.  A plan owns its workspace and
  * device-side descriptors; cor_plan_run() only enqueues kernels on `stream`

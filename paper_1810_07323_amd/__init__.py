@@ -45,6 +45,20 @@ class cor_opts(C.Structure):
                 ("orient", C.c_int32)]
 
 
+class cor_rpca_opts(C.Structure):
+    _fields_ = [("k", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("prec", C.c_int32),
+                ("seed", C.c_uint64), ("lam", C.c_double), ("rho", C.c_double),
+                ("mu_bar_ratio", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32)]
+
+
+class cor_rpca_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("rank", C.c_int32), ("zeta", C.c_double),
+                ("mu", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class cor_server_cfg(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int32),
                 ("convert_f32_to", C.c_int32)]
@@ -70,6 +84,8 @@ _SIGS = {
                                      C.POINTER(cor_info), _P]),
     "cor_utv_batched": (C.c_int, [C.POINTER(cor_problem), C.c_int32, C.POINTER(cor_opts),
                                   C.POINTER(cor_info), _P]),
+    "cor_rpca_alm": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, C.POINTER(cor_rpca_opts),
+                               _P, _P, C.POINTER(cor_rpca_info), _P]),
     "cor_plan_create": (C.c_int, [C.POINTER(cor_problem), C.c_int32, C.POINTER(cor_opts),
                                   C.POINTER(_P)]),
     "cor_plan_run": (C.c_int, [_P, _P]),
@@ -199,6 +215,29 @@ def cor_utv_batched(problems, opts=None, stream=None):
     st = lib().cor_utv_batched(arr, len(problems), C.byref(opts) if opts is not None else None,
                                infos, stream_handle(stream))
     return st, list(infos)
+
+
+def cor_rpca_alm(M, m, n, ldm, opts, L, S, stream=None):
+    """M, L, S: device FP64 tensors or addresses; returns (status, cor_rpca_info)."""
+    info = cor_rpca_info()
+    st = lib().cor_rpca_alm(ptr(M), m, n, ldm, C.byref(opts), ptr(L), ptr(S), C.byref(info),
+                            stream_handle(stream))
+    return st, info
+
+
+def rpca(M, k, p, q, seed=0, prec=COR_F64, lam=0.0, rho=0.0, mu_bar_ratio=0.0, tol=0.0,
+         max_iter=0, stream=None):
+    """Robust PCA of device FP64 matrix M (torch tensor): returns (L, S, info)."""
+    import torch
+
+    m, n = M.shape
+    assert M.dtype == torch.float64 and M.stride(1) == 1
+    L = torch.empty((m, n), dtype=torch.float64, device=M.device)
+    S = torch.empty((m, n), dtype=torch.float64, device=M.device)
+    o = cor_rpca_opts(k, p, q, prec, seed, lam, rho, mu_bar_ratio, tol, max_iter)
+    st, info = cor_rpca_alm(M, m, n, M.stride(0), o, L, S, stream)
+    check(st, "cor_rpca_alm")
+    return L, S, info
 
 
 def cor_plan_create(problems, opts=None):
