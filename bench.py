@@ -43,6 +43,11 @@ WORKLOADS = {
                    seed=303, desc="20000x10000 BF16, sigma_i=i^-1.5; k=200, l=220, q=2"),
     "c1": dict(m=1000, n=1000, rank=1000, spectrum="c1", k=10, p=5, q=1, prec="f64", seed=101,
                noise=1e-6, desc="1000x1000 FP64, sigma 1 (i<=10) then 1e-3*0.9^(i-10); k=10, l=15, q=1"),
+    # robust PCA by ALM-CoRUTV on the synthetic L + S matrix of the recovery
+    # experiment (Table I's largest shape; l = k + 64, the largest l supported)
+    "rpca": dict(n=4000, rank=200, frac=0.05, k=200, p=64, q=1, seed=606, cpu_iters=1,
+                 desc="robust PCA, M = L + S 4000x4000, rank(L)=200, 5% +-80 outliers; "
+                      "ALM-CoRUTV k=200, l=264, q=1, FP64"),
     # many independent problems in one batched plan (BF16 passes)
     "c4batched": dict(count=512, seed=404, prec="bf16",
                       desc="512 problems, m,n ~ U{256..4096}, k ~ U{8..64}, l=k+8, q=1, "
@@ -385,6 +390,25 @@ def traffic_of(name):
     return None
 
 
+def cpu_threads():
+    """BLAS threads for the numpy steps of the oracle's robust PCA (its
+    CoR-UTV is single-threaded C): the host's cores this process may use, at
+    most 16 (the host share of one GPU)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def blas_limit(nthreads):
+    """Context that pins numpy's BLAS pool to nthreads (the oracle's only
+    multithreaded part)."""
+    from threadpoolctl import threadpool_limits
+
+    return threadpool_limits(limits=nthreads, user_api="blas")
+
+
 def cpu_baseline_oracle(a64, k, p, q, seed, budget_rows=(300, 600)):
     """The FP64 oracle itself, end to end (Omega, 2q+2 products and QRs, the
     explicit compression pass, QRCP, U, V), on two leading row blocks of A
@@ -399,7 +423,7 @@ def cpu_baseline_oracle(a64, k, p, q, seed, budget_rows=(300, 600)):
     l = k + p
     om = oracle.omega(seed, n, l)
     times = []
-    for r in budget_rows:
+    for r in budget_rows:  # the oracle's CoR-UTV is single-threaded C
         blk = np.ascontiguousarray(a64[:r].cpu().numpy())
         t = time.perf_counter()
         oracle.cor_utv(blk, k, p, q, om)
@@ -440,7 +464,14 @@ def bench_c3(args, w, cu, torch, np):
                 gq[fmt] = json.load(f)
     import inputs as I
 
-    a64, sig = I.config_matrix("c3", backend="torch", device=dev)
+    if args.input_cache and os.path.exists(args.input_cache):
+        # a matrix saved by an earlier run of this workload (no QR on the device,
+        # which matters under counter profilers)
+        a64 = torch.from_numpy(np.load(args.input_cache, allow_pickle=False)).to(dev)
+    else:
+        a64, _ = I.config_matrix("c3", backend="torch", device=dev)
+        if args.input_cache:
+            np.save(args.input_cache, a64.cpu().numpy())
     k, p, q = gold["k"], gold["p"], gold["q"]
     l = k + p
     seed = gold["omega_seed"]
@@ -531,6 +562,85 @@ def bench_c3(args, w, cu, torch, np):
     }
 
 
+def bench_rpca(args, w, cu, torch, np):
+    """Robust PCA solves/s: each step is one whole ALM-CoRUTV solve (to
+    zeta < 1e-5) of the same M, from the input in HBM to L and S in HBM."""
+    import inputs as I
+    import oracle
+
+    n, rk, k, p, q, seed = w["n"], w["rank"], w["k"], w["p"], w["q"], w["seed"]
+    low, sp = I.rpca_matrix(n, n, rk, w["frac"], seed=seed)
+    M = torch.from_numpy(low + sp).to("cuda:0")
+    lowd = torch.from_numpy(low).to("cuda:0")
+    spd = torch.from_numpy(sp).to("cuda:0")
+    stream = torch.cuda.Stream()
+    infos, step_ms = [], []
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            L, S, info = cu.rpca(M, k, p, q, seed=seed, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            L, S, info = cu.rpca(M, k, p, q, seed=seed, stream=stream)
+            step_ms.append((time.perf_counter() - ts) * 1e3)
+            infos.append(info.as_dict())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        # pass timing over one more solve, every pass launch bracketed by events
+        cu.cor_profile_enable(True)
+        cu.cor_profile_read()
+        cu.rpca(M, k, p, q, seed=seed, stream=stream)
+        torch.cuda.synchronize()
+        prof = cu.cor_profile_read()
+        cu.cor_profile_enable(False)
+    lerr = float(torch.linalg.norm(L - lowd) / torch.linalg.norm(lowd))
+    serr = float(torch.linalg.norm(S - spd) / torch.linalg.norm(spd))
+    last = infos[-1]
+    ok = last["rank"] == rk and last["zeta"] < 1e-5 and lerr < 1e-4 and serr < 1e-4
+    roofline = pass_roofline("f64", k + p, prof)
+    roofline["traffic"] = traffic_of("rpca")
+    cpu = None
+    if not args.no_cpu:
+        # the oracle's ALM-CoRUTV on the same M for its first iterations; every
+        # iteration does the same work (one CoR-UTV, the product, the updates),
+        # so per-iteration time x the GPU solve's iteration count is the solve
+        mh = low + sp
+        nthr = cpu_threads()
+        with blas_limit(nthr):
+            t = time.perf_counter()
+            oracle.rpca_alm(mh, k, p, q, omega_seed=seed, max_iter=w["cpu_iters"])
+            dt = time.perf_counter() - t
+        est = dt / w["cpu_iters"] * last["iters"]
+        cpu = dict(value=1.0 / est, unit="solves/s", cores=nthr, kind="oracle",
+                   sample=f"oracle rpca_alm on the same {n}x{n} M, first {w['cpu_iters']} "
+                          f"iterations: {dt:.1f} s -> {est:.1f} s for the solve's "
+                          f"{last['iters']} iterations",
+                   seconds_sampled=round(dt, 2), cores_available=os.cpu_count())
+    return {
+        "metric": "ALM-CoRUTV robust PCA solves/s (to zeta < 1e-5)",
+        "value": round(args.steps / (t1 - t0), 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round((t1 - t0) / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rpca: " + w["desc"], "n": n, "rank": rk, "k": k, "l": k + p,
+                   "q": q},
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                       "p99": round(float(np.percentile(step_ms, 99)), 3)},
+        "result": {"iters": last["iters"], "rank": last["rank"], "zeta": last["zeta"],
+                   "L_err": lerr, "S_err": serr, "recovered": ok},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -540,6 +650,9 @@ def main():
     ap.add_argument("--formats", default="f64,f32,bf16,fp8",
                     help="c3: pass formats to run, the first one is the line's value")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--input-cache", default="", metavar="NPY",
+                    help="c3: load the 20000x10000 matrix from this .npy file if it exists, "
+                         "else build it and save it there")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
@@ -574,6 +687,9 @@ def main():
         return
     if args.workload == "c4batched":
         print(json.dumps(bench_batched(args, w, cu, torch, np)))
+        return
+    if args.workload == "rpca":
+        print(json.dumps(bench_rpca(args, w, cu, torch, np)))
         return
     if args.workload == "c5served":
         print(json.dumps(bench_served(args, w, cu, torch, np)))
