@@ -708,7 +708,11 @@ __device__ __forceinline__ double quad_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// QRCP of M = R2^T for l > 224 (one block of up to 1024 threads per problem).
+// QRCP of M = R2^T for l > 224, first part: the first l - 224 steps (one
+// block of up to 1024 threads per problem); k_qrcp_hy takes the remaining 224
+// steps on the trailing 224 x 224 block (rows >= l - 224, the columns not yet
+// pivoted, in their original order so that ties still go to the lowest
+// column index).
 //   M does not fit the registers of one work-group, so it stays in a global
 //   work array W (l x l, row-major, in P.R, which is free once R2 is formed;
 //   it stays in L2).  Four lanes own a column, lane t the rows i = 4 u + t
@@ -722,8 +726,12 @@ __device__ __forceinline__ double quad_sum(double v) {
 //        over its rows at and below j (loads in batches of 64 rows, four
 //        partial sums per lane, a quad sum), then col -= w v, stored back, and
 //        the squared norm below j posted as the next key.
-//   Rows above j are skipped in batches (uniform branches).  Outputs as in
-//   the register-resident kernel, read from W at the end.
+//   Rows above j are skipped in batches (uniform branches).  At the end it
+//   writes what its steps fix: tau, signs, perm and the reflectors of steps
+//   < l - 224, the block of T on those rows and columns, and the map from the
+//   trailing block's columns to the columns of M (int32, in P.Racc, free
+//   after R2 = R' R).  W keeps the rows above the trailing block, which
+//   k_qrcp_hy reads for the rest of T.
 // ---------------------------------------------------------------------------
 constexpr int QST_THREADS = 1024;
 constexpr int QST_COLS = QST_THREADS / 4;  // columns per pass over the lane groups
@@ -736,11 +744,14 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
     __shared__ double s_nrm[LMAX];
     __shared__ double s_tau[LMAX], s_scale[LMAX], s_beta[LMAX];
     __shared__ int s_perm[LMAX];
+    __shared__ unsigned char s_ret[LMAX];  // column pivoted
+    __shared__ int s_wcnt[QST_THREADS / 64];
     __shared__ unsigned long long s_key[2];
     int local;
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
     const int l = P.l;
     if (l <= QHY_LMAX) return;  // k_qrcp_rt, k_qrcp_hy
+    const int jend = l - QHY_LMAX;  // steps taken here
     const int tid = threadIdx.x, t = tid & 3;
     const int ngroups = blockDim.x >> 2;
     // a lane group owns column tid/4 and, when l exceeds the group count,
@@ -753,6 +764,7 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
 
     // W = M = R2^T, and the squared column norms
     if (tid < 2) s_key[tid] = 0ull;
+    for (int c = tid; c < l; c += blockDim.x) s_ret[c] = 0;
     __syncthreads();
     for (int cs = 0; cs < ncs; cs++) {
         const int c = (tid >> 2) + cs * ngroups;
@@ -774,7 +786,7 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
     bool active[2] = {(tid >> 2) < l, (tid >> 2) + ngroups < l};
     __syncthreads();
 
-    for (int j = 0; j < l; j++) {
+    for (int j = 0; j < jend; j++) {
         const unsigned long long key = s_key[j & 1];
         const int p = 511 - (int)(key & 0x1FFull);
         // the pivot column into LDS, one element per thread (one round trip);
@@ -803,6 +815,7 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
             s_scale[j] = scale;
             s_beta[j] = beta;
             s_perm[j] = p;
+            s_ret[p] = 1;
         }
         for (int cs = 0; cs < ncs; cs++) {
             const int c = (tid >> 2) + cs * ngroups;
@@ -857,24 +870,36 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
         __syncthreads();
     }
 
-    // Outputs: column perm[b] of W holds raw_b (frozen since step b).
-    for (int e = tid; e < l * l; e += blockDim.x) {
+    // Outputs of the steps taken here: column perm[b] of W holds raw_b
+    // (frozen since step b); T on rows and columns < jend, reflector rows < jend.
+    for (int e = tid; e < jend * l; e += blockDim.x) {
         const int a = e / l, b = e % l;
-        double tv = 0.0;
-        if (a < b) tv = W[a * l + s_perm[b]] * (s_beta[a] < 0.0 ? -1.0 : 1.0);
-        else if (a == b) tv = fabs(s_beta[a]);
-        P.T[e] = tv;
+        if (b < jend) {
+            double tv = 0.0;
+            if (a < b) tv = W[a * l + s_perm[b]] * (s_beta[a] < 0.0 ? -1.0 : 1.0);
+            else if (a == b) tv = fabs(s_beta[a]);
+            P.T[a * l + b] = tv;
+        }
         // reflector a, component b
         double vv = 0.0;
         if (b == a) vv = 1.0;
         else if (b > a) vv = W[b * l + s_perm[a]] * s_scale[a];
         P.Qt[e] = vv;
     }
-    for (int j = tid; j < l; j += blockDim.x) {
+    for (int j = tid; j < jend; j += blockDim.x) {
         P.tau[j] = s_tau[j];
         P.tau[LMAX + j] = s_beta[j] < 0.0 ? -1.0 : 1.0;
         P.perm[j] = s_perm[j];
     }
+    // the columns left for the trailing block, in increasing order
+    const int lane = tid & 63, wave = tid >> 6;
+    const bool act = tid < l && !s_ret[tid];
+    const unsigned long long bal = __ballot(act);
+    if (lane == 0) s_wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int off = __popcll(bal & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wave; w++) off += s_wcnt[w];
+    if (act) ((int32_t*)P.Racc)[off] = tid;
 }
 
 // ---------------------------------------------------------------------------
@@ -891,6 +916,11 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
 // col_i -= (w scale) raw_i below j, col_j -= w, and posts its squared norm
 // below j: one FMA per element and pass, masks only in the block of row j.
 // Register rows above j are skipped in blocks of 16 (uniform branches).
+// For l > 224 it takes the steps after k_qrcp_st's first l - 224: the
+// trailing 224 x 224 block (rows >= l - 224 of the columns k_qrcp_st left, read
+// from its work array through its column map), with its archive in P.Rinv, and
+// writes the rest of T, the reflectors, tau, signs and perm (mapped back to
+// the columns of M).
 // ---------------------------------------------------------------------------
 
 template <int LRC>
@@ -912,15 +942,21 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
     __shared__ unsigned long long s_key[2];
     int local;
     const Prob& P = group_prob2(probs, pidx, toff, cnt, local);
-    const int l = P.l;
-    if (l <= QRT_LMAX || l > QHY_LMAX) return;
+    const int L = P.l;
+    if (L <= QRT_LMAX) return;
+    const bool tail = L > QHY_LMAX;  // the trailing block after k_qrcp_st
+    const int l = tail ? QHY_LMAX : L;
+    const int j0 = L - l;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int c = tid >> 2, t = tid & 3;
     const bool incol = c < l;
     // archive: column j = raw pivot column of step j (global address space, so
     // that its stores do not hold up the LDS waits)
-    gdouble_rw* __restrict__ arc = (gdouble_rw*)P.R;
+    gdouble_rw* __restrict__ arc = (gdouble_rw*)(tail ? P.Rinv : P.R);
     gdouble* __restrict__ R2 = as_global(P.msrc);  // M^T: R2 (M = R2^T), or Mx
+    gdouble* __restrict__ W = as_global(P.R);      // k_qrcp_st's work array (tail)
+    const int32_t* __restrict__ cmap = (const int32_t*)P.Racc;
+    const int mc = tail && incol ? cmap[c] : 0;     // column of M held by this group
 
     // rows past l are zero and stay zero (the pivot column is zero there)
     double col[RR];
@@ -928,13 +964,15 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
 #pragma unroll
     for (int u = 0; u < RR; u++) {
         const int i = 4 * u + t;
-        col[u] = (incol && i < l) ? R2[c * l + i] : 0.0;  // M[i][c] = R2[c][i]
+        // M[i][c] = R2[c][i]; tail: row j0 + i of column mc of the work array
+        col[u] = (incol && i < l) ? (tail ? W[(j0 + i) * L + mc] : R2[c * l + i]) : 0.0;
         nn = fma(col[u], col[u], nn);
     }
 #pragma unroll
     for (int k = 0; k < LR; k++) {
         const int i = 4 * (RR + k) + t;
-        const double v = (incol && i < l) ? R2[c * l + i] : 0.0;
+        const double v =
+            (incol && i < l) ? (tail ? W[(j0 + i) * L + mc] : R2[c * l + i]) : 0.0;
         s_m[tid * LRP + k] = v;
         nn = fma(v, v, nn);
     }
@@ -1087,22 +1125,50 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
 
     // Outputs from the archive: arc[b * l + i] = raw_b[i] (the archive writes
     // of the pivot groups are visible after the barriers of the loop)
-    for (int e = tid; e < l * l; e += nth) {
-        const int a = e / l, b = e % l;
-        double tv = 0.0;
-        if (a < b) tv = arc[b * l + a] * (s_beta[a] < 0.0 ? -1.0 : 1.0);
-        else if (a == b) tv = fabs(s_beta[a]);
+    if (!tail) {
+        for (int e = tid; e < l * l; e += nth) {
+            const int a = e / l, b = e % l;
+            double tv = 0.0;
+            if (a < b) tv = arc[b * l + a] * (s_beta[a] < 0.0 ? -1.0 : 1.0);
+            else if (a == b) tv = fabs(s_beta[a]);
+            P.T[e] = tv;
+            // reflector a, component b
+            double vv = 0.0;
+            if (b == a) vv = 1.0;
+            else if (b > a) vv = arc[a * l + b] * s_scale[a];
+            P.Qt[e] = vv;
+        }
+        for (int jj = tid; jj < l; jj += nth) {
+            P.tau[jj] = s_tau[jj];
+            P.tau[LMAX + jj] = s_beta[jj] < 0.0 ? -1.0 : 1.0;
+            P.perm[jj] = s_perm[jj];
+        }
+        return;
+    }
+    // Tail: rows < j0 of T beyond column j0 are the final values of the
+    // columns pivoted here at those rows (W, untouched after step a < j0),
+    // with k_qrcp_st's row signs; rows >= j0 come from this block's archive.
+    for (int e = tid; e < L * L; e += nth) {
+        const int a = e / L, b = e % L;
+        if (a < j0) {
+            if (b >= j0) P.T[e] = W[a * L + cmap[s_perm[b - j0]]] * P.tau[LMAX + a];
+            continue;
+        }
+        const int a2 = a - j0, b2 = b - j0;
+        double tv = 0.0, vv = 0.0;
+        if (b2 >= 0) {
+            if (a2 < b2) tv = arc[b2 * l + a2] * (s_beta[a2] < 0.0 ? -1.0 : 1.0);
+            else if (a2 == b2) tv = fabs(s_beta[a2]);
+            if (b2 == a2) vv = 1.0;
+            else if (b2 > a2) vv = arc[a2 * l + b2] * s_scale[a2];
+        }
         P.T[e] = tv;
-        // reflector a, component b
-        double vv = 0.0;
-        if (b == a) vv = 1.0;
-        else if (b > a) vv = arc[a * l + b] * s_scale[a];
         P.Qt[e] = vv;
     }
     for (int jj = tid; jj < l; jj += nth) {
-        P.tau[jj] = s_tau[jj];
-        P.tau[LMAX + jj] = s_beta[jj] < 0.0 ? -1.0 : 1.0;
-        P.perm[jj] = s_perm[jj];
+        P.tau[j0 + jj] = s_tau[jj];
+        P.tau[LMAX + j0 + jj] = s_beta[jj] < 0.0 ? -1.0 : 1.0;
+        P.perm[j0 + jj] = cmap[s_perm[jj]];
     }
 }
 
@@ -1361,24 +1427,25 @@ hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
                                   : launch_qrcp_rt<16, 8>(g, lr, s);
         if (e != hipSuccess || lmax <= QRT_LMAX) return e;
     }
-    // 128 < l <= 224: registers and LDS
-    {
-        const int lh = std::min(lmax, QHY_LMAX);
-        // LDS rows per lane for the largest l of the launch, rounded up to 4
-        const int lrc = std::max(0, ((lh + 3) / 4 - QHY_RR + 3) / 4 * 4);
-        hipError_t e = lrc == 0    ? launch_qrcp_hy<0>(g, lh, s)
-                       : lrc == 4  ? launch_qrcp_hy<4>(g, lh, s)
-                       : lrc == 8  ? launch_qrcp_hy<8>(g, lh, s)
-                       : lrc == 12 ? launch_qrcp_hy<12>(g, lh, s)
-                       : lrc == 16 ? launch_qrcp_hy<16>(g, lh, s)
-                                   : launch_qrcp_hy<20>(g, lh, s);
-        if (e != hipSuccess || lmax <= QHY_LMAX) return e;
+    // l > 224: the first l - 224 steps with M streamed from the L2-resident
+    // work array, 4 lanes per column; k_qrcp_hy takes the rest
+    if (lmax > QHY_LMAX) {
+        const int threads = std::min(QST_THREADS, (4 * lmax + 63) / 64 * 64);
+        hipLaunchKernelGGL(k_qrcp_st, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx,
+                           g.toff, g.count);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    // l > 224: M streamed from the L2-resident work array, 4 lanes per column
-    const int threads = std::min(QST_THREADS, (4 * lmax + 63) / 64 * 64);
-    hipLaunchKernelGGL(k_qrcp_st, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx, g.toff,
-                       g.count);
-    return hipGetLastError();
+    // 128 < l <= 224, and the trailing 224 steps of larger l: registers and LDS
+    const int lh = std::min(lmax, QHY_LMAX);
+    // LDS rows per lane for the largest l of the launch, rounded up to 4
+    const int lrc = std::max(0, ((lh + 3) / 4 - QHY_RR + 3) / 4 * 4);
+    return lrc == 0    ? launch_qrcp_hy<0>(g, lh, s)
+           : lrc == 4  ? launch_qrcp_hy<4>(g, lh, s)
+           : lrc == 8  ? launch_qrcp_hy<8>(g, lh, s)
+           : lrc == 12 ? launch_qrcp_hy<12>(g, lh, s)
+           : lrc == 16 ? launch_qrcp_hy<16>(g, lh, s)
+                       : launch_qrcp_hy<20>(g, lh, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -210,6 +210,53 @@ def test_batched_equals_single_and_oracle(cu, dev, orc):
         assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
 
 
+def test_batched_every_qrcp_class(cu, dev, orc):
+    """One batched call whose problems take every QRCP kernel class (l = 20
+    register-resident, l = 150 registers + LDS, l = 240 and 264 streamed first
+    steps then the trailing 224 x 224 block) next to each other: each equals
+    its single call bitwise and the oracle to the FP64 rule."""
+    import torch
+
+    shapes = [(600, 500, 14, 6, 1), (640, 520, 140, 10, 0), (700, 560, 230, 10, 1),
+              (620, 600, 250, 14, 0)]
+    probs, outs, mats, oms = [], [], [], []
+    for i, (m, n, k, p, q) in enumerate(shapes):
+        a, _ = I.lowrank(m, n, np.exp(-np.arange(1, n + 1) / 50.0), seed=900 + i)
+        om = I.gaussian_omega(n, k + p, 30 + i)
+        A = torch.from_numpy(a).to(dev)
+        omd = torch.from_numpy(om).to(dev)
+        o = _outputs(dev, m, n, k + p)
+        probs.append(cu.make_problem(A, k, p, q, 0, *o, omega=omd))
+        outs.append(o)
+        mats.append((a, A))
+        oms.append((om, omd))
+    st, _ = cu.cor_utv_batched(probs, cu.cor_opts(0, 0))
+    cu.check(st, "batched")
+    torch.cuda.synchronize()
+    for i, (m, n, k, p, q) in enumerate(shapes):
+        a, A = mats[i]
+        o1 = _outputs(dev, m, n, k + p)
+        st, _ = cu.cor_utv_ex(cu.make_problem(A, k, p, q, 0, *o1, omega=oms[i][1]),
+                              cu.cor_opts(0, 0))
+        cu.check(st, "single")
+        torch.cuda.synchronize()
+        for x, y in zip(outs[i], o1):
+            assert torch.equal(x, y), f"problem {i} (l = {k + p}) differs from its single call"
+        Ub, Tb, Vb, Pb = [x.cpu().numpy() for x in outs[i]]
+        ref = orc.cor_utv(a, k, p, q, oms[i][0])
+        mg = orc.metrics(a, Ub, Tb, Vb, k)
+        mo = orc.metrics(a, ref["U"], ref["T"], ref["V"], k)
+        print(f"[qrcp classes l={k + p}] d eps {abs(mg['err_l'] - mo['err_l']):.1e} "
+              f"orth {mg['orth_u']:.1e} {mg['orth_v']:.1e} gap {ref['diag'][1]:.1e}")
+        assert abs(mg["err_l"] - mo["err_l"]) <= 1e-12
+        assert abs(mg["err_k"] - mo["err_k"]) <= 1e-12
+        assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
+        assert np.array_equal(np.tril(Tb, -1), np.zeros_like(Tb))
+        if ref["diag"][1] > 1e-8:
+            assert np.array_equal(Pb, ref["perm"])
+            assert np.abs(Tb - ref["T"]).max() <= 1e-10 * np.abs(ref["T"]).max()
+
+
 def test_batched_bf16_recipe_against_oracle(cu, dev, orc):
     """The batched workload's own recipe in BF16 (m, n ~ U{256..1024},
     k ~ U{8..64}, l = k + 8, sigma_i = exp(-i/k), q = 1, A stored BF16): each
