@@ -48,6 +48,10 @@ WORKLOADS = {
     "rpca": dict(n=4000, rank=200, frac=0.05, k=200, p=64, q=1, seed=606, cpu_iters=1,
                  desc="robust PCA, M = L + S 4000x4000, rank(L)=200, 5% +-80 outliers; "
                       "ALM-CoRUTV k=200, l=264, q=1, FP64"),
+    # the tall robust-PCA request shape with the fused power step
+    "tall": dict(m=76800, n=2000, rank=5, frac=0.05, k=5, p=8, q=2, seed=707,
+                 desc="76800x2000 FP32 (rank 5 + 5% +-80 outliers), k=5, l=13, q=2; fused power "
+                      "step (q + 2 = 4 reads of A) against the two-pass step (2q + 2 = 6)"),
     # many independent problems in one batched plan (BF16 passes)
     "c4batched": dict(count=512, seed=404, prec="bf16",
                       desc="512 problems, m,n ~ U{256..4096}, k ~ U{8..64}, l=k+8, q=1, "
@@ -287,7 +291,8 @@ def bench_served(args, w, cu, torch, np):
     }
 
 
-def timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=None, profile_steps=20):
+def timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=None, profile_steps=20,
+               opts=None, profile_kind=1):
     """Plan one decomposition of the device matrix A, capture it into a HIP
     graph, replay `warmup` untimed and `steps` timed decompositions, then time
     the passes over A of eager runs of the same plan with HIP events on the
@@ -301,7 +306,8 @@ def timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=None, profile_ste
     perm = torch.empty((l,), dtype=torch.int32, device=dev)
     prob = cu.make_problem(A, k, p, q, seed=seed, U=U, T=T, V=V, perm=perm, colscale=colscale)
     stream = torch.cuda.Stream()
-    st, plan = cu.cor_plan_create([prob], cu.cor_opts(0, 0))
+    opts = opts if opts is not None else cu.cor_opts(0, 0)
+    st, plan = cu.cor_plan_create([prob], opts)
     cu.check(st, "plan_create")
     graph = not args.no_graph
     try:
@@ -322,9 +328,9 @@ def timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=None, profile_ste
             t1 = time.perf_counter()
             # Pass timing: eager runs of a second plan over the same problem,
             # each pass launch bracketed by events on the plan's stream.
-            st2, plan2 = cu.cor_plan_create([prob], cu.cor_opts(0, 0))
+            st2, plan2 = cu.cor_plan_create([prob], opts)
             cu.check(st2, "plan_create")
-            cu.cor_profile_enable(True)
+            cu.cor_profile_enable(profile_kind)
             cu.cor_profile_read()
             for _ in range(profile_steps):
                 cu.check(cu.cor_plan_run(plan2, stream), "plan_run")
@@ -356,26 +362,28 @@ def accuracy(torch, a64, U, T, V, k):
                 orth_v=float(torch.linalg.norm(V.T @ V - eye)))
 
 
-def pass_roofline(prec, l, prof):
+def pass_roofline(prec, l, prof, kernel="k_sketch (passes over A)", flops_per_elem=2):
     """Roofline of the passes over A (the dominant kernel): achieved
     algorithmic flops or bytes per launch over the mean launch time."""
     launches = max(1, prof["launches"])
     avg_s = prof["ms"] / launches / 1e3
     flops = prof["flops"] / launches
     nbytes = prof["bytes"] / launches
-    # A pass does 2 l flops per element of A: MFMA-bound above the ridge
-    # (FP64 l >= 39, FP32 l >= 40), HBM-bound below it and in BF16/FP8.
-    if prec == "f64" and l >= 39:
+    # A pass does 2 l flops per element of A (the fused step 4 l): MFMA-bound
+    # above the ridge (FP64 l >= 39, FP32 l >= 40 for a pass), HBM-bound below
+    # it and in BF16/FP8.
+    lr = l * flops_per_elem / 2
+    if prec == "f64" and lr >= 39:
         bound, peak, unit = "mfma", PEAKS["f64"], "TFLOP/s"
         achieved = flops / avg_s / 1e12
-    elif prec == "f32" and l >= 40:
+    elif prec == "f32" and lr >= 40:
         bound, peak, unit = "mfma", PEAKS["f32"], "TFLOP/s"
         achieved = flops / avg_s / 1e12
     else:
         bound, peak, unit = "hbm", PEAKS["hbm_GBs"], "GB/s"
         achieved = nbytes / avg_s / 1e9
     return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 4), "kernel": "k_sketch (passes over A)",
+            "frac": round(achieved / peak, 4), "kernel": kernel,
             "avg_launch_us": round(avg_s * 1e6, 2), "launches_timed": prof["launches"],
             "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes}
 
@@ -562,6 +570,58 @@ def bench_c3(args, w, cu, torch, np):
     }
 
 
+def bench_tall(args, w, cu, torch, np):
+    """Decompositions/s of a tall FP32 matrix with a small rank, where the
+    passes are bound by HBM bandwidth: the fused power step (A^T (A X) in one
+    read of A) against the two-pass step, same matrix and test matrix."""
+    import inputs as I
+
+    m, n, k, p, q, seed = w["m"], w["n"], w["k"], w["p"], w["q"], w["seed"]
+    l = k + p
+    low, sp = I.rpca_matrix(m, n, w["rank"], w["frac"], seed=seed)
+    a64h = low + sp
+    del low, sp
+    a64 = torch.from_numpy(a64h).to("cuda:0")
+    A = a64.float().contiguous()
+    fused = timed_plan(cu, torch, np, A, k, p, q, 12345, args,
+                       opts=cu.cor_opts(0, 0, 0, 0, 1), profile_kind=2)
+    two = timed_plan(cu, torch, np, A, k, p, q, 12345, args, profile_kind=1)
+    acc_f = accuracy(torch, a64, fused["U"], fused["T"], fused["V"], k)
+    acc_2 = accuracy(torch, a64, two["U"], two["T"], two["V"], k)
+    roof = pass_roofline("f32", l, fused["prof"], kernel="k_ata (fused power step)",
+                         flops_per_elem=4)
+    roof["traffic"] = traffic_of("tall")
+    roof2 = pass_roofline("f32", l, two["prof"])
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_oracle(a64, k, p, q, 12345, budget_rows=(8000, 16000))
+        cpu["cores_available"] = os.cpu_count()
+    v_f = args.steps / fused["elapsed"]
+    v_2 = args.steps / two["elapsed"]
+    return {
+        "metric": "CoR-UTV decompositions/s, fused power step (roofline of the fused pass)",
+        "value": round(v_f, 3),
+        "unit": "decomps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(fused["elapsed"] / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tall: " + w["desc"], "m": m, "n": n, "k": k, "l": l, "q": q,
+                   "graph": fused["graph"]},
+        "latency_ms": {"p50": round(float(np.percentile(fused["step_ms"], 50)), 4),
+                       "p99": round(float(np.percentile(fused["step_ms"], 99)), 4)},
+        "two_pass": {"decomps_per_s": round(v_2, 3),
+                     "ms_per_decomp": round(two["elapsed"] / args.steps * 1e3, 4),
+                     "pass_roofline": roof2, "accuracy": acc_2},
+        "speedup_over_two_pass": round(v_f / v_2, 3),
+        "accuracy": dict(acc_f, err_l_minus_two_pass=acc_f["err_l"] - acc_2["err_l"],
+                         rule="|eps_fused - eps_two_pass| <= 1e-5 (FP32)",
+                         at_fixed_error=bool(abs(acc_f["err_l"] - acc_2["err_l"]) <= 1e-5)),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+
+
 def bench_rpca(args, w, cu, torch, np):
     """Robust PCA solves/s: each step is one whole ALM-CoRUTV solve (to
     zeta < 1e-5) of the same M, from the input in HBM to L and S in HBM."""
@@ -687,6 +747,9 @@ def main():
         return
     if args.workload == "c4batched":
         print(json.dumps(bench_batched(args, w, cu, torch, np)))
+        return
+    if args.workload == "tall":
+        print(json.dumps(bench_tall(args, w, cu, torch, np)))
         return
     if args.workload == "rpca":
         print(json.dumps(bench_rpca(args, w, cu, torch, np)))

@@ -121,6 +121,19 @@ typedef struct {
  * U = V', L = T'^T, V = U'.  For ULV the optional test matrix `omega` is
  * m x l, perm permutes the columns of U (U[:, j] = Q[:, perm[j]] for the
  * row-space basis Q), and the rank-k truncation is U L[:, :k] V[:, :k]^T. */
+/* Fused power step (cor_opts.fused_power = 1): for the q steps before the
+ * final pair, one pass over A forms Y = A^T (A X) (each block of rows of A is
+ * read from HBM once and used for both products), then R1 = chol(X^T Y), the
+ * Cholesky factor of the first sketch's Gram (A X)^T (A X), and Y R1^{-1} =
+ * A^T Q1 as in the two-pass step.  Passes over A: q + 2 instead of 2q + 2.
+ * It pays where the passes are bound by HBM bandwidth (FP32 with l < 20,
+ * FP64 with l < 39, e.g. tall matrices with a small rank).  Each block of a
+ * pass keeps its share of the n x l result in registers, so it requires
+ * COR_F32 or COR_F64 passes, l <= 64, n <= 2400 (FP32) or n <= 1024 (FP64),
+ * and ceil(n / 16) * ceil(l / 16) <= 8 T with T = 24 (FP32, l <= 32), 16
+ * (FP32, l > 32), 12 (FP64, l <= 32) or 8 (FP64, l > 32) -- n is the column
+ * count of the matrix the passes read, m for COR_ULV -- and one q for all
+ * problems of a batched call; else COR_E_INVAL. */
 #define COR_M_R2T 0
 #define COR_M_EXPLICIT 1
 #define COR_M_APPROX 2
@@ -134,6 +147,9 @@ typedef struct {
                          /*   arithmetic); 1: two passes after every product                      */
     int32_t compress;    /* COR_M_R2T (0, default), COR_M_EXPLICIT, COR_M_APPROX                 */
     int32_t orient;      /* COR_URV (0, default) or COR_ULV                                       */
+    int32_t fused_power; /* 1: each power step before the final pair reads A once, forming        */
+                         /*   A^T (A X) as Alg. 3's loop prints it (see below); 0 (default): two  */
+                         /*   passes, A X then A^T Q1                                             */
 } cor_opts;
 
 /* ---------------------------------------------------------------------------
@@ -297,7 +313,9 @@ cor_status cor_quantize(const float* A32, int64_t m, int64_t n, int64_t lda, int
 cor_status cor_omega(uint64_t seed, int64_t n, int32_t l, double* out, void* stream);
 
 /* Kernel timing of the passes over A for roofline reports: while enabled, each
- * launch of the sketch kernels is bracketed by HIP events on its own stream.
+ * launch of the pass kernels is bracketed by HIP events on its own stream.
+ * on: 0 off; 1 the two-pass kernels (A X, A^T X); 2 the fused power step's
+ * kernel (A^T (A X)); 3 both.
  * cor_profile_read() synchronises those events and returns the summed time
  * (ms), the number of launches and the algorithmic bytes and flops of those
  * launches, then resets the counters. */

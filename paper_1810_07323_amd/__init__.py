@@ -42,7 +42,7 @@ class cor_problem(C.Structure):
 
 class cor_opts(C.Structure):
     _fields_ = [("report", C.c_int32), ("cholqr2_all", C.c_int32), ("compress", C.c_int32),
-                ("orient", C.c_int32)]
+                ("orient", C.c_int32), ("fused_power", C.c_int32)]
 
 
 class cor_rpca_opts(C.Structure):
@@ -317,7 +317,8 @@ def cor_omega(seed, n, l, out, stream=None):
 
 
 def cor_profile_enable(on=True):
-    return lib().cor_profile_enable(1 if on else 0)
+    """on: False/0 off, True/1 the two-pass kernels, 2 the fused power step, 3 both."""
+    return lib().cor_profile_enable(int(on))
 
 
 def cor_profile_read():
@@ -342,7 +343,7 @@ def cor_release():
 # Convenience: allocate outputs with torch and run one decomposition.
 # ---------------------------------------------------------------------------
 def decompose(A, k, p, q, seed=0, omega=None, colscale=None, report=False, stream=None,
-              compress=COR_M_R2T, orient=COR_URV):
+              compress=COR_M_R2T, orient=COR_URV, fused=False):
     """Return (U, T, V, perm, info) for device matrix A (torch tensor on cuda)."""
     import torch
 
@@ -357,6 +358,7 @@ def decompose(A, k, p, q, seed=0, omega=None, colscale=None, report=False, strea
     if omega is not None:
         om = torch.as_tensor(omega, dtype=torch.float64, device=dev).contiguous()
     pr = make_problem(A, k, p, q, seed, U, T, V, perm, om, colscale)
-    st, info = cor_utv_ex(pr, cor_opts(1 if report else 0, 0, compress, orient), stream)
+    st, info = cor_utv_ex(pr, cor_opts(1 if report else 0, 0, compress, orient, 1 if fused else 0),
+                          stream)
     check(st, "cor_utv_ex")
     return U, T, V, perm, info

@@ -92,6 +92,11 @@ struct Prob {
     double* Tout;        // ULV: the caller's T, written as the transpose of T
     const void* ulv_src; // ULV: the caller's A (m_caller = n rows, leading dimension ulv_lda)
     int64_t ulv_lda;
+
+    // Fused power step (A^T (A X) in one read of A) for the iterations < q:
+    // s_f row splits of kc_f rows (a multiple of 128) each, partials in ypart.
+    int32_t fused, s_f;
+    int64_t kc_f;
 };
 
 // Compression of A to the l x l core.

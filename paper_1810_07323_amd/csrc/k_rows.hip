@@ -256,8 +256,9 @@ __global__ __launch_bounds__(256) void k_sum(const Prob* __restrict__ probs,
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter > P.q) return;
     if (iter < 0 && P.mmode != M_EXPLICIT) return;  // the pass A Q2 of eq. (14)
+    if (side == SIDE_F && (!P.fused || iter >= P.q)) return;
     const int64_t rows = side == SIDE_M ? P.m : P.n;
-    const int S = side == SIDE_M ? P.s_ax : P.s_atx;
+    const int S = side == SIDE_M ? P.s_ax : side == SIDE_N ? P.s_atx : P.s_f;
     const int l = P.l, lp = P.lp, nq = lp / 4;
     const int64_t idx = (int64_t)local * 256 + threadIdx.x;
     const int64_t r = idx / nq;
@@ -347,6 +348,7 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     if (iter >= 0 && iter > P.q) return;
     if (SRC == GSRC_QA && !second_pass(P, iter)) return;
     if (CROSS && P.mmode != (SRC == GSRC_XM ? M_EXPLICIT : M_APPROX)) return;
+    if (SRC == GSRC_XY && (!P.fused || iter >= P.q)) return;
     const int l = P.l, lp = P.lp;
     const int nt = lp / 16;
     // symmetric Grams: the upper tiles; cross products Z1^T Z2: every tile
@@ -371,8 +373,9 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     const double* __restrict__ Z = SRC == GSRC_Y ? P.Y : SRC == GSRC_QA ? P.Qa : SRC == GSRC_U ? P.U
                                  : SRC == GSRC_V ? P.V : SRC == GSRC_XM ? P.Q1 : P.Q2;
     // second operand: Z itself, or A Q2 (in Y) for M = Q1^T A Q2, or the last
-    // power step's input X for Q2^T X
-    const double* __restrict__ Z2 = SRC == GSRC_XM ? P.Y : SRC == GSRC_XA ? P.Xk : Z;
+    // power step's input X for Q2^T X, or A^T A X (in Y) for X^T A^T A X
+    const double* __restrict__ Z2 =
+        (SRC == GSRC_XM || SRC == GSRC_XY) ? P.Y : SRC == GSRC_XA ? P.Xk : Z;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -450,6 +453,7 @@ hipError_t launch_gram(const LaunchGroup& g, int side, int src, int iter, hipStr
         case GSRC_V: return launch_gram_t<GSRC_V>(g, side, iter, s);
         case GSRC_XM: return launch_gram_t<GSRC_XM>(g, side, iter, s);
         case GSRC_XA: return launch_gram_t<GSRC_XA>(g, side, iter, s);
+        case GSRC_XY: return launch_gram_t<GSRC_XY>(g, side, iter, s);
     }
     return hipErrorInvalidValue;
 }
@@ -618,7 +622,8 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     if (iter >= 0 && iter > P.q) return;
-    const bool two = MODE != AP_Q1_QS_U && second_pass(P, iter);
+    if (MODE == AP_Y_RINV_Y && (!P.fused || iter >= P.q)) return;
+    const bool two = MODE != AP_Q1_QS_U && MODE != AP_Y_RINV_Y && second_pass(P, iter);
     if (MODE == AP_QA_RINV_Q && !two) return;
     const int l = P.l, lp = P.lp;
     const int nt = lp / 16;
@@ -631,9 +636,11 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
     const double* __restrict__ S = MODE == AP_Q1_QS_U ? P.G : P.Rinv;
     // First pass: into Qa when a second pass follows, else straight into Q
     // (and its operand copy for the next pass).  U = Q1 Qs: into U only.
+    // The fused power step's Y R1^{-1} stays in Y (a block reads all of its
+    // rows before it writes them back).
     double* const qdst = MODE == AP_Q1_QS_U ? P.U : side == SIDE_M ? P.Q1 : P.Q2;
-    double* const dst = (MODE == AP_Y_RINV_QA && two) ? P.Qa : qdst;
-    const bool op = MODE != AP_Q1_QS_U && !(MODE == AP_Y_RINV_QA && two);
+    double* const dst = (MODE == AP_Y_RINV_QA && two) ? P.Qa : MODE == AP_Y_RINV_Y ? P.Y : qdst;
+    const bool op = MODE != AP_Q1_QS_U && MODE != AP_Y_RINV_Y && !(MODE == AP_Y_RINV_QA && two);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -782,6 +789,7 @@ hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int 
         case AP_QA_RINV_Q: return launch_apply_m<AP_QA_RINV_Q>(g, side, lmax, iter, s);
         case AP_Y_RINV_Q: return launch_apply_m<AP_Y_RINV_Q>(g, side, lmax, iter, s);
         case AP_Q1_QS_U: return launch_apply_m<AP_Q1_QS_U>(g, side, lmax, iter, s);
+        case AP_Y_RINV_Y: return launch_apply_m<AP_Y_RINV_Y>(g, side, lmax, iter, s);
     }
     return hipErrorInvalidValue;
 }

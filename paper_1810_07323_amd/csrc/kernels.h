@@ -18,13 +18,29 @@ struct LaunchGroup {
     int32_t blocks;
 };
 
-enum Side : int32_t { SIDE_M = 0, SIDE_N = 1 };
+// SIDE_F: the n-side rows summed over the row splits of the fused power step.
+enum Side : int32_t { SIDE_M = 0, SIDE_N = 1, SIDE_F = 2 };
 
 // Passes over A (split-K partial sums).
 hipError_t launch_sketch(int prec, bool trans, int nt, const LaunchGroup& g, int iter,
                          hipStream_t s);
 int sketch_rows_per_block(int prec, int nt, bool trans);  // output rows per block of A X / A^T X
 int sketch_k_tile(int prec);
+// Fused power step: per row split, the partial sums of A^T (A X) (n x lp, in
+// the accumulation format) into ypart; blocks per problem s_f.  nt = lp / 16 of
+// the launch (at most ATA_NTMAX), prec F32 or F64, tpw = tiles of the n x lp
+// sum per wave (ata_tiles_per_wave, at most ata_max_tiles_per_wave), lds =
+// the largest ata_lds_bytes of the launch (at most ATA_LDS).
+constexpr int ATA_ROWS = 128;      // granularity of a row split
+constexpr int ATA_NTMAX = 4;       // l <= 64
+constexpr int ATA_NMAX32 = 2400;   // largest n (FP32): a 16-row chunk of A in LDS
+constexpr int ATA_NMAX64 = 1024;   // largest n (FP64)
+constexpr int ATA_LDS = 160 * 1024;
+int ata_tiles_per_wave(int64_t n, int lp);
+int ata_max_tiles_per_wave(int prec, int lp);
+size_t ata_lds_bytes(int64_t n, int lp, int prec);
+hipError_t launch_ata(int prec, int nt, int tpw, size_t lds, const LaunchGroup& g, int iter,
+                      hipStream_t s);
 
 // Row-block kernels.
 hipError_t launch_omega(const LaunchGroup& g, hipStream_t s);          // blocks: ceil(n*l/2/256)
@@ -33,7 +49,8 @@ hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s); 
 // Gram partial sums of a row-major rows x l FP64 matrix picked by `src`.
 enum GramSrc : int32_t { GSRC_Y = 0, GSRC_QA = 1, GSRC_U = 2, GSRC_V = 3,
                          GSRC_XM = 4,   // Q1^T (A Q2): every tile (compression of eq. (14))
-                         GSRC_XA = 5 }; // Q2^T X: every tile (eq. (18))
+                         GSRC_XA = 5,   // Q2^T X: every tile (eq. (18))
+                         GSRC_XY = 6 }; // X^T (A^T A X) of the fused power step: symmetric
 constexpr int GRAM_THREADS = 256;
 // One upper 16 x 16 tile of the l x l Gram matrix per block (four waves
 // split the chunk's rows); a launch covers (row chunks) x (upper tiles) blocks.
@@ -51,7 +68,8 @@ constexpr int MO_COLS = 16;
 // dst = src R^{-1}, row blocks of APPLY_ROWS; lmax = largest l of the group.
 constexpr int APPLY_ROWS = 16;
 enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2,
-                           AP_Q1_QS_U = 3 };  // U = Q1 Qs (Qs in G, after the QRCP)
+                           AP_Q1_QS_U = 3,   // U = Q1 Qs (Qs in G, after the QRCP)
+                           AP_Y_RINV_Y = 4 };  // Y <- Y R1^{-1} in place (fused power step)
 hipError_t launch_apply(const LaunchGroup& g, int side, int mode, int lmax, int iter,
                         hipStream_t s);
 hipError_t launch_gather_v(const LaunchGroup& g, hipStream_t s);  // blocks: ceil(n*l/256)

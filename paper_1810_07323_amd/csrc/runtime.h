@@ -29,6 +29,9 @@ size_t plan_bytes(const Plan* P);
 const Prob& plan_desc(const Plan* P, int i);
 int plan_count(const Plan* P);
 int plan_report(const Plan* P);
+// Whether a problem can take the fused power step (COR_OK, else COR_E_INVAL
+// with the reason in cor_last_error()).
+cor_status fused_check(const cor_problem& p, int ulv);
 // Device workspace of one decomposition with the given options (NULL: defaults).
 size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec, const cor_opts* opts = nullptr);
 

@@ -46,7 +46,7 @@ cor_status hip_fail(hipError_t e, const char* what) {
 // ---------------------------------------------------------------------------
 struct ProfState {
     std::mutex mu;
-    bool on = false;
+    int on = 0;  // bit 0: the two-pass kernels (A X, A^T X); bit 1: the fused power step
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> free_ev;
     double bytes = 0.0, flops = 0.0;
@@ -54,9 +54,9 @@ struct ProfState {
 };
 static ProfState g_prof;
 
-static void prof_begin(hipStream_t s, hipEvent_t* a, hipEvent_t* b) {
+static void prof_begin(hipStream_t s, hipEvent_t* a, hipEvent_t* b, int kind) {
     *a = *b = nullptr;
-    if (!g_prof.on) return;
+    if (!(g_prof.on & kind)) return;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     if (g_prof.free_ev.empty()) {
         hipEvent_t x, y;
@@ -98,8 +98,8 @@ struct Layout {
     // per-problem sizes
     int32_t l, lp, nt;
     int64_t ldx, ldq;
-    int32_t s_ax, s_atx;
-    int64_t kc_ax, kc_atx;
+    int32_t s_ax, s_atx, s_f;
+    int64_t kc_ax, kc_atx, kc_f;
     int32_t rb_m, rb_n, gb_m, gb_n;
     size_t off[O_COUNT];
     size_t total;
@@ -107,14 +107,17 @@ struct Layout {
 
 
 // K splits of a pass: about `target` blocks in all (row blocks x splits, never
-// more), at most 8 splits, each split at least 16 K tiles long in BF16 and FP8
+// more), at most 8 splits (64 with fewer than 32 row blocks), each split at least 16 K tiles long in BF16 and FP8
 // and 4 in FP32 and FP64.  The layout of
 // a problem depends on its own shape only, never on what it is batched with,
 // so a decomposition gives bitwise the same result alone, batched or served.
 static void split_k(int64_t rows, int64_t K, int bk, int target, int prec, int nt, bool trans,
                     int32_t* s, int64_t* kc) {
     const int64_t nrb = cdiv(rows, sketch_rows_per_block(prec, nt, trans));
-    int64_t sp = std::min<int64_t>(8, std::max<int64_t>(1, target / nrb));
+    // Few output row blocks (the transposed pass of a tall matrix: n small,
+    // K = m long) need more splits to fill the GPU: up to 64 there.
+    const int64_t cap = nrb >= 32 ? 8 : 64;
+    int64_t sp = std::min<int64_t>(cap, std::max<int64_t>(1, target / nrb));
     // Short BF16 and FP8 splits cost more in prologue, epilogue and partial
     // sums than they win (small problems of a batch); an FP32 or FP64 tile
     // holds 2-4x fewer elements of K, so more MFMA work, and small problems
@@ -168,9 +171,17 @@ static int sketch_block_target() {
 // request: rows of 16-byte multiples.
 static int64_t at_ld(int64_t n, int prec) { return roundup(n, 16); }
 
+// Row splits of the fused power step: one block per CU (the kernel holds
+// its n x lp partial sum in LDS), whole chunks of ATA_ROWS rows each.
+static void fused_splits(int64_t m, int32_t* s, int64_t* kc) {
+    const int64_t sp = std::max<int64_t>(1, std::min<int64_t>(256, cdiv(m, ATA_ROWS)));
+    *kc = roundup(cdiv(m, sp), ATA_ROWS);
+    *s = (int32_t)cdiv(m, *kc);
+}
+
 // m, n are the dimensions of the matrix the passes read (A^T for ULV).
 static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_target,
-                          int gram_target, int mmode = M_R2T, int ulv = 0) {
+                          int gram_target, int mmode = M_R2T, int ulv = 0, int fused = 0) {
     Layout L;
     L.l = l;
     L.lp = (int32_t)roundup(l, 16);
@@ -187,6 +198,9 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
             prec, L.nt, true, &L.s_atx, &L.kc_atx);
     gram_chunks(m, L.lp, gram_target, &L.rb_m, &L.gb_m);
     gram_chunks(n, L.lp, gram_target, &L.rb_n, &L.gb_n);
+    L.s_f = 0;
+    L.kc_f = 0;
+    if (fused) fused_splits(m, &L.s_f, &L.kc_f);
     const int sz = prec_size(prec);
     const int acc = prec == P_F64 ? 8 : 4;
     size_t sizes[O_COUNT];
@@ -194,7 +208,8 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
     sizes[O_QOP] = (size_t)L.lp * L.ldq * sz;
     sizes[O_XSC] = (size_t)L.lp * 4;
     sizes[O_QSC] = (size_t)L.lp * 4;
-    sizes[O_YPART] = (size_t)std::max((int64_t)L.s_ax * m, (int64_t)L.s_atx * n) * L.lp * acc;
+    sizes[O_YPART] = (size_t)std::max({(int64_t)L.s_ax * m, (int64_t)L.s_atx * n,
+                                       (int64_t)L.s_f * n}) * L.lp * acc;
     const int64_t mx = std::max(m, n);
     sizes[O_Y] = (size_t)mx * l * 8;
     sizes[O_QA] = (size_t)mx * l * 8;
@@ -235,6 +250,25 @@ static cor_status validate_opts(const cor_opts* o, const cor_problem& p) {
     return COR_OK;
 }
 
+// The fused power step (A^T (A X) in one read of A): FP32 or FP64 passes,
+// l <= 64, and the n x lp partial sum plus a chunk of A X in one CU's LDS.
+// n is the column count of the matrix the passes read (m for ULV).
+cor_status fused_check(const cor_problem& p, int ulv) {
+    const int64_t n = ulv ? p.m : p.n;
+    const int lp = (int)roundup((int64_t)p.k + p.p, 16);
+    if (p.prec != COR_F64 && p.prec != COR_F32)
+        return fail(COR_E_INVAL, "the fused power step needs COR_F64 or COR_F32 passes");
+    if (lp / 16 > ATA_NTMAX) return fail(COR_E_INVAL, "the fused power step needs l <= 64");
+    const bool f64 = p.prec == COR_F64;
+    if (n > (f64 ? ATA_NMAX64 : ATA_NMAX32) ||
+        ata_tiles_per_wave(n, lp) > ata_max_tiles_per_wave(p.prec, lp) ||
+        ata_lds_bytes(n, lp, p.prec) > ATA_LDS)
+        return fail(COR_E_INVAL, "the fused power step needs n <= 2400 (FP32) or n <= 1024 "
+                                 "(FP64) and ceil(n / 16) * roundup(l, 16) / 16 <= 8 T with "
+                                 "T = 24 (FP32, l <= 32), 16 (FP32), 12 (FP64, l <= 32), 8 (FP64)");
+    return COR_OK;
+}
+
 static cor_status validate(const cor_problem& p) {
     const int64_t l = (int64_t)p.k + p.p;
     if (!p.A || !p.U || !p.T || !p.V) return fail(COR_E_INVAL, "null A, U, T or V");
@@ -257,7 +291,7 @@ struct Plan {
     int max_q = 0;
     int report = 0;
     int prec_mix = 0;  // bitmask of precisions present
-    bool has_explicit = false, has_approx = false, has_ulv = false;
+    bool has_explicit = false, has_approx = false, has_ulv = false, has_fused = false;
     int nj = 1;        // ceil(max l / 64): column tiles of the row-block products
     int lmax = 0;      // largest l of the plan
     std::vector<cor_problem> reqs;
@@ -271,12 +305,15 @@ struct Plan {
         LaunchGroup g{};
         int nt = 0;
         int prec = 0;
+        int aux = 0;      // fused step: tiles per wave
+        size_t lds = 0;   // fused step: dynamic LDS bytes
         double bytes = 0, flops = 0;  // algorithmic cost of one launch
     };
     Grp omega, opM, opN, sumM, sumN, gramM, gramN, redM, redN, small, applyM, applyN, vg, r2, norm;
     Grp scM, scN;  // FP8 operand scales: row chunks of the column maxima
     Grp xgM, xgN, xred, keepx, tra, ulvt;  // compression modes and ULV
     std::vector<Grp> skAX, skATX;  // per (precision, column tiles)
+    std::vector<Grp> ata;          // fused power step, per (precision, column tiles)
     std::vector<Grp> formU;        // per register-tile class of l (nt holds l)
     Grp applyU;                    // U = Q1 Qs for the problems with u_via_qs
     // per iteration of the power loop: whether any problem of the plan takes
@@ -322,6 +359,15 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     }
     const int mmode = opts ? opts->compress : M_R2T;
     const int ulv = (opts && opts->orient == COR_ULV) ? 1 : 0;
+    const int fused = (opts && opts->fused_power) ? 1 : 0;
+    if (fused)
+        for (int i = 0; i < count; i++) {
+            cor_status st = fused_check(probs[i], ulv);
+            if (st != COR_OK) return st;
+            if (probs[i].q != probs[0].q)
+                return fail(COR_E_INVAL, "a plan with the fused power step needs one q for all "
+                                         "its problems");
+        }
     // A ULV request is run as the URV of A^T (an n x m matrix in the
     // workspace): the problem the stages see has m and n, U and V swapped.
     const cor_problem* const caller = probs;
@@ -344,7 +390,8 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     std::vector<size_t> base(count);
     for (int i = 0; i < count; i++) {
         const cor_problem& q = probs[i];
-        P->lay.push_back(make_layout(q.m, q.n, q.k + q.p, q.prec, sk_target, gr_target, mmode, ulv));
+        P->lay.push_back(
+            make_layout(q.m, q.n, q.k + q.p, q.prec, sk_target, gr_target, mmode, ulv, fused));
         base[i] = ws;
         ws += P->lay.back().total;
         P->max_q = std::max(P->max_q, (int)q.q);
@@ -352,6 +399,7 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         P->nj = std::max(P->nj, (int)((q.k + q.p + 63) / 64));
         P->lmax = std::max(P->lmax, (int)(q.k + q.p));
     }
+    P->has_fused = fused != 0;
     P->has_explicit = mmode == M_EXPLICIT;
     P->has_approx = mmode == M_APPROX;
     P->has_ulv = ulv != 0;
@@ -427,11 +475,19 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
             ublk.push_back(cdiv(probs[i].m, APPLY_ROWS));
         }
     const TableBuilder::Ref R_applyU = tb.add(usub, ublk);
-    struct SkRef { int prec, nt; TableBuilder::Ref ax, atx; double bax, fax, batx, fatx; };
+    struct SkRef {
+        int prec, nt;
+        TableBuilder::Ref ax, atx, ata;
+        double bax, fax, batx, fatx, bata, fata;
+        int tpw;
+        size_t lds;
+    };
     std::vector<SkRef> skrefs;
     for (auto& kv : classes) {
-        std::vector<int64_t> bax, batx;
-        double bytes_ax = 0, fl = 0, bytes_atx = 0;
+        std::vector<int64_t> bax, batx, bata;
+        double bytes_ax = 0, fl = 0, bytes_atx = 0, bytes_ata = 0;
+        int tpw = 0;
+        size_t lds = 0;
         for (int i : kv.second) {
             const cor_problem& q = probs[i];
             const Layout& L = P->lay[i];
@@ -442,9 +498,17 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
             bytes_ax += abytes + (double)q.n * L.l * sz + (double)q.m * L.l * 4.0;
             bytes_atx += abytes + (double)q.m * L.l * sz + (double)q.n * L.l * 4.0;
             fl += 2.0 * q.m * q.n * L.l;
+            // fused step: A once, X, and the n x l result
+            bata.push_back(L.s_f);
+            bytes_ata += abytes + (double)q.n * L.l * sz + (double)q.n * L.l * 8.0;
+            if (fused) {
+                tpw = std::max(tpw, ata_tiles_per_wave(q.n, L.lp));
+                lds = std::max(lds, ata_lds_bytes(q.n, L.lp, q.prec));
+            }
         }
         SkRef r{kv.first.first, kv.first.second, tb.add(kv.second, bax), tb.add(kv.second, batx),
-                bytes_ax, fl, bytes_atx, fl};
+                tb.add(kv.second, bata), bytes_ax, fl, bytes_atx, fl, bytes_ata, 2.0 * fl,
+                tpw, lds};
         skrefs.push_back(r);
     }
 
@@ -533,6 +597,9 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         d.perm = q.perm ? q.perm : (int32_t*)(w + L.off[O_PERM]);
         d.omega = q.omega;
         d.seed = q.seed;
+        d.fused = fused;
+        d.s_f = L.s_f;
+        d.kc_f = L.kc_f;
     }
     P->tab_host.swap(tb.host);
     if (ext_mem) {
@@ -599,6 +666,16 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         b.bytes = r.batx; b.flops = r.fatx;
         P->skAX.push_back(a);
         P->skATX.push_back(b);
+        if (P->has_fused) {
+            Plan::Grp f = mk(r.ata);
+            f.nt = r.nt;
+            f.prec = r.prec;
+            f.bytes = r.bata;
+            f.flops = r.fata;
+            f.aux = r.tpw;
+            f.lds = r.lds;
+            P->ata.push_back(f);
+        }
     }
     *out = P;
     return COR_OK;
@@ -608,7 +685,7 @@ static hipError_t run_sketch(const std::vector<Plan::Grp>& gs, bool trans, int i
                              hipStream_t s) {
     for (const auto& g : gs) {
         hipEvent_t a, b;
-        prof_begin(s, &a, &b);
+        prof_begin(s, &a, &b, 1);
         hipError_t e = launch_sketch(g.prec, trans, g.nt, g.g, iter, s);
         if (e != hipSuccess) return e;
         prof_end(s, a, b, g.bytes, g.flops);
@@ -629,7 +706,42 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
     E(launch_omega(P->omega.g, s));  // Q2 <- Omega (FP64)
     if (fp8) E(launch_op_scales(P->scN.g, P->small.g, SIDE_N, 0, s));
     E(launch_make_op(P->opN.g, SIDE_N, s));  // X <- Omega in the pass format
+    // Q2 R2 = Y (CholeskyQR, two passes for the final pair); X <- Q2
+    auto nside = [&](int it) -> hipError_t {
+        E(launch_gram(P->gramN.g, SIDE_N, GSRC_Y, it, s));
+        E(launch_gram_reduce(P->redN.g, SIDE_N, 0, it, s));
+        E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
+        E(launch_apply(P->applyN.g, SIDE_N, AP_Y_RINV_QA, P->lmax, it, s));
+        if (P->second[it]) {
+            E(launch_gram(P->gramN.g, SIDE_N, GSRC_QA, it, s));
+            E(launch_gram_reduce(P->redN.g, SIDE_N, 1, it, s));
+            E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
+        }
+        if (P->last[it]) E(launch_r2(P->r2.g, it, 0, s));
+        if (P->second[it]) E(launch_apply(P->applyN.g, SIDE_N, AP_QA_RINV_Q, P->lmax, it, s));
+        return hipSuccess;
+    };
     for (int it = 0; it <= P->max_q; it++) {
+        if (P->has_fused && it < P->max_q) {
+            // The loop of Alg. 3 as printed, C2 = A^T (A C2), in one read of
+            // A: Y = A^T A X; R1 from X^T Y = (A X)^T (A X) (the Gram of the
+            // first sketch); Y <- Y R1^{-1} = A^T Q1; then the n-side
+            // orthonormalisation as after the A^T Q1 pass.  (Every problem of
+            // a fused plan has the same q.)
+            for (const auto& g : P->ata) {
+                hipEvent_t a, b;
+                prof_begin(s, &a, &b, 2);
+                E(launch_ata(g.prec, g.nt, g.aux, g.lds, g.g, it, s));
+                prof_end(s, a, b, g.bytes, g.flops);
+            }
+            E(launch_sum(P->sumN.g, SIDE_F, it, s));
+            E(launch_gram(P->gramN.g, SIDE_N, GSRC_XY, it, s));
+            E(launch_gram_reduce(P->redN.g, SIDE_N, 0, it, s));
+            E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
+            E(launch_apply(P->applyN.g, SIDE_N, AP_Y_RINV_Y, P->lmax, it, s));
+            E(nside(it));
+            continue;
+        }
         // Y1 = A X, Q1 R1 = Y1 (CholeskyQR2)
         E(run_sketch(P->skAX, false, it, s));
         E(launch_sum(P->sumM.g, SIDE_M, it, s));
@@ -654,17 +766,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         // Y2 = A^T Q1, Q2 R2 = Y2 (CholeskyQR2); X <- Q2
         E(run_sketch(P->skATX, true, it, s));
         E(launch_sum(P->sumN.g, SIDE_N, it, s));
-        E(launch_gram(P->gramN.g, SIDE_N, GSRC_Y, it, s));
-        E(launch_gram_reduce(P->redN.g, SIDE_N, 0, it, s));
-        E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
-        E(launch_apply(P->applyN.g, SIDE_N, AP_Y_RINV_QA, P->lmax, it, s));
-        if (P->second[it]) {
-            E(launch_gram(P->gramN.g, SIDE_N, GSRC_QA, it, s));
-            E(launch_gram_reduce(P->redN.g, SIDE_N, 1, it, s));
-            E(launch_chol(P->small.g, CHOL_SECOND, P->lmax, it, s));
-        }
-        if (P->last[it]) E(launch_r2(P->r2.g, it, 0, s));
-        if (P->second[it]) E(launch_apply(P->applyN.g, SIDE_N, AP_QA_RINV_Q, P->lmax, it, s));
+        E(nside(it));
         if (fp8 && it < P->max_q) {
             E(launch_op_scales(P->scN.g, P->small.g, SIDE_N, it, s));
             E(launch_make_op(P->opN.g, SIDE_N, s));
@@ -725,8 +827,8 @@ cor_status plan_capture(Plan* P, hipStream_t s) {
         P->graph = nullptr;
     }
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    const bool prof = g_prof.on;
-    g_prof.on = false;  // no event records inside the graph
+    const int prof = g_prof.on;
+    g_prof.on = 0;  // no event records inside the graph
     hipError_t e = plan_enqueue(P, s);
     g_prof.on = prof;
     hipGraph_t g = nullptr;
@@ -783,8 +885,9 @@ size_t plan_bytes(const Plan* P) { return P->mem_bytes; }
 size_t workspace_bytes(int64_t m, int64_t n, int32_t l, int prec, const cor_opts* opts) {
     const int mmode = opts ? opts->compress : M_R2T;
     const int ulv = (opts && opts->orient == COR_ULV) ? 1 : 0;
-    Layout L = ulv ? make_layout(n, m, l, prec, sketch_block_target(), 1024, mmode, 1)
-                   : make_layout(m, n, l, prec, sketch_block_target(), 1024, mmode, 0);
+    const int fused = (opts && opts->fused_power) ? 1 : 0;
+    Layout L = ulv ? make_layout(n, m, l, prec, sketch_block_target(), 1024, mmode, 1, fused)
+                   : make_layout(m, n, l, prec, sketch_block_target(), 1024, mmode, 0, fused);
     return L.total + 256 + 1024;
 }
 
@@ -1005,7 +1108,7 @@ cor_status cor_omega(uint64_t seed, int64_t n, int32_t l, double* out, void* str
 
 cor_status cor_profile_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    g_prof.on = on != 0;
+    g_prof.on = on & 3;
     return COR_OK;
 }
 

@@ -139,6 +139,7 @@ static void launch_round(Server* S, std::vector<Request*>& adm) {
         o.cholqr2_all = ok[0]->opts.cholqr2_all;
         o.compress = ok[0]->opts.compress;
         o.orient = ok[0]->opts.orient;
+        o.fused_power = ok[0]->opts.fused_power;
     }
     cor_status st = COR_OK;
     if (!ok.empty()) st = plan_create(probs.data(), (int32_t)probs.size(), &o, &R->plan, s, true);
@@ -217,12 +218,16 @@ static void server_loop(Server* S) {
         }
         if (!adm.empty()) {
             // one round per combination of the options that change the
-            // stage sequence (orthonormalisation, compression, orientation);
-            // the report option does not change the results
+            // stage sequence (orthonormalisation, compression, orientation,
+            // the fused power step, which also needs one q per round); the
+            // report option does not change the results
             std::map<int, std::vector<Request*>> part;
-            for (Request* r : adm)
-                part[(r->opts.cholqr2_all ? 1 : 0) + 2 * r->opts.compress + 8 * r->opts.orient]
+            for (Request* r : adm) {
+                const int f = r->opts.fused_power ? 1 : 0;
+                part[(r->opts.cholqr2_all ? 1 : 0) + 2 * r->opts.compress + 8 * r->opts.orient +
+                     16 * f + 32 * f * r->prob.q]
                     .push_back(r);
+            }
             for (auto& kv : part) launch_round(S, kv.second);
         }
         bool progressed = !adm.empty();
@@ -289,10 +294,18 @@ cor_status cor_server_submit(cor_server* server, const cor_problem* prob, const 
         S->rejected++;
         return fail(COR_E_INVAL, "malformed request");
     }
+    const bool convert = S->cfg.convert_f32_to == COR_BF16 && p.prec == COR_F32;
+    if (opts && opts->fused_power &&
+        (convert || fused_check(p, opts->orient == COR_ULV ? 1 : 0) != COR_OK)) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->rejected++;
+        return fail(COR_E_INVAL, "the fused power step cannot run this request (FP32 or FP64 "
+                                 "passes, l <= 64, n within the limits of cor_opts)");
+    }
     Request* r = new Request();
     r->prob = p;
     if (opts) r->opts = *opts;
-    r->convert = (S->cfg.convert_f32_to == COR_BF16 && p.prec == COR_F32);
+    r->convert = convert;
     r->footprint = request_footprint(p, r->opts, r->convert);
     if (r->footprint > S->cfg.hbm_budget) {
         delete r;
