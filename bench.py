@@ -52,6 +52,11 @@ WORKLOADS = {
     "tall": dict(m=76800, n=2000, rank=5, frac=0.05, k=5, p=8, q=2, seed=707,
                  desc="76800x2000 FP32 (rank 5 + 5% +-80 outliers), k=5, l=13, q=2; fused power "
                       "step (q + 2 = 4 reads of A) against the two-pass step (2q + 2 = 6)"),
+    # A in pinned host memory, streamed in panels for every pass
+    "host": dict(m=200000, n=1000, rank=5, frac=0.05, k=5, p=8, q=2, seed=808, panel_rows=32768,
+                 desc="200000x1000 FP32 in pinned host memory (rank 5 + 5% +-80 outliers), k=5, "
+                      "l=13, q=2, panels of 32768 rows; fused power step (q + 2 = 4 streams of A) "
+                      "and two-pass step (6 streams)"),
     # many independent problems in one batched plan (BF16 passes)
     "c4batched": dict(count=512, seed=404, prec="bf16",
                       desc="512 problems, m,n ~ U{256..4096}, k ~ U{8..64}, l=k+8, q=1, "
@@ -622,6 +627,88 @@ def bench_tall(args, w, cu, torch, np):
     }
 
 
+def bench_host(args, w, cu, torch, np):
+    """Decompositions/s with A in pinned host memory: every pass streams A
+    over the host link in row panels, the copy of the next panel overlapping
+    the kernels of the current one.  The bound is the host-to-device copy
+    rate, calibrated here with a plain pinned copy of the same size."""
+    import inputs as I
+
+    m, n, k, p, q, seed = w["m"], w["n"], w["k"], w["p"], w["q"], w["seed"]
+    l = k + p
+    low, sp = I.rpca_matrix(m, n, w["rank"], w["frac"], seed=seed)
+    a64h = low + sp
+    del low, sp
+    Ah = torch.from_numpy(a64h.astype(np.float32)).pin_memory()
+    dev = torch.device("cuda:0")
+    nbytes = m * n * 4
+    # link calibration: the same bytes in one pinned host-to-device copy
+    dst = torch.empty((m, n), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        dst.copy_(Ah, non_blocking=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(Ah, non_blocking=True)
+    torch.cuda.synchronize()
+    link = 3 * nbytes / (time.perf_counter() - t) / 1e9
+    U = torch.empty((m, l), dtype=torch.float64, device=dev)
+    T = torch.empty((l, l), dtype=torch.float64, device=dev)
+    V = torch.empty((n, l), dtype=torch.float64, device=dev)
+    pr = cu.make_problem(Ah, k, p, q, 12345, U, T, V)
+    res = {}
+    for name, fused in (("fused", 1), ("two_pass", 0)):
+        opts = cu.cor_opts(0, 0, 0, 0, fused)
+        for _ in range(max(1, args.warmup)):
+            cu.check(cu.cor_utv_host(pr, opts, w["panel_rows"])[0], "cor_utv_host")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = []
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            st, info = cu.cor_utv_host(pr, opts, w["panel_rows"])
+            cu.check(st, "cor_utv_host")
+            ms.append((time.perf_counter() - ts) * 1e3)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        passes = (q + 2) if fused else (2 * q + 2)
+        acc = accuracy(torch, torch.from_numpy(a64h).to(dev), U, T, V, k) if name == "fused" \
+            else None
+        res[name] = dict(decomps_per_s=args.steps / el, ms=el / args.steps * 1e3,
+                         p50=float(np.percentile(ms, 50)), p99=float(np.percentile(ms, 99)),
+                         link_GBs=passes * nbytes / (el / args.steps) / 1e9, passes=passes,
+                         accuracy=acc)
+    f, tp = res["fused"], res["two_pass"]
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline_oracle(torch.from_numpy(a64h), k, p, q, 12345,
+                                  budget_rows=(20000, 40000))
+        cpu["cores_available"] = os.cpu_count()
+    return {
+        "metric": "CoR-UTV decompositions/s with A in host memory (host link rate against a "
+                  "pinned copy)",
+        "value": round(f["decomps_per_s"], 3),
+        "unit": "decomps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(f["ms"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "host: " + w["desc"], "m": m, "n": n, "k": k, "l": l, "q": q,
+                   "panel_rows": w["panel_rows"]},
+        "latency_ms": {"p50": round(f["p50"], 3), "p99": round(f["p99"], 3)},
+        "link": {"bound": "host-to-device copy", "achieved_GBs": round(f["link_GBs"], 2),
+                 "pinned_copy_GBs": round(link, 2), "frac": round(f["link_GBs"] / link, 4),
+                 "streams_of_A": f["passes"]},
+        "two_pass": {"decomps_per_s": round(tp["decomps_per_s"], 3), "ms": round(tp["ms"], 3),
+                     "link_GBs": round(tp["link_GBs"], 2), "streams_of_A": tp["passes"],
+                     "frac": round(tp["link_GBs"] / link, 4)},
+        "speedup_over_two_pass": round(f["decomps_per_s"] / tp["decomps_per_s"], 3),
+        "accuracy": f["accuracy"],
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+
+
 def bench_rpca(args, w, cu, torch, np):
     """Robust PCA solves/s: each step is one whole ALM-CoRUTV solve (to
     zeta < 1e-5) of the same M, from the input in HBM to L and S in HBM."""
@@ -747,6 +834,9 @@ def main():
         return
     if args.workload == "c4batched":
         print(json.dumps(bench_batched(args, w, cu, torch, np)))
+        return
+    if args.workload == "host":
+        print(json.dumps(bench_host(args, w, cu, torch, np)))
         return
     if args.workload == "tall":
         print(json.dumps(bench_tall(args, w, cu, torch, np)))

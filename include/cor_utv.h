@@ -173,6 +173,25 @@ cor_status cor_utv_batched(const cor_problem* probs, int32_t count, const cor_op
                            cor_info* infos, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * A in host memory (larger than HBM, or not resident): the pass model of
+ * Sec. III with A stored outside the fast memory, where each pass over A is
+ * the cost (2q + 2 passes, q + 2 with cor_opts.fused_power).  prob->A is a
+ * HOST pointer (m x n, leading dimension lda, format prec; page-locked memory
+ * from hipHostMalloc gives full copy bandwidth, pageable memory also works);
+ * colscale, omega and the outputs are device pointers as for cor_utv_ex.
+ * Every pass streams A in panels of `panel_rows` rows (<= 0: about 256 MiB per
+ * panel; rounded up to a multiple of 128) through two device staging
+ * buffers, the copy of the next panel overlapping the kernels of the current
+ * one.  The device holds the m x l and n x l factors and the panels only.
+ * Results equal cor_utv_ex's up to the order of the K-split partial sums.
+ * Not available with report = 1, COR_M_EXPLICIT or COR_ULV (COR_E_INVAL).
+ * Returns after the work on `stream` has completed; device_ms covers the
+ * whole call, copies included.
+ * ------------------------------------------------------------------------- */
+cor_status cor_utv_host(const cor_problem* prob, const cor_opts* opts, int64_t panel_rows,
+                        cor_info* info, void* stream);
+
+/* ---------------------------------------------------------------------------
  * For callers that cannot allocate device memory (code that must not call
  * hipMalloc: tight serving loops, harnesses that forbid allocation): the
  * decomposition of cor_utv_ex run entirely inside a fixed array of

@@ -82,6 +82,8 @@ _SIGS = {
     "cor_utv_ex": (C.c_int, [C.POINTER(cor_problem), C.POINTER(cor_opts), C.POINTER(cor_info), _P]),
     "cor_utv_ex_noalloc": (C.c_int, [C.POINTER(cor_problem), C.POINTER(cor_opts),
                                      C.POINTER(cor_info), _P]),
+    "cor_utv_host": (C.c_int, [C.POINTER(cor_problem), C.POINTER(cor_opts), C.c_int64,
+                               C.POINTER(cor_info), _P]),
     "cor_utv_batched": (C.c_int, [C.POINTER(cor_problem), C.c_int32, C.POINTER(cor_opts),
                                   C.POINTER(cor_info), _P]),
     "cor_rpca_alm": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, C.POINTER(cor_rpca_opts),
@@ -206,6 +208,14 @@ def cor_utv_ex_noalloc(problem, opts=None, stream=None):
     info = cor_info()
     st = lib().cor_utv_ex_noalloc(C.byref(problem), C.byref(opts) if opts is not None else None,
                                   C.byref(info), stream_handle(stream))
+    return st, info
+
+
+def cor_utv_host(problem, opts=None, panel_rows=0, stream=None):
+    """problem.A is a host address (e.g. a pinned torch tensor's data_ptr())."""
+    info = cor_info()
+    st = lib().cor_utv_host(C.byref(problem), C.byref(opts) if opts is not None else None,
+                            panel_rows, C.byref(info), stream_handle(stream))
     return st, info
 
 

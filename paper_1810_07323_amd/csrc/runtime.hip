@@ -322,6 +322,7 @@ struct Plan {
     std::vector<char> second, last;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
+    struct HostStream* hs = nullptr;  // A in host memory, streamed in row panels
     bool async = false;
     bool owned = true;  // mem was allocated by the plan (else caller-provided)
     std::vector<int32_t> tab_host;
@@ -681,6 +682,71 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     return COR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// A in host memory (the paper's pass model with A stored externally): every
+// pass streams A in row panels through NB device staging buffers, the copy
+// of panel p + 1 (on a copy stream) overlapping the kernels of panel p.  Each
+// panel has descriptors of its own: for A X, rows r0 .. r0 + mp of the
+// problem (A = the staging buffer, Y = the panel's rows of Y); for A^T Q1
+// and the fused step, a K range of the problem whose split-K partial sums go
+// to the panel's own split slots, which the problem's k_sum then adds.
+// ---------------------------------------------------------------------------
+enum HostPass { HP_AX = 0, HP_ATX = 1, HP_ATA = 2 };
+constexpr int HS_NB = 2;  // staging buffers
+
+struct HostStream {
+    const char* A = nullptr;  // host, m x n, leading dimension lda (elements)
+    int64_t m = 0, n = 0, lda = 0, rows = 0;  // rows per panel
+    int npanel = 0, sz = 0, nt = 0, prec = 0;
+    void* mem = nullptr;  // device: staging | partial scratch | descriptors | tables
+    char* stage[HS_NB] = {nullptr, nullptr};
+    hipStream_t cs = nullptr;
+    hipEvent_t copied[HS_NB] = {nullptr, nullptr}, freed[HS_NB] = {nullptr, nullptr};
+    hipEvent_t start = nullptr;
+    bool used[HS_NB] = {false, false};
+    // per panel and pass kind: its launch groups
+    std::vector<LaunchGroup> sk[3], sum;  // sketch / fused kernel; M-side sum of A X
+};
+
+static hipError_t host_pass(Plan* P, int kind, int it, hipStream_t s) {
+    HostStream* H = P->hs;
+    hipError_t e = hipEventRecord(H->start, s);
+    if (e != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(H->cs, H->start, 0)) != hipSuccess) return e;
+    for (int p = 0; p < H->npanel; p++) {
+        const int slot = p % HS_NB;
+        const int64_t r0 = (int64_t)p * H->rows;
+        const int64_t mp = std::min(H->rows, H->m - r0);
+        if (H->used[slot] && (e = hipStreamWaitEvent(H->cs, H->freed[slot], 0)) != hipSuccess)
+            return e;
+        const size_t w = (size_t)H->n * H->sz;
+        e = H->lda == H->n
+                ? hipMemcpyAsync(H->stage[slot], H->A + r0 * w, mp * w, hipMemcpyHostToDevice, H->cs)
+                : hipMemcpy2DAsync(H->stage[slot], w, H->A + r0 * H->lda * H->sz,
+                                   (size_t)H->lda * H->sz, w, mp, hipMemcpyHostToDevice, H->cs);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventRecord(H->copied[slot], H->cs)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, H->copied[slot], 0)) != hipSuccess) return e;
+        const LaunchGroup& g = H->sk[kind][p];
+        hipEvent_t a, b;
+        prof_begin(s, &a, &b, kind == HP_ATA ? 2 : 1);
+        if (kind == HP_ATA) {
+            const Prob& d = P->hp[0];
+            e = launch_ata(H->prec, H->nt, ata_tiles_per_wave(H->n, d.lp),
+                           ata_lds_bytes(H->n, d.lp, H->prec), g, it, s);
+        } else {
+            e = launch_sketch(H->prec, kind == HP_ATX, H->nt, g, it, s);
+        }
+        if (e != hipSuccess) return e;
+        const double abytes = (double)mp * H->n * H->sz;
+        prof_end(s, a, b, abytes, (kind == HP_ATA ? 4.0 : 2.0) * mp * H->n * P->hp[0].l);
+        if (kind == HP_AX && (e = launch_sum(H->sum[p], SIDE_M, it, s)) != hipSuccess) return e;
+        if ((e = hipEventRecord(H->freed[slot], s)) != hipSuccess) return e;
+        H->used[slot] = true;
+    }
+    return hipSuccess;
+}
+
 static hipError_t run_sketch(const std::vector<Plan::Grp>& gs, bool trans, int iter,
                              hipStream_t s) {
     for (const auto& g : gs) {
@@ -728,11 +794,15 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
             // first sketch); Y <- Y R1^{-1} = A^T Q1; then the n-side
             // orthonormalisation as after the A^T Q1 pass.  (Every problem of
             // a fused plan has the same q.)
-            for (const auto& g : P->ata) {
-                hipEvent_t a, b;
-                prof_begin(s, &a, &b, 2);
-                E(launch_ata(g.prec, g.nt, g.aux, g.lds, g.g, it, s));
-                prof_end(s, a, b, g.bytes, g.flops);
+            if (P->hs) {
+                E(host_pass(P, HP_ATA, it, s));
+            } else {
+                for (const auto& g : P->ata) {
+                    hipEvent_t a, b;
+                    prof_begin(s, &a, &b, 2);
+                    E(launch_ata(g.prec, g.nt, g.aux, g.lds, g.g, it, s));
+                    prof_end(s, a, b, g.bytes, g.flops);
+                }
             }
             E(launch_sum(P->sumN.g, SIDE_F, it, s));
             E(launch_gram(P->gramN.g, SIDE_N, GSRC_XY, it, s));
@@ -743,8 +813,12 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
             continue;
         }
         // Y1 = A X, Q1 R1 = Y1 (CholeskyQR2)
-        E(run_sketch(P->skAX, false, it, s));
-        E(launch_sum(P->sumM.g, SIDE_M, it, s));
+        if (P->hs) {
+            E(host_pass(P, HP_AX, it, s));
+        } else {
+            E(run_sketch(P->skAX, false, it, s));
+            E(launch_sum(P->sumM.g, SIDE_M, it, s));
+        }
         E(launch_gram(P->gramM.g, SIDE_M, GSRC_Y, it, s));
         E(launch_gram_reduce(P->redM.g, SIDE_M, 0, it, s));
         E(launch_chol(P->small.g, CHOL_FIRST, P->lmax, it, s));
@@ -764,7 +838,8 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         // eq. (18) keeps the last step's input X before Q2 is overwritten
         if (P->has_approx && P->last[it]) E(launch_keep_x(P->keepx.g, it, s));
         // Y2 = A^T Q1, Q2 R2 = Y2 (CholeskyQR2); X <- Q2
-        E(run_sketch(P->skATX, true, it, s));
+        if (P->hs) E(host_pass(P, HP_ATX, it, s));
+        else E(run_sketch(P->skATX, true, it, s));
         E(launch_sum(P->sumN.g, SIDE_N, it, s));
         E(nside(it));
         if (fp8 && it < P->max_q) {
@@ -820,6 +895,7 @@ cor_status plan_run(Plan* P, hipStream_t s) {
 
 cor_status plan_capture(Plan* P, hipStream_t s) {
     if (!s) return fail(COR_E_INVAL, "graph capture needs a non-null stream");
+    if (P->hs) return fail(COR_E_INVAL, "a plan that streams A from host memory is not captured");
     if (P->gexec) {
         (void)hipGraphExecDestroy(P->gexec);
         (void)hipGraphDestroy(P->graph);
@@ -863,8 +939,22 @@ cor_status plan_info(Plan* P, cor_info* infos, hipStream_t s) {
     return COR_OK;
 }
 
+static void host_stream_free(HostStream* H) {
+    if (!H) return;
+    if (H->cs) (void)hipStreamSynchronize(H->cs);
+    for (int i = 0; i < HS_NB; i++) {
+        if (H->copied[i]) (void)hipEventDestroy(H->copied[i]);
+        if (H->freed[i]) (void)hipEventDestroy(H->freed[i]);
+    }
+    if (H->start) (void)hipEventDestroy(H->start);
+    if (H->cs) (void)hipStreamDestroy(H->cs);
+    if (H->mem) (void)hipFree(H->mem);
+    delete H;
+}
+
 void plan_destroy(Plan* P, hipStream_t s) {
     if (!P) return;
+    host_stream_free(P->hs);
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->mem && P->owned) {
@@ -990,6 +1080,165 @@ cor_status run_single(const cor_problem& p, const cor_opts* opts, cor_info* info
     return st;
 }
 
+// A host-streamed plan: panel descriptors and launch tables for a one-problem
+// plan whose A (q.A) is in host memory.  panel_rows <= 0: panels of about
+// 256 MiB.  The problem descriptor's n-side partial sums are redirected to
+// the panels' split slots.
+static cor_status host_setup(Plan* P, const cor_problem& q, int64_t panel_rows, int fused) {
+    HostStream* H = new HostStream();
+    P->hs = H;
+    Prob& W = P->hp[0];
+    const Layout& L = P->lay[0];
+    H->A = (const char*)q.A;
+    H->m = q.m;
+    H->n = q.n;
+    H->lda = q.lda;
+    H->sz = prec_size(q.prec);
+    H->nt = L.nt;
+    H->prec = q.prec;
+    const int64_t row_bytes = q.n * H->sz;
+    int64_t rows = panel_rows > 0 ? panel_rows : std::max<int64_t>(1, (256ll << 20) / row_bytes);
+    rows = roundup(std::max<int64_t>(rows, ATA_ROWS), ATA_ROWS);  // 16-byte aligned operand offsets
+    if (rows >= q.m) rows = q.m;
+    H->rows = rows;
+    H->npanel = (int)cdiv(q.m, rows);
+    const int np = H->npanel;
+    const int acc = q.prec == P_F64 ? 8 : 4;
+    const int bk = sketch_k_tile(q.prec);
+    const int tgt = sketch_block_target();
+    std::vector<int32_t> sax(np), satx(np), sf(np, 0);
+    std::vector<int64_t> kcax(np), kcatx(np), kcf(np, 0), off(np + 1, 0), offf(np + 1, 0);
+    int32_t sax_max = 0;
+    for (int p = 0; p < np; p++) {
+        const int64_t mp = std::min(rows, q.m - (int64_t)p * rows);
+        split_k(mp, q.n, bk,
+                sketch_rows_per_block(q.prec, L.nt, false) > 128 ? tgt / 2 : tgt, q.prec, L.nt,
+                false, &sax[p], &kcax[p]);
+        split_k(q.n, mp, bk,
+                sketch_rows_per_block(q.prec, L.nt, true) > 128 ? tgt / 2 : tgt, q.prec, L.nt,
+                true, &satx[p], &kcatx[p]);
+        if (fused) fused_splits(mp, &sf[p], &kcf[p]);
+        sax_max = std::max(sax_max, sax[p]);
+        off[p + 1] = off[p] + satx[p];
+        offf[p + 1] = offf[p] + sf[p];
+    }
+    // device memory: staging | M-side partials per slot | n-side partials |
+    // panel descriptors | launch tables
+    const size_t b_stage = roundup(rows * row_bytes, 256);
+    const size_t b_scm = roundup((int64_t)sax_max * rows * L.lp * acc, 256);
+    const size_t b_scn = roundup(std::max(off[np], offf[np]) * q.n * L.lp * acc, 256);
+    const size_t b_desc = roundup(sizeof(Prob) * 3 * np, 256);
+    const size_t b_tab = roundup(sizeof(int32_t) * 3 * 4 * np, 256);
+    const size_t total = HS_NB * (b_stage + b_scm) + b_scn + b_desc + b_tab;
+    if (hipMalloc(&H->mem, total) != hipSuccess) return fail(COR_E_NOMEM, "panel buffers");
+    char* base = (char*)H->mem;
+    for (int i = 0; i < HS_NB; i++) H->stage[i] = base + i * b_stage;
+    char* scm = base + HS_NB * b_stage;
+    char* scn = scm + HS_NB * b_scm;
+    Prob* d_desc = (Prob*)(scn + b_scn);
+    int32_t* d_tab = (int32_t*)((char*)d_desc + b_desc);
+    std::vector<Prob> hd(3 * np);
+    std::vector<int32_t> tab(3 * 4 * np);
+    for (int k = 0; k < 3; k++) H->sk[k].resize(np);
+    H->sum.resize(np);
+    const int avec = (row_bytes % 16) == 0 ? 1 : 0;  // staging rows start 16-byte aligned
+    for (int p = 0; p < np; p++) {
+        const int slot = p % HS_NB;
+        const int64_t r0 = (int64_t)p * rows, mp = std::min(rows, q.m - r0);
+        Prob& ax = hd[3 * p + HP_AX];
+        ax = W;
+        ax.A = H->stage[slot];
+        ax.m = mp;
+        ax.lda = q.n;
+        ax.avec = avec;
+        ax.ypart = scm + slot * b_scm;
+        ax.s_ax = sax[p];
+        ax.kc_ax = kcax[p];
+        ax.Y = W.Y + r0 * L.l;
+        Prob& at = hd[3 * p + HP_ATX];
+        at = W;
+        at.A = H->stage[slot];
+        at.m = mp;
+        at.lda = q.n;
+        at.avec = avec;
+        at.qop = (char*)W.qop + r0 * H->sz;
+        at.ypart = scn + off[p] * q.n * L.lp * acc;
+        at.s_atx = satx[p];
+        at.kc_atx = kcatx[p];
+        Prob& af = hd[3 * p + HP_ATA];
+        af = at;
+        af.ypart = scn + offf[p] * q.n * L.lp * acc;
+        af.s_f = sf[p];
+        af.kc_f = kcf[p];
+        // tables: [pidx, toff0, toff1] per (panel, kind) and for the panel's A X sum
+        const int64_t blocks[4] = {
+            cdiv(mp, sketch_rows_per_block(q.prec, L.nt, false)) * sax[p],
+            cdiv(q.n, sketch_rows_per_block(q.prec, L.nt, true)) * satx[p], (int64_t)sf[p],
+            cdiv(mp * L.lp / 4, 256)};
+        for (int k = 0; k < 4; k++) {
+            int32_t* t = tab.data() + 3 * (4 * p + k);
+            t[0] = 3 * p + (k == 3 ? HP_AX : k);
+            t[1] = 0;
+            t[2] = (int32_t)blocks[k];
+            LaunchGroup g;
+            g.probs = d_desc;
+            g.pidx = d_tab + 3 * (4 * p + k);
+            g.toff = g.pidx + 1;
+            g.count = 1;
+            g.blocks = (int32_t)blocks[k];
+            if (k < 3) H->sk[k][p] = g;
+            else H->sum[p] = g;
+        }
+    }
+    // the problem's n-side sums add the panels' split slots
+    W.ypart = scn;
+    W.s_atx = (int32_t)off[np];
+    W.s_f = (int32_t)offf[np];
+    hipError_t e = hipMemcpy(d_desc, hd.data(), sizeof(Prob) * hd.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(d_tab, tab.data(), sizeof(int32_t) * tab.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(P->d_probs, &W, sizeof(Prob), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreate(&H->cs);
+    for (int i = 0; i < HS_NB && e == hipSuccess; i++) {
+        e = hipEventCreateWithFlags(&H->copied[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&H->freed[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&H->start, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "panel set-up");
+    return COR_OK;
+}
+
+cor_status run_host(const cor_problem& p, const cor_opts* opts, int64_t panel_rows,
+                    cor_info* info, hipStream_t s) {
+    cor_status st = validate(p);
+    if (st != COR_OK) return st;
+    if (opts && (opts->report || opts->compress == COR_M_EXPLICIT || opts->orient == COR_ULV))
+        return fail(COR_E_INVAL, "A in host memory: no report, no COR_M_EXPLICIT, no COR_ULV");
+    Plan* P = nullptr;
+    st = plan_create(&p, 1, opts, &P, nullptr, false);
+    if (st != COR_OK) return st;
+    st = host_setup(P, p, panel_rows, opts && opts->fused_power ? 1 : 0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == COR_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = fail(COR_E_DEVICE, "timing events");
+    if (st == COR_OK) {
+        (void)hipEventRecord(e0, s);
+        st = plan_run(P, s);
+        (void)hipEventRecord(e1, s);
+    }
+    const cor_status st_info = plan_info(P, info, s);
+    if (st == COR_OK) st = st_info;
+    if (st == COR_OK && info) {
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        info->device_ms = ms;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    plan_destroy(P, nullptr);
+    return st;
+}
+
 void release_all() {
     std::lock_guard<std::mutex> lk(g_cache.mu);
     std::vector<Cache::Item> keep;
@@ -1027,6 +1276,12 @@ cor_status cor_utv_ex(const cor_problem* prob, const cor_opts* opts, cor_info* i
                       void* stream) {
     if (!prob) return fail(COR_E_INVAL, "null problem");
     return run_single(*prob, opts, info, (hipStream_t)stream);
+}
+
+cor_status cor_utv_host(const cor_problem* prob, const cor_opts* opts, int64_t panel_rows,
+                        cor_info* info, void* stream) {
+    if (!prob) return fail(COR_E_INVAL, "null problem");
+    return run_host(*prob, opts, panel_rows, info, (hipStream_t)stream);
 }
 
 cor_status cor_utv_batched(const cor_problem* probs, int32_t count, const cor_opts* opts,
