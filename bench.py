@@ -274,6 +274,11 @@ def bench_served(args, w, cu, torch, np):
     big = [(e, p) for e, p in zip(errs, plain_err) if p >= floor]
     ratio = max((e / p for e, p in big), default=None)
     absdiff = max(abs(e - p) for e, p in zip(errs, plain_err))
+    worst = sorted(((e / p, i) for i, (e, p) in enumerate(zip(errs, plain_err)) if p >= floor),
+                   reverse=True)[:3]
+    worst = [dict(kind=reqs[i]["kind"], m=reqs[i]["m"], n=reqs[i]["n"], k=reqs[i]["k"],
+                  q=reqs[i]["q"], err_served=errs[i], err_plain=plain_err[i], ratio=rt)
+             for rt, i in worst]
     return {
         "metric": "CoR-UTV decompositions/s (roofline of the passes over A; p50/p99 latency)",
         "value": round(sat["decomps_per_s"], 3),
@@ -289,8 +294,9 @@ def bench_served(args, w, cu, torch, np):
                        "p50_ms": float(np.percentile(plain_lat, 50)),
                        "p99_ms": float(np.percentile(plain_lat, 99))},
         "served_over_plain": sat["decomps_per_s"] / plain_rate,
-        "accuracy": {"max_err_l_served_over_plain": ratio, "requests_compared": len(big),
-                     "max_abs_err_l_difference": absdiff, "bf16_floor": floor},
+        "accuracy": {"max_err_l_served_over_plain": ratio, "worst_requests": worst,
+                     "requests_compared": len(big), "max_abs_err_l_difference": absdiff,
+                     "bf16_floor": floor},
         "roofline": None,
         "cpu_baseline": None,
     }

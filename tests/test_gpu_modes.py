@@ -143,6 +143,19 @@ def test_quantised_passes_widest_l(cu, dev, orc, fmt, l):
     assert r["fp64"] <= 1.05 and r["fp64_k"] <= 1.05
 
 
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_quantised_tall_many_splits(cu, dev, orc, fmt):
+    """A tall matrix (30000 x 1500): the transposed pass has few output row
+    blocks and takes up to 64 K splits; the result matches the stored-format
+    oracle as the few-split passes do."""
+    m, n, k, p, q = 30000, 1500, 20, 8, 1
+    low, s = I.rpca_matrix(m, n, 5, 0.05, seed=17)
+    a = low + s + 1e-3 * np.random.default_rng(18).standard_normal((m, n))
+    om = I.gaussian_omega(n, k + p, 19)
+    r = _quantised_case(cu, dev, orc, a, k, p, q, fmt, om, "tall")
+    assert abs(r["stored"] - 1.0) <= 0.01
+
+
 def test_f32_l220_matches_oracle(cu, dev, orc):
     """FP32 passes at l = 220 (global-memory Cholesky and QRCP paths)."""
     import torch
