@@ -303,7 +303,7 @@ def bench_served(args, w, cu, torch, np):
 
 
 def timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=None, profile_steps=20,
-               opts=None, profile_kind=1):
+               opts=None, profile_kind=1, tune=False):
     """Plan one decomposition of the device matrix A, capture it into a HIP
     graph, replay `warmup` untimed and `steps` timed decompositions, then time
     the passes over A of eager runs of the same plan with HIP events on the
@@ -316,6 +316,11 @@ def timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=None, profile_ste
     V = torch.empty((n, l), dtype=torch.float64, device=dev)
     perm = torch.empty((l,), dtype=torch.int32, device=dev)
     prob = cu.make_problem(A, k, p, q, seed=seed, U=U, T=T, V=V, perm=perm, colscale=colscale)
+    splits = None
+    if tune:  # the split tuner measures the passes' candidates on this matrix
+        st, s_ax, s_atx = cu.cor_tune(prob, 3)
+        cu.check(st, "cor_tune")
+        splits = {"s_ax": s_ax, "s_atx": s_atx, "tuned": True}
     stream = torch.cuda.Stream()
     opts = opts if opts is not None else cu.cor_opts(0, 0)
     st, plan = cu.cor_plan_create([prob], opts)
@@ -357,7 +362,7 @@ def timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=None, profile_ste
         cu.cor_plan_destroy(plan)
     step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     return dict(U=U, T=T, V=V, perm=perm, elapsed=t1 - t0, step_ms=step_ms, prof=prof,
-                graph=graph, flags=info[0].flags)
+                graph=graph, flags=info[0].flags, splits=splits)
 
 
 def accuracy(torch, a64, U, T, V, k):
@@ -399,12 +404,16 @@ def pass_roofline(prec, l, prof, kernel="k_sketch (passes over A)", flops_per_el
             "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes}
 
 
-def traffic_of(name):
+def traffic_of(name, splits=None):
+    """Calibrated HBM bytes per pass launch from the committed counters, if
+    they were taken on the current k_sketch.hip and the same split counts."""
     tpath = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if os.path.exists(tpath):
         with open(tpath) as f:
             tr = json.load(f)
-        if tr.get("source_hash") == source_hash():
+        same = splits is None or (tr.get("s_ax"), tr.get("s_atx")) == (splits["s_ax"],
+                                                                         splits["s_atx"])
+        if tr.get("source_hash") == source_hash() and same:
             return tr.get("bytes_per_launch")
     return None
 
@@ -494,6 +503,13 @@ def bench_c3(args, w, cu, torch, np):
     k, p, q = gold["k"], gold["p"], gold["q"]
     l = k + p
     seed = gold["omega_seed"]
+    # split tuning: from --tune-cache when it has this shape, else measured
+    # here (and written to --tune-cache)
+    loaded = {}
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        cu.check(cu.cor_tune_load(args.tune_cache), "cor_tune_load")
+        with open(args.tune_cache) as f:
+            loaded = {(e["m"], e["n"], e["l"], e["prec"]): e for e in json.load(f)["entries"]}
     modes = {}
     for fmt in args.formats.split(","):
         colscale = None
@@ -512,7 +528,12 @@ def bench_c3(args, w, cu, torch, np):
         if fmt != "f32":
             del A32
         torch.cuda.synchronize()
-        r = timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=colscale)
+        ent = loaded.get((A.shape[0], A.shape[1], l, cu.PREC[fmt]))
+        r = timed_plan(cu, torch, np, A, k, p, q, seed, args, colscale=colscale,
+                       tune=not args.no_tune and ent is None)
+        if ent is not None:
+            r["splits"] = {"s_ax": ent["s_ax"], "s_atx": ent["s_atx"], "tuned": True,
+                           "from": "tune cache"}
         del A
         acc = accuracy(torch, a64, r["U"], r["T"], r["V"], k)
         ratio = acc["err_l"] / gold["err_l"]
@@ -536,6 +557,7 @@ def bench_c3(args, w, cu, torch, np):
             "orth_u": acc["orth_u"], "orth_v": acc["orth_v"],
             "rule": C3_RULE[fmt], "at_fixed_error": bool(ok),
             "pass_roofline": pass_roofline(fmt, l, r["prof"]),
+            "splits": r["splits"],
         }
         if fmt in gq:
             res["err_l_over_stored_format_oracle"] = acc["err_l"] / gq[fmt]["err_l"]
@@ -549,10 +571,12 @@ def bench_c3(args, w, cu, torch, np):
         print(f"# c3 {fmt}: {res['decomps_per_s']:.1f} decomps/s, eps/eps_oracle {ratio:.5f}, "
               f"pass {res['pass_roofline']['frac']:.3f} of {res['pass_roofline']['bound']} peak",
               file=sys.stderr, flush=True)
+    if args.tune_cache and not os.path.exists(args.tune_cache):
+        cu.check(cu.cor_tune_save(args.tune_cache), "cor_tune_save")
     fmt0, r0 = first
     main_mode = modes[fmt0]
     roofline = dict(main_mode["pass_roofline"])
-    roofline["traffic"] = traffic_of(f"c3{fmt0}")
+    roofline["traffic"] = traffic_of(f"c3{fmt0}", r0["splits"])
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline_oracle(a64, k, p, q, seed)
@@ -568,6 +592,7 @@ def bench_c3(args, w, cu, torch, np):
         "dtype": fmt0, "data": "synthetic",
         "config": {"workload": f"c3 {fmt0.upper()}: " + w["desc"], "m": a64.shape[0],
                    "n": a64.shape[1], "k": k, "l": l, "q": q, "graph": r0["graph"],
+                   "splits": r0["splits"],
                    "omega_seed": seed},
         "latency_ms": main_mode["latency_ms"],
         "accuracy": {"err_l": main_mode["err_l"], "err_l_oracle": gold["err_l"],
@@ -807,6 +832,14 @@ def main():
                     help="c3: load the 20000x10000 matrix from this .npy file if it exists, "
                          "else build it and save it there")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune-cache", metavar="JSON",
+                    default=os.path.join(ROOT, "paper_1810_07323_amd", "tune_mi355x.json"),
+                    help="c3: split table to load (shapes it holds are not tuned again; "
+                         "default: the table measured on MI355X for this workload); written "
+                         "after the run when it does not exist")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="c3: keep the rule's split counts instead of running the split tuner "
+                         "on the matrix before timing")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "HBM byte counters against a kernel of known traffic)")

@@ -308,6 +308,29 @@ cor_status cor_server_stats_get(cor_server* server, cor_server_stats* stats);
 cor_status cor_server_destroy(cor_server* server);
 
 /* ---------------------------------------------------------------------------
+ * Split tuner with a JSON cache.  The K-split counts of the two passes over A
+ * follow a fixed rule of the shape (about 512 blocks per launch).  cor_tune
+ * measures, on the caller's matrix (prob: URV, default options), the pass
+ * kernels' mean time over `reps` launches for candidate split counts (A X
+ * first, then A^T X) and stores the fastest pair in the library's tuning
+ * table under (m, n, l, prec); every plan created afterwards for that shape
+ * uses them (cached plans are dropped).  s_ax, s_atx (optional) receive the
+ * chosen counts.  cor_tune_save writes the table as JSON:
+ *   {"version": 1, "entries": [{"m": .., "n": .., "l": .., "prec": ..,
+ *    "s_ax": .., "s_atx": .., "us_ax": .., "us_atx": ..}, ...]}
+ * cor_tune_load merges such a file into the table (COR_E_INVAL if it is
+ * unreadable or an entry is out of range: 1 <= s <= 64); the file named by
+ * the environment variable COR_TUNE_FILE is loaded before the first plan.
+ * A shape's result depends only on the shape and the table, not on what it
+ * is batched with.
+ * ------------------------------------------------------------------------- */
+cor_status cor_tune(const cor_problem* prob, int32_t reps, int32_t* s_ax, int32_t* s_atx,
+                    void* stream);
+cor_status cor_tune_save(const char* path);
+cor_status cor_tune_load(const char* path);
+cor_status cor_tune_clear(void);
+
+/* ---------------------------------------------------------------------------
  * Helpers
  * ------------------------------------------------------------------------- */
 /* Device workspace of one decomposition of an m x n matrix with l = k + p

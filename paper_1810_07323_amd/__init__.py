@@ -82,6 +82,11 @@ _SIGS = {
     "cor_utv_ex": (C.c_int, [C.POINTER(cor_problem), C.POINTER(cor_opts), C.POINTER(cor_info), _P]),
     "cor_utv_ex_noalloc": (C.c_int, [C.POINTER(cor_problem), C.POINTER(cor_opts),
                                      C.POINTER(cor_info), _P]),
+    "cor_tune": (C.c_int, [C.POINTER(cor_problem), C.c_int32, C.POINTER(C.c_int32),
+                           C.POINTER(C.c_int32), _P]),
+    "cor_tune_save": (C.c_int, [C.c_char_p]),
+    "cor_tune_load": (C.c_int, [C.c_char_p]),
+    "cor_tune_clear": (C.c_int, []),
     "cor_utv_host": (C.c_int, [C.POINTER(cor_problem), C.POINTER(cor_opts), C.c_int64,
                                C.POINTER(cor_info), _P]),
     "cor_utv_batched": (C.c_int, [C.POINTER(cor_problem), C.c_int32, C.POINTER(cor_opts),
@@ -209,6 +214,25 @@ def cor_utv_ex_noalloc(problem, opts=None, stream=None):
     st = lib().cor_utv_ex_noalloc(C.byref(problem), C.byref(opts) if opts is not None else None,
                                   C.byref(info), stream_handle(stream))
     return st, info
+
+
+def cor_tune(problem, reps=5, stream=None):
+    """Returns (status, s_ax, s_atx)."""
+    a, b = C.c_int32(0), C.c_int32(0)
+    st = lib().cor_tune(C.byref(problem), reps, C.byref(a), C.byref(b), stream_handle(stream))
+    return st, a.value, b.value
+
+
+def cor_tune_save(path):
+    return lib().cor_tune_save(os.fsencode(path))
+
+
+def cor_tune_load(path):
+    return lib().cor_tune_load(os.fsencode(path))
+
+
+def cor_tune_clear():
+    return lib().cor_tune_clear()
 
 
 def cor_utv_host(problem, opts=None, panel_rows=0, stream=None):

@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/cor_utv.h"
@@ -171,6 +172,65 @@ static int sketch_block_target() {
 // request: rows of 16-byte multiples.
 static int64_t at_ld(int64_t n, int prec) { return roundup(n, 16); }
 
+// ---------------------------------------------------------------------------
+// Split tuning table: (m, n, l, prec) of the matrix the passes read -> the K
+// splits of A X and A^T X.  Filled by cor_tune (measured on the caller's
+// matrix) or from a JSON file (cor_tune_load, or the file named by
+// COR_TUNE_FILE, read at the first plan); a plan for a tuned shape uses its
+// splits, every other shape the fixed rule of split_k.  A shape's layout
+// still depends on nothing but the shape and the table, so a problem gives
+// the same result alone, batched or served.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int64_t m, n;
+    int32_t l, prec;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(m, n, l, prec) < std::tie(o.m, o.n, o.l, o.prec);
+    }
+};
+struct TuneVal {
+    int32_t s_ax, s_atx;
+    double us_ax, us_atx;
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneVal> g_tune;
+static bool g_tune_env = false;
+static thread_local int32_t g_force_ax = 0, g_force_atx = 0;  // the tuner's candidates
+cor_status tune_load_file(const char* path);
+
+static bool tuned_splits(int64_t m, int64_t n, int32_t l, int prec, int32_t* s_ax,
+                         int32_t* s_atx) {
+    if (g_force_ax > 0 || g_force_atx > 0) {
+        *s_ax = g_force_ax;
+        *s_atx = g_force_atx;
+        return true;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_env) {
+        g_tune_env = true;
+        const char* f = getenv("COR_TUNE_FILE");
+        if (f && *f) {
+            g_tune_mu.unlock();
+            (void)tune_load_file(f);
+            g_tune_mu.lock();
+        }
+    }
+    auto it = g_tune.find(TuneKey{m, n, l, prec});
+    if (it == g_tune.end()) return false;
+    *s_ax = it->second.s_ax;
+    *s_atx = it->second.s_atx;
+    return true;
+}
+
+// s splits of K (> 0) in whole K tiles; 0 keeps the rule's choice.
+static void apply_splits(int64_t K, int bk, int32_t s, int32_t* sp, int64_t* kc) {
+    if (s <= 0) return;
+    s = std::min<int32_t>(s, 64);
+    const int64_t c = roundup(cdiv(K, s), bk);
+    *kc = c;
+    *sp = (int32_t)cdiv(K, c);
+}
+
 // Row splits of the fused power step: one block per CU (the kernel holds
 // its n x lp partial sum in LDS), whole chunks of ATA_ROWS rows each.
 static void fused_splits(int64_t m, int32_t* s, int64_t* kc) {
@@ -196,6 +256,13 @@ static Layout make_layout(int64_t m, int64_t n, int32_t l, int prec, int sketch_
     split_k(n, m, bk,
             sketch_rows_per_block(prec, L.nt, true) > 128 ? sketch_target / 2 : sketch_target,
             prec, L.nt, true, &L.s_atx, &L.kc_atx);
+    {
+        int32_t ta = 0, tt = 0;
+        if (tuned_splits(m, n, l, prec, &ta, &tt)) {
+            apply_splits(n, bk, ta, &L.s_ax, &L.kc_ax);
+            apply_splits(m, bk, tt, &L.s_atx, &L.kc_atx);
+        }
+    }
     gram_chunks(m, L.lp, gram_target, &L.rb_m, &L.gb_m);
     gram_chunks(n, L.lp, gram_target, &L.rb_n, &L.gb_n);
     L.s_f = 0;
@@ -1249,6 +1316,162 @@ void release_all() {
     g_cache.items.swap(keep);
 }
 
+// ---------------------------------------------------------------------------
+// The split tuner: for the problem's shape (URV, default options), the mean
+// time of each pass kernel over `reps` launches for candidate split counts,
+// A X first (A^T X at the rule's choice), then A^T X with the best A X; the
+// fastest pair goes into the table.  Candidates keep at least one K tile per
+// split and at most 4096 blocks per launch.
+// ---------------------------------------------------------------------------
+static cor_status tune_measure(const cor_problem& p, int32_t s_ax, int32_t s_atx, int reps,
+                               hipStream_t s, double* us_ax, double* us_atx, int32_t* got_ax,
+                               int32_t* got_atx) {
+    g_force_ax = s_ax;
+    g_force_atx = s_atx;
+    Plan* P = nullptr;
+    cor_status st = plan_create(&p, 1, nullptr, &P, nullptr, false);
+    g_force_ax = g_force_atx = 0;
+    if (st != COR_OK) return st;
+    *got_ax = P->lay[0].s_ax;
+    *got_atx = P->lay[0].s_atx;
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    hipError_t he = hipSuccess;
+    for (int i = 0; i < 3 && he == hipSuccess; i++) he = hipEventCreate(&e[i]);
+    if (he == hipSuccess) st = plan_run(P, s);  // every operand initialised
+    if (he == hipSuccess && st == COR_OK) {
+        he = hipEventRecord(e[0], s);
+        for (int r = 0; r < reps && he == hipSuccess; r++) he = run_sketch(P->skAX, false, 0, s);
+        if (he == hipSuccess) he = hipEventRecord(e[1], s);
+        for (int r = 0; r < reps && he == hipSuccess; r++) he = run_sketch(P->skATX, true, 0, s);
+        if (he == hipSuccess) he = hipEventRecord(e[2], s);
+        if (he == hipSuccess) he = hipEventSynchronize(e[2]);
+        float a = 0.0f, b = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&a, e[0], e[1]);
+        if (he == hipSuccess) he = hipEventElapsedTime(&b, e[1], e[2]);
+        *us_ax = 1e3 * a / reps;
+        *us_atx = 1e3 * b / reps;
+    }
+    for (int i = 0; i < 3; i++)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    (void)hipStreamSynchronize(s);
+    plan_destroy(P, nullptr);
+    if (he != hipSuccess) return hip_fail(he, "tuning runs");
+    return st;
+}
+
+static cor_status tune_problem(const cor_problem& p, int reps, hipStream_t s, int32_t* s_ax,
+                               int32_t* s_atx) {
+    cor_status st = validate(p);
+    if (st != COR_OK) return st;
+    reps = std::max(1, std::min(reps, 100));
+    const int l = p.k + p.p, lp = (int)roundup(l, 16), nt = lp / 16;
+    const int bk = sketch_k_tile(p.prec);
+    const int64_t nrb_ax = cdiv(p.m, sketch_rows_per_block(p.prec, nt, false));
+    const int64_t nrb_atx = cdiv(p.n, sketch_rows_per_block(p.prec, nt, true));
+    const int cand[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64};
+    auto list = [&](int64_t K, int64_t nrb) {
+        std::vector<int32_t> out;
+        for (int c : cand) {
+            int32_t sp = 0;
+            int64_t kc = 0;
+            apply_splits(K, bk, c, &sp, &kc);
+            if (nrb * sp > 4096) break;
+            if (std::find(out.begin(), out.end(), sp) == out.end()) out.push_back(sp);
+        }
+        return out;
+    };
+    double best_ax = 1e30, best_atx = 1e30, u_ax = 0, u_atx = 0;
+    int32_t b_ax = 0, b_atx = 0, g_ax = 0, g_atx = 0;
+    for (int32_t c : list(p.n, nrb_ax)) {
+        st = tune_measure(p, c, 0, reps, s, &u_ax, &u_atx, &g_ax, &g_atx);
+        if (st != COR_OK) return st;
+        if (u_ax < best_ax) { best_ax = u_ax; b_ax = g_ax; }
+    }
+    for (int32_t c : list(p.m, nrb_atx)) {
+        st = tune_measure(p, b_ax, c, reps, s, &u_ax, &u_atx, &g_ax, &g_atx);
+        if (st != COR_OK) return st;
+        if (u_atx < best_atx) { best_atx = u_atx; b_atx = g_atx; }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[TuneKey{p.m, p.n, l, p.prec}] = TuneVal{b_ax, b_atx, best_ax, best_atx};
+    }
+    release_all();  // cached plans of this shape carry the old splits
+    if (s_ax) *s_ax = b_ax;
+    if (s_atx) *s_atx = b_atx;
+    return COR_OK;
+}
+
+// JSON: {"version": 1, "entries": [{"m": .., "n": .., "l": .., "prec": ..,
+// "s_ax": .., "s_atx": .., "us_ax": .., "us_atx": ..}, ...]}
+static cor_status tune_save_file(const char* path) {
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(COR_E_INVAL, std::string("cannot write ") + path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    fprintf(f, "{\"version\": 1, \"entries\": [");
+    bool first = true;
+    for (const auto& kv : g_tune) {
+        fprintf(f, "%s\n {\"m\": %lld, \"n\": %lld, \"l\": %d, \"prec\": %d, \"s_ax\": %d, "
+                   "\"s_atx\": %d, \"us_ax\": %.3f, \"us_atx\": %.3f}",
+                first ? "" : ",", (long long)kv.first.m, (long long)kv.first.n, kv.first.l,
+                kv.first.prec, kv.second.s_ax, kv.second.s_atx, kv.second.us_ax,
+                kv.second.us_atx);
+        first = false;
+    }
+    fprintf(f, "\n]}\n");
+    const bool ok = fclose(f) == 0;
+    return ok ? COR_OK : fail(COR_E_INVAL, std::string("cannot write ") + path);
+}
+
+static bool json_num(const std::string& obj, const char* key, double* v) {
+    const std::string k = std::string("\"") + key + "\"";
+    size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    p = obj.find(':', p + k.size());
+    if (p == std::string::npos) return false;
+    char* end = nullptr;
+    *v = strtod(obj.c_str() + p + 1, &end);
+    return end != obj.c_str() + p + 1;
+}
+
+cor_status tune_load_file(const char* path) {
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(COR_E_INVAL, std::string("cannot read ") + path);
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
+    fclose(f);
+    const size_t arr = txt.find("\"entries\"");
+    if (arr == std::string::npos) return fail(COR_E_INVAL, "no entries in the tuning file");
+    std::vector<std::pair<TuneKey, TuneVal>> add;
+    size_t pos = txt.find('[', arr);
+    while (pos != std::string::npos) {
+        const size_t a = txt.find('{', pos), b = txt.find('}', a == std::string::npos ? pos : a);
+        if (a == std::string::npos || b == std::string::npos) break;
+        const std::string obj = txt.substr(a, b - a + 1);
+        double m, n, l, pr, sa, st, ua = 0, ut = 0;
+        if (!json_num(obj, "m", &m) || !json_num(obj, "n", &n) || !json_num(obj, "l", &l) ||
+            !json_num(obj, "prec", &pr) || !json_num(obj, "s_ax", &sa) ||
+            !json_num(obj, "s_atx", &st))
+            return fail(COR_E_INVAL, "malformed tuning entry");
+        (void)json_num(obj, "us_ax", &ua);
+        (void)json_num(obj, "us_atx", &ut);
+        if (sa < 1 || sa > 64 || st < 1 || st > 64 || m < 1 || n < 1 || l < 2 || l > LMAX ||
+            !valid_prec((int)pr))
+            return fail(COR_E_INVAL, "tuning entry out of range");
+        add.push_back({TuneKey{(int64_t)m, (int64_t)n, (int32_t)l, (int32_t)pr},
+                       TuneVal{(int32_t)sa, (int32_t)st, ua, ut}});
+        pos = b + 1;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (auto& kv : add) g_tune[kv.first] = kv.second;
+    }
+    release_all();
+    return COR_OK;
+}
+
 }  // namespace cor
 
 // ===========================================================================
@@ -1276,6 +1499,31 @@ cor_status cor_utv_ex(const cor_problem* prob, const cor_opts* opts, cor_info* i
                       void* stream) {
     if (!prob) return fail(COR_E_INVAL, "null problem");
     return run_single(*prob, opts, info, (hipStream_t)stream);
+}
+
+cor_status cor_tune(const cor_problem* prob, int32_t reps, int32_t* s_ax, int32_t* s_atx,
+                    void* stream) {
+    if (!prob) return fail(COR_E_INVAL, "null problem");
+    return tune_problem(*prob, reps, (hipStream_t)stream, s_ax, s_atx);
+}
+
+cor_status cor_tune_save(const char* path) {
+    if (!path) return fail(COR_E_INVAL, "null path");
+    return tune_save_file(path);
+}
+
+cor_status cor_tune_load(const char* path) {
+    if (!path) return fail(COR_E_INVAL, "null path");
+    return tune_load_file(path);
+}
+
+cor_status cor_tune_clear(void) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune.clear();
+    }
+    release_all();
+    return COR_OK;
 }
 
 cor_status cor_utv_host(const cor_problem* prob, const cor_opts* opts, int64_t panel_rows,
