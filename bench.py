@@ -219,23 +219,34 @@ def bench_served(args, w, cu, torch, np):
                 torch.empty((l,), dtype=torch.int32, device=dev))
 
     opts = cu.cor_opts(1, 0)  # report: each result carries its error
-    # plain path: FP32, one request after another (warm the code paths first)
-    for r in reqs[:2]:
-        st, _ = cu.cor_utv_ex(cu.make_problem(mat(r), r["k"], r["p"], r["q"], r["seed"],
-                                              *outputs(r)), opts)
-        cu.check(st, "plain warmup")
+    # plain path: FP32, one request after another, each from a plan created
+    # (workspace allocated, descriptors uploaded) before the timed loop, so the
+    # comparison measures batching rather than allocation
+    plans = []
+    for r in reqs:
+        o = outputs(r)
+        st, plan = cu.cor_plan_create(
+            [cu.make_problem(mat(r), r["k"], r["p"], r["q"], r["seed"], *o)], opts)
+        cu.check(st, "plain plan")
+        plans.append((plan, o))
+    for plan, _ in plans[:2]:  # warm the code paths
+        cu.check(cu.cor_plan_run(plan), "plain warmup")
+        cu.check(cu.cor_plan_info(plan, 1)[0], "plain warmup")
     torch.cuda.synchronize()
     plain_err, plain_lat = [], []
     t0 = time.perf_counter()
-    for r in reqs:
+    for plan, _ in plans:
         ts = time.perf_counter()
-        st, info = cu.cor_utv_ex(cu.make_problem(mat(r), r["k"], r["p"], r["q"], r["seed"],
-                                                 *outputs(r)), opts)
-        cu.check(st, "plain")
+        cu.check(cu.cor_plan_run(plan), "plain")
+        st, infos = cu.cor_plan_info(plan, 1)  # waits for the request
+        cu.check(st, "plain info")
         plain_lat.append((time.perf_counter() - ts) * 1e3)
-        plain_err.append(info.err_l)
+        plain_err.append(infos[0].err_l)
     torch.cuda.synchronize()
     plain_rate = len(reqs) / (time.perf_counter() - t0)
+    for plan, _ in plans:
+        cu.cor_plan_destroy(plan)
+    del plans
 
     def serve(rate):
         st, srv = cu.cor_server_create(hbm_budget=0, max_slots=0, convert_f32_to=cu.COR_BF16)

@@ -396,6 +396,13 @@ def test_server_mix_equals_single(cu, dev, orc):
         elif fmt == "bf16":
             A = A.to(torch.bfloat16).contiguous()
         reqs.append(dict(m=m, n=n, k=k, p=p, q=q, A=A, fmt=fmt, a=a, seed=777 + i))
+    # a robust-PCA-shaped request (tall FP32, rank 5 plus outliers), converted
+    # to BF16 by the server like the other FP32 ones
+    low, sp = I.rpca_matrix(76800, 2000, 5, 0.05, seed=5060)
+    a = low + sp
+    reqs.append(dict(m=76800, n=2000, k=16, p=8, q=1, fmt="f32", a=a, seed=790,
+                     A=torch.from_numpy(a.astype(np.float32)).to(dev)))
+    del low, sp
     # room for about three requests at a time: the rest queue
     budget = 3 * max(cu.cor_workspace_bytes(r["m"], r["n"], r["k"] + r["p"], cu.COR_F64)
                      + r["m"] * r["n"] * 2 for r in reqs)
