@@ -46,13 +46,22 @@ template <> struct SkCfg<P_FP8> { static constexpr int BK = 128, VEC = 16; };
 // halves the X tile traffic per byte of A (the X tile is as large as the A
 // tile at l = 220).  Eight waves mean two per SIMD and half the register file
 // each: shapes whose accumulators do not fit that (FP64 beyond 8 column
-// tiles, FP32 beyond 12, FP8 beyond 9, FP8 A X) keep 4 waves.
+// tiles, FP32 beyond 12, FP8 beyond 9, FP8 A X) keep 4 waves -- except FP64
+// beyond 8 column tiles and FP32 where it would have one wave per SIMD (A X
+// beyond 9 column tiles, A^T X beyond 12), which take 8 waves of 128-row
+// blocks in 4 row groups x 2 column groups: a wave's accumulators (2 row
+// tiles x half the column tiles) then leave room for two waves per SIMD (with
+// one wave of 2 x NT tiles per SIMD the MFMA pipe waits on every tile's loads).
+template <int PREC, bool TRANS> __host__ __device__ constexpr bool sk_split_cols(int nt) {
+    return (PREC == P_F64 && nt >= 9) || (PREC == P_F32 && nt >= (TRANS ? 13 : 10));
+}
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_waves() {
     constexpr int ntmax = PREC == P_F64 ? 8 : PREC == P_F32 ? 12 : PREC == P_FP8 ? 9 : NTMAX;
     // BF16 with at most 7 column tiles (l <= 112): 4 waves, whose smaller LDS
     // tiles let two or three blocks share a CU, so more A tiles are in flight where
     // the MFMA work per tile is too short to hide one tile's load.
     if (PREC == P_BF16 && NT <= 7) return 4;
+    if (sk_split_cols<PREC, TRANS>(NT)) return 8;
     return (NT <= ntmax && (TRANS || PREC == P_BF16)) ? 8 : 4;
 }
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_threads() { return 64 * sk_waves<PREC, NT, TRANS>(); }
@@ -63,12 +72,19 @@ template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_thr
 // reads 4 A and NT/2 X fragments from LDS per K step instead of 2 and NT,
 // about a third less LDS traffic per MFMA.
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_wc() {
-    return (PREC == P_BF16 && NT >= 8 && NT <= 14 && sk_waves<PREC, NT, TRANS>() == 8) ? 2 : 1;
+    return ((PREC == P_BF16 && NT >= 8 && NT <= 14 && sk_waves<PREC, NT, TRANS>() == 8) ||
+            sk_split_cols<PREC, TRANS>(NT))
+               ? 2
+               : 1;
 }
+// Row tiles per wave: 2 WC for BF16 (64 rows per wave with two column groups),
+// 2 for the FP32 / FP64 column split.
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_rt() {
-    return 2 * sk_wc<PREC, NT, TRANS>();
+    return PREC == P_BF16 ? 2 * sk_wc<PREC, NT, TRANS>() : 2;
 }
-template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_bm() { return 32 * sk_waves<PREC, NT, TRANS>(); }
+template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_bm() {
+    return 16 * sk_rt<PREC, NT, TRANS>() * (sk_waves<PREC, NT, TRANS>() / sk_wc<PREC, NT, TRANS>());
+}
 constexpr int ROWB = 144;                     // LDS bytes per 128-byte K row (+16 pad)
 
 template <int PREC, int NT, bool TRANS>
@@ -383,21 +399,24 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                             av[r][e] = *reinterpret_cast<const T*>(As + (kk + e) * AROWB + orow * SZ);
                     }
                 }
-                // All NT operand vectors first, then MFMAs ordered so that the
-                // RT*NT accumulators are visited round-robin: consecutive MFMAs
-                // never update the same accumulator.
-                T bv[NT][VEC];
+                // All of the wave's column tiles' operand vectors first, then
+                // MFMAs ordered so that the RT*NTW accumulators are visited
+                // round-robin: consecutive MFMAs never update the same
+                // accumulator.  (A second column group past NT repeats the
+                // last tile; its accumulators are never stored.)
+                T bv[NTW][VEC];
 #pragma unroll
-                for (int c = 0; c < NT; c++) {
+                for (int c = 0; c < NTW; c++) {
+                    const int cc = SK_WC == 1 ? c : min(c0 + c, NT - 1);
                     union { i32x4 v; T e[VEC]; } b;
-                    b.v = *reinterpret_cast<const i32x4*>(Xs + (c * 16 + li) * ROWB + kk * SZ);
+                    b.v = *reinterpret_cast<const i32x4*>(Xs + (cc * 16 + li) * ROWB + kk * SZ);
 #pragma unroll
                     for (int e = 0; e < VEC; e++) bv[c][e] = b.e[e];
                 }
 #pragma unroll
                 for (int e = 0; e < VEC; e++)
 #pragma unroll
-                    for (int c = 0; c < NT; c++)
+                    for (int c = 0; c < NTW; c++)
 #pragma unroll
                         for (int r = 0; r < SK_RT; r++) {
                             if constexpr (PREC == P_F32)
