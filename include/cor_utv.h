@@ -77,6 +77,8 @@ typedef enum {
  * replaced by Gaussian columns, so U and V stay orthonormal. */
 #define COR_FLAG_RANK_DEFICIENT 2 /* a pivot was clamped in some orthonormalisation    */
 #define COR_FLAG_NONFINITE 4      /* a non-finite value reached a Gram matrix          */
+#define COR_FLAG_SYNC_TIMEOUT 8   /* l > 224: the QRCP's work-groups gave up waiting   */
+                                  /* for each other (results unusable; COR_E_DEVICE)   */
 
 typedef struct {
     double err_l;     /* ||A - U T V^T||_F / ||A||_F  (report >= 1; identity 1 - ||T||^2/||A||^2) */

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcorutv.so")
 
 COR_OK, COR_E_INVAL, COR_E_NOMEM, COR_E_DEVICE, COR_E_NUMERIC, COR_E_BUSY, COR_E_NOTFOUND = range(7)
 COR_F64, COR_F32, COR_BF16, COR_FP8 = range(4)
-COR_FLAG_RANK_DEFICIENT, COR_FLAG_NONFINITE = 2, 4
+COR_FLAG_RANK_DEFICIENT, COR_FLAG_NONFINITE, COR_FLAG_SYNC_TIMEOUT = 2, 4, 8
 COR_NOALLOC_SCRATCH_BYTES = 64 << 20
 COR_M_R2T, COR_M_EXPLICIT, COR_M_APPROX = 0, 1, 2
 COR_URV, COR_ULV = 0, 1

@@ -28,6 +28,7 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 // Flags (device word per problem; mirrored by COR_FLAG_* of the public header).
 constexpr int32_t FLAG_RANK_DEF = 2;
 constexpr int32_t FLAG_NONFINITE = 4;
+constexpr int32_t FLAG_SYNC_TIMEOUT = 8;
 
 // One decomposition: inputs, workspace and outputs (all device pointers).
 struct Prob {

@@ -903,6 +903,272 @@ __global__ __launch_bounds__(QST_THREADS) void k_qrcp_st(const Prob* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// The same first l - 224 steps on QMB_G work-groups per problem, the trailing
+// matrix held in registers (the alternative to k_qrcp_st for launches small
+// enough that every group of every problem is resident at once).  Group y
+// owns the columns c = y (mod QMB_G): four lanes a column, lane t the rows
+// i = 4 u + t.  Step j: each group posts its candidate -- the key of its
+// largest trailing norm, that norm and the whole column -- into a
+// double-buffered slot (in the Gram array, free until the QRCP ends), the
+// groups meet at a counter in the problem's flag words, and every group then
+// reads all candidates in one round trip, takes the largest key as the pivot
+// (the same choice in every group), forms the reflector from the pivot column
+// and applies it to its own active columns, leaving the pivot column frozen
+// with its raw values in its owner's registers (the column k_qrcp_st leaves
+// in its work array).  At the end every group writes its columns to the work
+// array, the T entries and the reflector row of each pivot it owns; group 0
+// writes tau, the signs, perm and the column map for k_qrcp_hy.
+// A wait past its spin bound sets FLAG_SYNC_TIMEOUT and the group leaves the
+// loop; the last group out resets the counter words to zero.
+// ---------------------------------------------------------------------------
+constexpr int QMB_THREADS = 256;
+constexpr int QMB_COLS = QMB_THREADS / 4;                 // columns per group
+constexpr int QMB_G = (LMAX + QMB_COLS - 1) / QMB_COLS;   // groups per problem
+constexpr int QMB_RPT = (LMAX + 3) / 4;                   // register rows per lane
+constexpr int QMB_ST = (QMB_RPT + 1) / 2 * 2;             // LDS doubles per lane row of v
+constexpr int QMB_SLOT = LMAX + 8;  // doubles per candidate: column, key, norm
+constexpr int QMB_MAX_PROBS = 48;   // problems per launch
+constexpr int QMB_SPIN = 1 << 21;   // polls before a wait gives up (seconds)
+static_assert(2 * QMB_G * QMB_SLOT <= (QHY_LMAX + 1) * (QHY_LMAX + 1), "slots fit the Gram array");
+static_assert(LMAX <= 2 * QMB_THREADS && QMB_RPT % 2 == 0, "two column entries per thread");
+static_assert(QMB_THREADS > LMAX - QHY_LMAX, "rows past the first thread row are below every j");
+
+// Arrival at the step barrier of a problem's groups: every thread's stores
+// are released at agent scope, thread 0 counts the group in and polls until
+// `target` groups have arrived, then every thread acquires.  False when the
+// wait gave up.
+__device__ __forceinline__ bool qmb_sync(int32_t* ctr, int target, int* s_ok) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1, spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > QMB_SPIN) {
+                ok = 0;
+                break;
+            }
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return *s_ok != 0;
+}
+
+__global__ __launch_bounds__(QMB_THREADS) void k_qrcp_mb(const Prob* __restrict__ probs,
+                                                        const int32_t* __restrict__ pidx,
+                                                        const int32_t* __restrict__ toff, int cnt) {
+    __shared__ __align__(16) double s_v[4 * QMB_ST];  // reflector vector, [t][u]
+    __shared__ double s_tau[LMAX], s_scale[LMAX], s_beta[LMAX];
+    __shared__ int s_perm[LMAX];
+    __shared__ unsigned char s_ret[LMAX];  // column pivoted
+    __shared__ int s_wcnt[QMB_THREADS / 64];
+    __shared__ unsigned long long s_key[2];
+    __shared__ int s_ok;
+    const int y = blockIdx.x % QMB_G;
+    const Prob& P = probs[pidx[find_group(toff, cnt, blockIdx.x / QMB_G)]];
+    const int l = P.l;
+    if (l <= QHY_LMAX) return;  // k_qrcp_rt, k_qrcp_hy
+    const int jend = l - QHY_LMAX;
+    const int tid = threadIdx.x, t = tid & 3;
+    const int c = y + QMB_G * (tid >> 2);  // this lane group's column
+    const bool mine = c < l;
+    double* __restrict__ slots = P.G;
+    int32_t* ctr = P.flags + 4;  // [0] arrivals, [1] exits
+    const double* __restrict__ R2 = P.msrc;  // M^T: R2 (M = R2^T), or Mx
+
+    double col[QMB_RPT];
+    double nn = 0.0;
+#pragma unroll
+    for (int u = 0; u < QMB_RPT; u++) {
+        const int i = 4 * u + t;
+        col[u] = (mine && i < l) ? R2[c * l + i] : 0.0;
+        nn = fma(col[u], col[u], nn);
+    }
+    nn = quad_sum(nn);
+    for (int i = tid; i < LMAX; i += QMB_THREADS) s_ret[i] = 0;
+    if (tid < 2) s_key[tid] = 0ull;
+    __syncthreads();
+    if (mine && t == 0) atomicMax(&s_key[0], qr_key(nn, c));
+    bool active = mine;
+    int mystep = -1;  // the step that pivoted this column
+    bool ok = true;
+
+    for (int j = 0; j < jend; j++) {
+        const int par = j & 1;
+        __syncthreads();  // s_key[par] complete, s_piv free
+        // post this group's candidate for step j
+        {
+            const unsigned long long bk = s_key[par];
+            double* sl = slots + (par * QMB_G + y) * QMB_SLOT;
+            if (active && qr_key(nn, c) == bk) {
+#pragma unroll
+                for (int u = 0; u < QMB_RPT; u++) sl[4 * u + t] = col[u];  // zeros past l
+                if (t == 0) sl[LMAX + 1] = nn;
+            }
+            if (tid == 0) {
+                reinterpret_cast<unsigned long long*>(sl)[LMAX] = bk;
+                s_key[par ^ 1] = 0ull;  // last read above; filled after the barrier
+            }
+        }
+        if (!qmb_sync(ctr, QMB_G * (j + 1), &s_ok)) {
+            ok = false;
+            break;
+        }
+        // every candidate in one round trip; the largest key wins
+        const double* sl = slots + par * QMB_G * QMB_SLOT;
+        unsigned long long kk[QMB_G];
+        double cn[QMB_G], ca[QMB_G], c0[QMB_G], c1[QMB_G];
+#pragma unroll
+        for (int g = 0; g < QMB_G; g++) {
+            kk[g] = reinterpret_cast<const unsigned long long*>(sl + g * QMB_SLOT)[LMAX];
+            cn[g] = sl[g * QMB_SLOT + LMAX + 1];
+            ca[g] = sl[g * QMB_SLOT + j];
+            c0[g] = tid < l ? sl[g * QMB_SLOT + tid] : 0.0;
+            c1[g] = tid + QMB_THREADS < l ? sl[g * QMB_SLOT + tid + QMB_THREADS] : 0.0;
+        }
+        unsigned long long key = kk[0];
+        double ss = cn[0], alpha = ca[0], p0 = c0[0], p1 = c1[0];
+#pragma unroll
+        for (int g = 1; g < QMB_G; g++) {
+            if (kk[g] > key) {
+                key = kk[g];
+                ss = cn[g];  // sum over rows >= j of the pivot column squared
+                alpha = ca[g];
+                p0 = c0[g];
+                p1 = c1[g];
+            }
+        }
+        const int p = 511 - (int)(key & 0x1FFull);
+        // the reflector's scalars (every lane, as in k_qrcp_st)
+        double tau = 0.0, beta = alpha, scale = 1.0;
+        if (ss > 0.0) {
+            const double h = 0.5 * ss;
+            double yr = __builtin_amdgcn_rsq(ss);
+#pragma unroll
+            for (int it = 0; it < 2; it++) yr = fma(yr, fma(-h * yr, yr, 0.5), yr);
+            const double xnorm = ss * yr;
+            const double sg = alpha >= 0.0 ? -1.0 : 1.0;
+            beta = sg * xnorm;
+            scale = recip_nr(alpha - beta);
+            tau = (beta - alpha) * (sg * yr);
+        }
+        // v (v_j = 1, scale piv_i below j, zero above j and past l) into LDS,
+        // lane-row major: lane t reads its rows u, u + 1 as one 16-byte word
+        s_v[(tid & 3) * QMB_ST + (tid >> 2)] = tid > j ? p0 * scale : (tid == j ? 1.0 : 0.0);
+        if (tid + QMB_THREADS < 4 * QMB_RPT) {
+            const int i = tid + QMB_THREADS;
+            s_v[(i & 3) * QMB_ST + (i >> 2)] = p1 * scale;  // i > 255 >= jend > j
+        }
+        if (tid == 0) {
+            s_tau[j] = tau;
+            s_scale[j] = scale;
+            s_beta[j] = beta;
+            s_perm[j] = p;
+            s_ret[p] = 1;
+        }
+        __syncthreads();
+        if (active && c == p) {
+            active = false;
+            mystep = j;
+        }
+        if (active) {
+            // w = tau v^T col (the zeros of v above j included), col -= w v,
+            // and the trailing norm below j; register rows wholly above j are
+            // skipped in blocks of 8
+            const double* pv = s_v + t * QMB_ST;
+            double d4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ub = 0; ub < QMB_RPT; ub += 8) {
+                if (4 * (ub + 8) <= j) continue;
+#pragma unroll
+                for (int u = ub; u < ub + 8 && u < QMB_RPT; u += 2) {
+                    const double2 r = *reinterpret_cast<const double2*>(pv + u);
+                    d4[u & 3] = fma(r.x, col[u], d4[u & 3]);
+                    d4[(u + 1) & 3] = fma(r.y, col[u + 1], d4[(u + 1) & 3]);
+                }
+            }
+            const double w = tau * quad_sum((d4[0] + d4[1]) + (d4[2] + d4[3]));
+            double n4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ub = 0; ub < QMB_RPT; ub += 8) {
+                if (4 * (ub + 8) <= j) continue;
+#pragma unroll
+                for (int u = ub; u < ub + 8 && u < QMB_RPT; u += 2) {
+                    const double2 r = *reinterpret_cast<const double2*>(pv + u);
+                    col[u] = fma(-w, r.x, col[u]);
+                    col[u + 1] = fma(-w, r.y, col[u + 1]);
+                    const double x0 = 4 * u + t > j ? col[u] : 0.0;
+                    const double x1 = 4 * u + 4 + t > j ? col[u + 1] : 0.0;
+                    n4[u & 3] = fma(x0, x0, n4[u & 3]);
+                    n4[(u + 1) & 3] = fma(x1, x1, n4[(u + 1) & 3]);
+                }
+            }
+            nn = quad_sum((n4[0] + n4[1]) + (n4[2] + n4[3]));
+            if (t == 0) atomicMax(&s_key[par ^ 1], qr_key(nn, c));
+        }
+    }
+
+    if (ok) {
+        __syncthreads();  // s_tau, s_scale, s_beta, s_perm, s_ret complete
+        double* __restrict__ W = P.R;
+        if (mine) {
+#pragma unroll
+            for (int u = 0; u < QMB_RPT; u++) {
+                const int i = 4 * u + t;
+                if (i < l) W[i * l + c] = col[u];
+            }
+        }
+        if (mystep >= 0) {
+            // column b of T (rows < jend) and reflector b, from the frozen pivot column
+            const int b = mystep;
+            const double sc = s_scale[b];
+#pragma unroll
+            for (int u = 0; u < QMB_RPT; u++) {
+                const int a = 4 * u + t;
+                if (a < jend)
+                    P.T[a * l + b] = a < b ? col[u] * (s_beta[a] < 0.0 ? -1.0 : 1.0)
+                                           : (a == b ? fabs(s_beta[b]) : 0.0);
+                if (a < l) P.Qt[b * l + a] = a == b ? 1.0 : (a > b ? col[u] * sc : 0.0);
+            }
+        }
+        if (y == 0) {
+            for (int jj = tid; jj < jend; jj += QMB_THREADS) {
+                P.tau[jj] = s_tau[jj];
+                P.tau[LMAX + jj] = s_beta[jj] < 0.0 ? -1.0 : 1.0;
+                P.perm[jj] = s_perm[jj];
+            }
+            // the columns left for the trailing block, in increasing order
+            const int lane = tid & 63, wave = tid >> 6;
+            int base = 0;
+            for (int c0 = 0; c0 < l; c0 += QMB_THREADS) {
+                const int cc = c0 + tid;
+                const bool act = cc < l && !s_ret[cc];
+                const unsigned long long bal = __ballot(act);
+                if (lane == 0) s_wcnt[wave] = __popcll(bal);
+                __syncthreads();
+                int off = base + __popcll(bal & ((1ull << lane) - 1ull));
+                for (int w = 0; w < wave; w++) off += s_wcnt[w];
+                if (act) ((int32_t*)P.Racc)[off] = cc;
+                for (int w = 0; w < QMB_THREADS / 64; w++) base += s_wcnt[w];
+                __syncthreads();
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (!ok) atomicOr(P.flags, FLAG_SYNC_TIMEOUT);
+        const int e = __hip_atomic_fetch_add(ctr + 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (e == QMB_G - 1) {  // every group is past its last wait
+            __hip_atomic_store(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ctr + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // QRCP of M = R2^T for 128 < l <= 224: registers and LDS (one block of 4 l
 // threads per problem).  Four lanes own a column, lane t the rows
 // i = 4 u + t; rows u < QHY_RR stay in registers and the next LRC rows in LDS
@@ -1429,10 +1695,17 @@ hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
     }
     // l > 224: the first l - 224 steps with M streamed from the L2-resident
     // work array, 4 lanes per column; k_qrcp_hy takes the rest
+    // (QMB_G groups per problem with the matrix in registers when every group
+    // of the launch fits on the chip at once, else one block streaming it)
     if (lmax > QHY_LMAX) {
-        const int threads = std::min(QST_THREADS, (4 * lmax + 63) / 64 * 64);
-        hipLaunchKernelGGL(k_qrcp_st, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx,
-                           g.toff, g.count);
+        if (g.blocks <= QMB_MAX_PROBS) {
+            hipLaunchKernelGGL(k_qrcp_mb, dim3(g.blocks * QMB_G), dim3(QMB_THREADS), 0, s, g.probs,
+                               g.pidx, g.toff, g.count);
+        } else {
+            const int threads = std::min(QST_THREADS, (4 * lmax + 63) / 64 * 64);
+            hipLaunchKernelGGL(k_qrcp_st, dim3(g.blocks), dim3(threads), 0, s, g.probs, g.pidx,
+                               g.toff, g.count);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

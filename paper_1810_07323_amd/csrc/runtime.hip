@@ -1002,6 +1002,8 @@ cor_status plan_info(Plan* P, cor_info* infos, hipStream_t s) {
             f.l = d.l;
         }
         if (flags & FLAG_NONFINITE) return fail(COR_E_NUMERIC, "non-finite value in a Gram matrix");
+        if (flags & FLAG_SYNC_TIMEOUT)
+            return fail(COR_E_DEVICE, "the QRCP's work-groups timed out waiting for each other");
     }
     return COR_OK;
 }

@@ -152,10 +152,10 @@ def test_f64_core_small_sizes(cu, dev, orc, l):
 @pytest.mark.parametrize("l", [130, 150, 170, 185, 200, 224, 225, 240, 260, 264])
 def test_f64_core_qrcp_sizes(cu, dev, orc, l):
     """l x l stages beyond 128 columns: every LDS row count of the register +
-    LDS QRCP kernel (l = 130 .. 224), the streamed first l - 224 steps followed
-    by the register + LDS kernel on the trailing block (l = 225: one streamed
-    step; 240, 260, 264), and the Cholesky in two (l <= 256) and three
-    (l > 256) diagonal blocks."""
+    LDS QRCP kernel (l = 130 .. 224), the first l - 224 steps on several
+    work-groups followed by the register + LDS kernel on the trailing block
+    (l = 225: one such step; 240, 260, 264), and the Cholesky in two
+    (l <= 256) and three (l > 256) diagonal blocks."""
     import torch
 
     m, n = 560, 500

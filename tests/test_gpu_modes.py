@@ -225,9 +225,10 @@ def test_batched_equals_single_and_oracle(cu, dev, orc):
 
 def test_batched_every_qrcp_class(cu, dev, orc):
     """One batched call whose problems take every QRCP kernel class (l = 20
-    register-resident, l = 150 registers + LDS, l = 240 and 264 streamed first
-    steps then the trailing 224 x 224 block) next to each other: each equals
-    its single call bitwise and the oracle to the FP64 rule."""
+    register-resident, l = 150 registers + LDS, l = 240 and 264 the first
+    l - 224 steps on several work-groups, then the trailing 224 x 224 block)
+    next to each other: each equals its single call bitwise and the oracle to
+    the FP64 rule."""
     import torch
 
     shapes = [(600, 500, 14, 6, 1), (640, 520, 140, 10, 0), (700, 560, 230, 10, 1),
@@ -268,6 +269,64 @@ def test_batched_every_qrcp_class(cu, dev, orc):
         if ref["diag"][1] > 1e-8:
             assert np.array_equal(Pb, ref["perm"])
             assert np.abs(Tb - ref["T"]).max() <= 1e-10 * np.abs(ref["T"]).max()
+
+
+def test_large_batch_streamed_qrcp(cu, dev, orc):
+    """A batched call of more problems than the multi-group QRCP launch takes
+    (48), so the first l - 224 steps of its l > 224 problems run on the
+    single-block streamed kernel: those problems equal their single calls
+    (multi-group kernel) to rounding and the oracle to the FP64 rule; the
+    small problems equal their single calls bitwise."""
+    import torch
+
+    big = [(700, 560, 230, 10, 1), (620, 600, 250, 14, 0), (650, 580, 236, 12, 1)]
+    shapes = [(300 + 7 * i, 200 + 3 * i, 8, 4, 1) for i in range(50)]
+    for j, b in enumerate(big):
+        shapes.insert(10 + 20 * j, b)
+    probs, outs, mats, oms = [], [], [], []
+    for i, (m, n, k, p, q) in enumerate(shapes):
+        a, _ = I.lowrank(m, n, np.exp(-np.arange(1, n + 1) / 40.0), seed=1300 + i)
+        om = I.gaussian_omega(n, k + p, 300 + i)
+        A = torch.from_numpy(a).to(dev)
+        omd = torch.from_numpy(om).to(dev)
+        o = _outputs(dev, m, n, k + p)
+        probs.append(cu.make_problem(A, k, p, q, 0, *o, omega=omd))
+        outs.append(o)
+        mats.append((a, A))
+        oms.append((om, omd))
+    st, _ = cu.cor_utv_batched(probs, cu.cor_opts(0, 0))
+    cu.check(st, "batched")
+    torch.cuda.synchronize()
+    for i, (m, n, k, p, q) in enumerate(shapes):
+        a, A = mats[i]
+        l = k + p
+        if l <= 224 and i % 7:
+            continue
+        o1 = _outputs(dev, m, n, l)
+        st, _ = cu.cor_utv_ex(cu.make_problem(A, k, p, q, 0, *o1, omega=oms[i][1]),
+                              cu.cor_opts(0, 0))
+        cu.check(st, "single")
+        torch.cuda.synchronize()
+        Ub, Tb, Vb, Pb = [x.cpu().numpy() for x in outs[i]]
+        if l <= 224:
+            for x, y in zip(outs[i], o1):
+                assert torch.equal(x, y), f"problem {i} (l = {l}) differs from its single call"
+            continue
+        U1, T1, V1, P1 = [x.cpu().numpy() for x in o1]
+        ref = orc.cor_utv(a, k, p, q, oms[i][0])
+        mg = orc.metrics(a, Ub, Tb, Vb, k)
+        mo = orc.metrics(a, ref["U"], ref["T"], ref["V"], k)
+        scale = np.abs(ref["T"]).max()
+        print(f"[streamed qrcp l={l}] d eps {abs(mg['err_l'] - mo['err_l']):.1e} vs single "
+              f"|dT| {np.abs(Tb - T1).max() / scale:.1e} gap {ref['diag'][1]:.1e}")
+        assert abs(mg["err_l"] - mo["err_l"]) <= 1e-12
+        assert mg["orth_u"] <= 1e-13 and mg["orth_v"] <= 1e-13
+        assert np.array_equal(np.tril(Tb, -1), np.zeros_like(Tb))
+        if ref["diag"][1] > 1e-8:
+            assert np.array_equal(Pb, ref["perm"]) and np.array_equal(P1, ref["perm"])
+            assert np.abs(Tb - ref["T"]).max() <= 1e-10 * scale
+            assert np.abs(Tb - T1).max() <= 1e-12 * scale
+            assert np.abs(Ub - U1).max() <= 1e-12 and np.abs(Vb - V1).max() <= 1e-12
 
 
 def test_batched_bf16_recipe_against_oracle(cu, dev, orc):
