@@ -69,9 +69,9 @@ WORKLOADS = {
 }
 
 
-def source_hash():
+def source_hash(fname="k_sketch.hip"):
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1810_07323_amd", "csrc", "k_sketch.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_1810_07323_amd", "csrc", fname), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -416,15 +416,18 @@ def pass_roofline(prec, l, prof, kernel="k_sketch (passes over A)", flops_per_el
 
 
 def traffic_of(name, splits=None):
-    """Calibrated HBM bytes per pass launch from the committed counters, if
-    they were taken on the current k_sketch.hip and the same split counts."""
+    """Calibrated HBM bytes per launch of the dominant kernel from the
+    committed counters, if they were taken on the current source of that
+    kernel (k_sketch.hip unless the file names another) and the same split
+    counts."""
     tpath = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if os.path.exists(tpath):
         with open(tpath) as f:
             tr = json.load(f)
         same = splits is None or (tr.get("s_ax"), tr.get("s_atx")) == (splits["s_ax"],
                                                                          splits["s_atx"])
-        if tr.get("source_hash") == source_hash() and same:
+        src = tr.get("source", "k_sketch.hip")
+        if tr.get("source_hash") == source_hash(src) and same:
             return tr.get("bytes_per_launch")
     return None
 
