@@ -1171,10 +1171,12 @@ __global__ __launch_bounds__(QMB_THREADS) void k_qrcp_mb(const Prob* __restrict_
 // ---------------------------------------------------------------------------
 // QRCP of M = R2^T for 128 < l <= 224: registers and LDS (one block of 4 l
 // threads per problem).  Four lanes own a column, lane t the rows
-// i = 4 u + t; rows u < QHY_RR stay in registers and the next LRC rows in LDS
-// (thread-major with an odd stride, so that the row offsets are immediates
-// and 8-byte reads are free of bank conflicts; LRC is the launch's LDS row
-// count rounded up to 4, rows past l are zeros and stay zeros).  Step j as in the
+// i = 4 u + t; the first LRC rows per lane (u < LRC) live in LDS and the next
+// QHY_RR in registers, so that once the steps pass row 4 LRC the LDS rows are
+// above j and no step touches them again (thread-major with an odd stride,
+// so that the row offsets are immediates and 8-byte reads are free of bank
+// conflicts; LRC is the launch's LDS row count rounded up to 4, rows past l
+// are zeros and stay zeros).  Step j as in the
 // register-resident kernel: the pivot group puts its raw column into an LDS
 // buffer laid out [t][u] (16-byte reads) and into a global archive (P.R,
 // column j = raw_j, read only at the end) and forms beta, tau and scale;
@@ -1200,7 +1202,7 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
     constexpr int LR = LRC;
     constexpr int LRP = LRC + 1;  // LDS doubles per thread (odd: conflict-free 8-byte reads)
     constexpr int ST = RR + LR + 2;  // doubles per lane row of the pivot buffer
-    extern __shared__ __align__(16) double s_m[];  // [thread][u - RR]
+    extern __shared__ __align__(16) double s_m[];  // [thread][u], u < LR
     __shared__ __align__(16) double s_pv[4 * ST];  // raw pivot column, [t][u]
     __shared__ double s_nrm[QHY_LMAX];
     __shared__ double s_tau[QHY_LMAX], s_scale[QHY_LMAX], s_beta[QHY_LMAX];
@@ -1224,23 +1226,24 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
     const int32_t* __restrict__ cmap = (const int32_t*)P.Racc;
     const int mc = tail && incol ? cmap[c] : 0;     // column of M held by this group
 
-    // rows past l are zero and stay zero (the pivot column is zero there)
+    // rows past l are zero and stay zero (the pivot column is zero there);
+    // the norm takes the rows in increasing order, as every step does
     double col[RR];
     double nn = 0.0;
 #pragma unroll
-    for (int u = 0; u < RR; u++) {
-        const int i = 4 * u + t;
-        // M[i][c] = R2[c][i]; tail: row j0 + i of column mc of the work array
-        col[u] = (incol && i < l) ? (tail ? W[(j0 + i) * L + mc] : R2[c * l + i]) : 0.0;
-        nn = fma(col[u], col[u], nn);
-    }
-#pragma unroll
     for (int k = 0; k < LR; k++) {
-        const int i = 4 * (RR + k) + t;
+        const int i = 4 * k + t;
         const double v =
             (incol && i < l) ? (tail ? W[(j0 + i) * L + mc] : R2[c * l + i]) : 0.0;
         s_m[tid * LRP + k] = v;
         nn = fma(v, v, nn);
+    }
+#pragma unroll
+    for (int u = 0; u < RR; u++) {
+        const int i = 4 * (LR + u) + t;
+        // M[i][c] = R2[c][i]; tail: row j0 + i of column mc of the work array
+        col[u] = (incol && i < l) ? (tail ? W[(j0 + i) * L + mc] : R2[c * l + i]) : 0.0;
+        nn = fma(col[u], col[u], nn);
     }
     nn = quad_sum(nn);
     if (tid < 2) s_key[tid] = 0ull;
@@ -1259,10 +1262,10 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
             double* pv = s_pv + t * ST;
 #pragma unroll
             for (int u = 0; u < RR; u += 2)
-                *reinterpret_cast<double2*>(pv + u) = make_double2(col[u], col[u + 1]);
+                *reinterpret_cast<double2*>(pv + LR + u) = make_double2(col[u], col[u + 1]);
 #pragma unroll
             for (int k = 0; k < LR; k++) {
-                pv[RR + k] = s_m[tid * LRP + k];
+                pv[k] = s_m[tid * LRP + k];
                 if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // 4 rows in flight
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1297,43 +1300,47 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
         if (active) {
             const double tau = s_tau[j], scale = s_scale[j];
             const double* pv = s_pv + t * ST;
-            // row i = 4 u + t of this lane is below / at row j iff 4 u > / == jt
-            // (compares against constants: no per-row index registers)
+            // row i = 4 u' + t of this lane (u' = u + LR in registers, u' = k
+            // in LDS) is below / at row j iff 4 u' > / == jt (compares
+            // against constants: no per-row index registers)
             const int jt = j - t;
             // w = tau (col_j + scale sum_{i > j} raw_i col_i); only the block
-            // that holds row j needs per-element masks
+            // that holds row j needs per-element masks.  Each partial sum
+            // takes its rows in increasing order (LDS rows, then register
+            // rows), so the result does not depend on the LDS row count.
             double d4[4] = {0.0, 0.0, 0.0, 0.0};
             double cj = 0.0;  // col_j in the lane that holds row j
 #pragma unroll
-            for (int q = 0; q < RR / CH; q++) {
-                const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
+            for (int q = 0; q < LR / 4; q++) {  // LDS rows in blocks of 16
+                const int lo = 16 * q, hi = lo + 15;
                 if (hi < j) continue;
 #pragma unroll
-                for (int u = q * CH; u < q * CH + CH; u += 2) {
-                    const double2 r = *reinterpret_cast<const double2*>(pv + u);
+                for (int kk = 0; kk < 4; kk++) {
+                    const int k = 4 * q + kk, i4 = 4 * k;
+                    const double x = s_m[tid * LRP + k];
                     if (lo > j) {
-                        d4[u & 3] = fma(r.x, col[u], d4[u & 3]);
-                        d4[(u + 1) & 3] = fma(r.y, col[u + 1], d4[(u + 1) & 3]);
+                        d4[kk] = fma(pv[k], x, d4[kk]);
                     } else {
-                        d4[u & 3] = fma(4 * u > jt ? r.x : 0.0, col[u], d4[u & 3]);
-                        d4[(u + 1) & 3] = fma(4 * u + 4 > jt ? r.y : 0.0, col[u + 1], d4[(u + 1) & 3]);
-                        cj = 4 * u == jt ? col[u] : (4 * u + 4 == jt ? col[u + 1] : cj);
+                        d4[kk] = fma(i4 > jt ? pv[k] : 0.0, x, d4[kk]);
+                        cj = i4 == jt ? x : cj;
                     }
                 }
             }
 #pragma unroll
-            for (int q = 0; q < LR / 4; q++) {  // LDS rows in blocks of 16
-                const int lo = 4 * (RR + 4 * q), hi = lo + 15;
+            for (int q = 0; q < RR / CH; q++) {
+                const int lo = 4 * (LR + CH * q), hi = lo + 4 * CH - 1;
                 if (hi < j) continue;
 #pragma unroll
-                for (int kk = 0; kk < 4; kk++) {
-                    const int k = 4 * q + kk, i4 = 4 * (RR + k);
-                    const double x = s_m[tid * LRP + k];
+                for (int u = q * CH; u < q * CH + CH; u += 2) {
+                    const double2 r = *reinterpret_cast<const double2*>(pv + LR + u);
                     if (lo > j) {
-                        d4[kk] = fma(pv[RR + k], x, d4[kk]);
+                        d4[u & 3] = fma(r.x, col[u], d4[u & 3]);
+                        d4[(u + 1) & 3] = fma(r.y, col[u + 1], d4[(u + 1) & 3]);
                     } else {
-                        d4[kk] = fma(i4 > jt ? pv[RR + k] : 0.0, x, d4[kk]);
-                        cj = i4 == jt ? x : cj;
+                        const int i0 = 4 * (LR + u), i1 = i0 + 4;
+                        d4[u & 3] = fma(i0 > jt ? r.x : 0.0, col[u], d4[u & 3]);
+                        d4[(u + 1) & 3] = fma(i1 > jt ? r.y : 0.0, col[u + 1], d4[(u + 1) & 3]);
+                        cj = i0 == jt ? col[u] : (i1 == jt ? col[u + 1] : cj);
                     }
                 }
             }
@@ -1342,42 +1349,42 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
             // col_i -= ws raw_i below j, col_j -= w; squared norm below j
             double n4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
+            for (int q = 0; q < LR / 4; q++) {
+                const int lo = 16 * q, hi = lo + 15;
+                if (hi < j) continue;
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++) {
+                    const int k = 4 * q + kk, i4 = 4 * k;
+                    double x = s_m[tid * LRP + k];
+                    if (lo > j) {
+                        x = fma(-ws, pv[k], x);
+                        n4[kk] = fma(x, x, n4[kk]);
+                    } else {
+                        x = i4 > jt ? fma(-ws, pv[k], x) : (i4 == jt ? x - w : x);
+                        if (i4 > jt) n4[kk] = fma(x, x, n4[kk]);
+                    }
+                    s_m[tid * LRP + k] = x;
+                }
+            }
+#pragma unroll
             for (int q = 0; q < RR / CH; q++) {
-                const int lo = 4 * CH * q, hi = lo + 4 * CH - 1;
+                const int lo = 4 * (LR + CH * q), hi = lo + 4 * CH - 1;
                 if (hi < j) continue;
 #pragma unroll
                 for (int u = q * CH; u < q * CH + CH; u += 2) {
-                    const double2 r = *reinterpret_cast<const double2*>(pv + u);
+                    const double2 r = *reinterpret_cast<const double2*>(pv + LR + u);
                     if (lo > j) {
                         col[u] = fma(-ws, r.x, col[u]);
                         col[u + 1] = fma(-ws, r.y, col[u + 1]);
                         n4[u & 3] = fma(col[u], col[u], n4[u & 3]);
                         n4[(u + 1) & 3] = fma(col[u + 1], col[u + 1], n4[(u + 1) & 3]);
                     } else {
-                        const int i0 = 4 * u, i1 = i0 + 4;
+                        const int i0 = 4 * (LR + u), i1 = i0 + 4;
                         col[u] = i0 > jt ? fma(-ws, r.x, col[u]) : (i0 == jt ? col[u] - w : col[u]);
                         col[u + 1] = i1 > jt ? fma(-ws, r.y, col[u + 1]) : (i1 == jt ? col[u + 1] - w : col[u + 1]);
                         if (i0 > jt) n4[u & 3] = fma(col[u], col[u], n4[u & 3]);
                         if (i1 > jt) n4[(u + 1) & 3] = fma(col[u + 1], col[u + 1], n4[(u + 1) & 3]);
                     }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < LR / 4; q++) {
-                const int lo = 4 * (RR + 4 * q), hi = lo + 15;
-                if (hi < j) continue;
-#pragma unroll
-                for (int kk = 0; kk < 4; kk++) {
-                    const int k = 4 * q + kk, i4 = 4 * (RR + k);
-                    double x = s_m[tid * LRP + k];
-                    if (lo > j) {
-                        x = fma(-ws, pv[RR + k], x);
-                        n4[kk] = fma(x, x, n4[kk]);
-                    } else {
-                        x = i4 > jt ? fma(-ws, pv[RR + k], x) : (i4 == jt ? x - w : x);
-                        if (i4 > jt) n4[kk] = fma(x, x, n4[kk]);
-                    }
-                    s_m[tid * LRP + k] = x;
                 }
             }
             const double n = quad_sum((n4[0] + n4[1]) + (n4[2] + n4[3]));
