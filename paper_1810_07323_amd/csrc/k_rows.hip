@@ -778,6 +778,7 @@ static hipError_t launch_apply_m(const LaunchGroup& g, int side, int lmax, int i
     if (qn <= 1) return launch_apply_t<MODE, 1>(g, side, lmax, iter, s);
     if (qn <= 2) return launch_apply_t<MODE, 2>(g, side, lmax, iter, s);
     if (qn <= 3) return launch_apply_t<MODE, 3>(g, side, lmax, iter, s);
+    if (qn <= 4) return launch_apply_t<MODE, 4>(g, side, lmax, iter, s);
     return launch_apply_t<MODE, 5>(g, side, lmax, iter, s);
 }
 
