@@ -393,7 +393,15 @@ struct Plan {
     bool async = false;
     bool owned = true;  // mem was allocated by the plan (else caller-provided)
     std::vector<int32_t> tab_host;
+    // Passes of several column-tile classes: the classes' launches run side
+    // by side on these streams (fork and join through events), so that one
+    // class's last blocks overlap the others' instead of each launch ending
+    // in its own tail.  ev[0] forks, ev[1 + i] joins aux[i].
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> ev;
 };
+
+constexpr int PASS_AUX_STREAMS = 4;
 
 // Build a launch table: per-problem block counts -> (pidx, toff) in device memory.
 struct TableBuilder {
@@ -745,6 +753,26 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
             P->ata.push_back(f);
         }
     }
+    // streams for the classes of a pass (not for caller-provided memory: that
+    // entry point creates nothing)
+    if (P->owned && P->skAX.size() > 1) {
+        const int na = std::min<int>(PASS_AUX_STREAMS, (int)P->skAX.size() - 1);
+        hipError_t se = hipSuccess;
+        for (int i = 0; i < na && se == hipSuccess; i++) {
+            hipStream_t st = nullptr;
+            se = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (se == hipSuccess) P->aux.push_back(st);
+        }
+        for (int i = 0; i <= na && se == hipSuccess; i++) {
+            hipEvent_t ev = nullptr;
+            se = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (se == hipSuccess) P->ev.push_back(ev);
+        }
+        if (se != hipSuccess) {
+            plan_destroy(P, nullptr);
+            return hip_fail(se, "pass streams");
+        }
+    }
     *out = P;
     return COR_OK;
 }
@@ -814,15 +842,40 @@ static hipError_t host_pass(Plan* P, int kind, int it, hipStream_t s) {
     return hipSuccess;
 }
 
-static hipError_t run_sketch(const std::vector<Plan::Grp>& gs, bool trans, int iter,
-                             hipStream_t s) {
-    for (const auto& g : gs) {
-        hipEvent_t a, b;
-        prof_begin(s, &a, &b, 1);
-        hipError_t e = launch_sketch(g.prec, trans, g.nt, g.g, iter, s);
-        if (e != hipSuccess) return e;
-        prof_end(s, a, b, g.bytes, g.flops);
+static hipError_t run_sketch(const Plan* P, const std::vector<Plan::Grp>& gs, bool trans,
+                             int iter, hipStream_t s) {
+    const int na = std::min<int>((int)gs.size() - 1, (int)P->aux.size());
+    if (na <= 0) {
+        for (const auto& g : gs) {
+            hipEvent_t a, b;
+            prof_begin(s, &a, &b, 1);
+            hipError_t e = launch_sketch(g.prec, trans, g.nt, g.g, iter, s);
+            if (e != hipSuccess) return e;
+            prof_end(s, a, b, g.bytes, g.flops);
+        }
+        return hipSuccess;
     }
+    // classes side by side: class 0 on s, class k on aux[(k - 1) mod na];
+    // profiled as one launch from the fork to the join
+    double bytes = 0, flops = 0;
+    for (const auto& g : gs) {
+        bytes += g.bytes;
+        flops += g.flops;
+    }
+    hipEvent_t a, b;
+    prof_begin(s, &a, &b, 1);
+    hipError_t e = hipEventRecord(P->ev[0], s);
+    for (int i = 0; i < na && e == hipSuccess; i++) e = hipStreamWaitEvent(P->aux[i], P->ev[0], 0);
+    for (size_t k = 0; k < gs.size() && e == hipSuccess; k++) {
+        hipStream_t st = k == 0 ? s : P->aux[(k - 1) % na];
+        e = launch_sketch(gs[k].prec, trans, gs[k].nt, gs[k].g, iter, st);
+    }
+    for (int i = 0; i < na && e == hipSuccess; i++) {
+        e = hipEventRecord(P->ev[1 + i], P->aux[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, P->ev[1 + i], 0);
+    }
+    if (e != hipSuccess) return e;
+    prof_end(s, a, b, bytes, flops);
     return hipSuccess;
 }
 
@@ -883,7 +936,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         if (P->hs) {
             E(host_pass(P, HP_AX, it, s));
         } else {
-            E(run_sketch(P->skAX, false, it, s));
+            E(run_sketch(P, P->skAX, false, it, s));
             E(launch_sum(P->sumM.g, SIDE_M, it, s));
         }
         E(launch_gram(P->gramM.g, SIDE_M, GSRC_Y, it, s));
@@ -906,7 +959,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
         if (P->has_approx && P->last[it]) E(launch_keep_x(P->keepx.g, it, s));
         // Y2 = A^T Q1, Q2 R2 = Y2 (CholeskyQR2); X <- Q2
         if (P->hs) E(host_pass(P, HP_ATX, it, s));
-        else E(run_sketch(P->skATX, true, it, s));
+        else E(run_sketch(P, P->skATX, true, it, s));
         E(launch_sum(P->sumN.g, SIDE_N, it, s));
         E(nside(it));
         if (fp8 && it < P->max_q) {
@@ -921,7 +974,7 @@ static hipError_t plan_enqueue(Plan* P, hipStream_t s) {
             E(launch_op_scales(P->scN.g, P->small.g, SIDE_N, P->max_q, s));
             E(launch_make_op(P->opN.g, SIDE_N, s));
         }
-        E(run_sketch(P->skAX, false, -1, s));  // Y = A Q2
+        E(run_sketch(P, P->skAX, false, -1, s));  // Y = A Q2
         E(launch_sum(P->sumM.g, SIDE_M, -1, s));
         E(launch_gram(P->xgM.g, SIDE_M, GSRC_XM, -1, s));  // Q1^T Y
         E(launch_xreduce(P->xred.g, GSRC_XM, s));
@@ -1024,6 +1077,8 @@ static void host_stream_free(HostStream* H) {
 void plan_destroy(Plan* P, hipStream_t s) {
     if (!P) return;
     host_stream_free(P->hs);
+    for (hipStream_t st : P->aux) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : P->ev) (void)hipEventDestroy(ev);
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->mem && P->owned) {
@@ -1342,9 +1397,9 @@ static cor_status tune_measure(const cor_problem& p, int32_t s_ax, int32_t s_atx
     if (he == hipSuccess) st = plan_run(P, s);  // every operand initialised
     if (he == hipSuccess && st == COR_OK) {
         he = hipEventRecord(e[0], s);
-        for (int r = 0; r < reps && he == hipSuccess; r++) he = run_sketch(P->skAX, false, 0, s);
+        for (int r = 0; r < reps && he == hipSuccess; r++) he = run_sketch(P, P->skAX, false, 0, s);
         if (he == hipSuccess) he = hipEventRecord(e[1], s);
-        for (int r = 0; r < reps && he == hipSuccess; r++) he = run_sketch(P->skATX, true, 0, s);
+        for (int r = 0; r < reps && he == hipSuccess; r++) he = run_sketch(P, P->skATX, true, 0, s);
         if (he == hipSuccess) he = hipEventRecord(e[2], s);
         if (he == hipSuccess) he = hipEventSynchronize(e[2]);
         float a = 0.0f, b = 0.0f;
