@@ -382,7 +382,9 @@ def test_graph_replay_equals_eager(cu, dev, orc):
     """A plan captured into a HIP graph and replayed gives bit for bit the
     result of the eager run; replays are interleaved with other device work
     and host synchronisations, and every replay is checked (FP32 and BF16
-    problems in one plan, seeded test matrices, report on)."""
+    problems in one plan, seeded test matrices, report on).  The three
+    problems fall in three (format, column tiles) classes, so every pass runs
+    its classes on the plan's forked streams, as graph branches here."""
     import torch
 
     shapes = [(1300, 900, 40, 8, 1, "f32"), (700, 1100, 20, 5, 2, "bf16"), (600, 500, 9, 3, 0, "f32")]
