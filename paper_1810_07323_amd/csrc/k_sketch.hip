@@ -47,13 +47,15 @@ template <> struct SkCfg<P_FP8> { static constexpr int BK = 128, VEC = 16; };
 // tile at l = 220).  Eight waves mean two per SIMD and half the register file
 // each: shapes whose accumulators do not fit that (FP64 beyond 8 column
 // tiles, FP32 beyond 12, FP8 beyond 9, FP8 A X) keep 4 waves -- except FP64
-// beyond 8 column tiles and FP32 where it would have one wave per SIMD (A X
-// beyond 9 column tiles, A^T X beyond 12), which take 8 waves of 128-row
-// blocks in 4 row groups x 2 column groups: a wave's accumulators (2 row
-// tiles x half the column tiles) then leave room for two waves per SIMD (with
-// one wave of 2 x NT tiles per SIMD the MFMA pipe waits on every tile's loads).
+// beyond 8 column tiles, FP32 where it would have one wave per SIMD (A X
+// beyond 9 column tiles, A^T X beyond 12) and FP8 A X beyond 9, which take 8
+// waves of 128-row blocks in 4 row groups x 2 column groups: a wave's
+// accumulators (2 row tiles x half the column tiles) then leave room for two
+// waves per SIMD (with one wave of 2 x NT tiles per SIMD the MFMA pipe waits
+// on every tile's loads).
 template <int PREC, bool TRANS> __host__ __device__ constexpr bool sk_split_cols(int nt) {
-    return (PREC == P_F64 && nt >= 9) || (PREC == P_F32 && nt >= (TRANS ? 13 : 10));
+    return (PREC == P_F64 && nt >= 9) || (PREC == P_F32 && nt >= (TRANS ? 13 : 10)) ||
+           (PREC == P_FP8 && !TRANS && nt >= 10);
 }
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_waves() {
     constexpr int ntmax = PREC == P_F64 ? 8 : PREC == P_F32 ? 12 : PREC == P_FP8 ? 9 : NTMAX;
@@ -468,8 +470,10 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 av[r] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
             }
 #pragma unroll
-            for (int c = 0; c < NT; c++) {
-                const unsigned char* p = Xs + (c * 16 + li) * ROWB + kk;
+            for (int c = 0; c < NTW; c++) {
+                const int cc = c0 + c;  // column tile (wave-uniform test)
+                if (SK_WC > 1 && cc >= NT) break;
+                const unsigned char* p = Xs + (cc * 16 + li) * ROWB + kk;
                 i32x4 lo = *reinterpret_cast<const i32x4*>(p);
                 i32x4 hi = *reinterpret_cast<const i32x4*>(p + 16);
                 i32x8 bv = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
