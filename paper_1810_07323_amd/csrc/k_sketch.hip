@@ -48,14 +48,15 @@ template <> struct SkCfg<P_FP8> { static constexpr int BK = 128, VEC = 16; };
 // each: shapes whose accumulators do not fit that (FP64 beyond 8 column
 // tiles, FP32 beyond 12, FP8 beyond 9, FP8 A X) keep 4 waves -- except FP64
 // beyond 8 column tiles, FP32 where it would have one wave per SIMD (A X
-// beyond 9 column tiles, A^T X beyond 12) and FP8 A X beyond 9, which take 8
-// waves of 128-row blocks in 4 row groups x 2 column groups: a wave's
-// accumulators (2 row tiles x half the column tiles) then leave room for two
-// waves per SIMD (with one wave of 2 x NT tiles per SIMD the MFMA pipe waits
-// on every tile's loads).
+// beyond 9 column tiles, A^T X beyond 12) and FP8 beyond 9 (A^T X: 10, 12
+// and 14, the counts that do not spill), which take 8 waves in 4 row groups
+// x 2 column groups: a wave's accumulators (2 row tiles -- 4 for FP8 A^T X,
+// whose register transpose wants 256-row tiles -- x half the column tiles)
+// then leave room for two waves per SIMD (with one wave of 2 x NT tiles per
+// SIMD the MFMA pipe waits on every tile's loads).
 template <int PREC, bool TRANS> __host__ __device__ constexpr bool sk_split_cols(int nt) {
     return (PREC == P_F64 && nt >= 9) || (PREC == P_F32 && nt >= (TRANS ? 13 : 10)) ||
-           (PREC == P_FP8 && !TRANS && nt >= 10);
+           (PREC == P_FP8 && nt >= 10 && (!TRANS || (nt <= 14 && nt % 2 == 0)));
 }
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_waves() {
     constexpr int ntmax = PREC == P_F64 ? 8 : PREC == P_F32 ? 12 : PREC == P_FP8 ? 9 : NTMAX;
@@ -79,10 +80,10 @@ template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_wc(
                ? 2
                : 1;
 }
-// Row tiles per wave: 2 WC for BF16 (64 rows per wave with two column groups),
-// 2 for the FP32 / FP64 column split.
+// Row tiles per wave: 2 WC for BF16 and FP8 A^T X (64 rows per wave with two
+// column groups), 2 for the FP32 / FP64 / FP8 A X column split.
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_rt() {
-    return PREC == P_BF16 ? 2 * sk_wc<PREC, NT, TRANS>() : 2;
+    return (PREC == P_BF16 || (PREC == P_FP8 && TRANS)) ? 2 * sk_wc<PREC, NT, TRANS>() : 2;
 }
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_bm() {
     return 16 * sk_rt<PREC, NT, TRANS>() * (sk_waves<PREC, NT, TRANS>() / sk_wc<PREC, NT, TRANS>());

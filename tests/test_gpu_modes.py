@@ -144,6 +144,23 @@ def test_quantised_passes_widest_l(cu, dev, orc, fmt, l):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("l", [150, 170, 190])
+def test_quantised_passes_column_groups(cu, dev, orc, fmt, l):
+    """Ten to twelve column tiles (l = 150, 170, 190): the 8-wave blocks whose
+    waves split the column tiles in two groups (BF16; FP8 A X, and FP8 A^T X
+    at an even tile count, with 256-row tiles for its register transpose)
+    next to the 4-wave form (FP8 A^T X at eleven tiles); same rules as the
+    widest sketches."""
+    m, n = 1100, 900
+    a, _ = I.lowrank(m, n, np.exp(-np.arange(1, n + 1) / 150.0), seed=2600 + l)
+    k, p, q = l - 16, 16, 1
+    om = I.gaussian_omega(n, l, 14)
+    r = _quantised_case(cu, dev, orc, a, k, p, q, fmt, om, f"l={l}")
+    assert abs(r["stored"] - 1.0) <= 0.05 and abs(r["stored_k"] - 1.0) <= 0.05
+    assert r["fp64"] <= 1.05 and r["fp64_k"] <= 1.05
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
 def test_quantised_tall_many_splits(cu, dev, orc, fmt):
     """A tall matrix (30000 x 1500): the transposed pass has few output row
     blocks and takes up to 64 K splits; the result matches the stored-format
