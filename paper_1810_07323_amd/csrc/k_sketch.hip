@@ -8,8 +8,11 @@
 // column tiles of 16, so each element of A loaded into LDS feeds NT MFMAs
 // from registers and the skinny operand X is the only operand re-read
 // (from LDS) per row tile.  Tiles are 128 bytes of K per row (BK elements),
-// double-buffered in LDS with rows padded to 144 bytes, which makes the
-// 16-byte operand reads of a 16-lane group cover all 64 banks once.
+// double-buffered in LDS; the 16-byte granules of a row are XOR-swizzled by
+// the row index, so that the 16-byte operand reads (16 rows x 4 granules per
+// wave instruction) and the row-major tile stores are free of bank conflicts
+// (rows padded to 144 bytes, the obvious alternative, still conflict on the
+// reads).
 //
 // MFMA forms (gfx950):  f64 16x16x4,  f32 16x16x4,  bf16 16x16x32,
 // fp8 (E4M3FN) 16x16x128 with unit block scales.  Lane l = 16 g + i supplies
@@ -88,11 +91,23 @@ template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_rt(
 template <int PREC, int NT, bool TRANS> __host__ __device__ constexpr int sk_bm() {
     return 16 * sk_rt<PREC, NT, TRANS>() * (sk_waves<PREC, NT, TRANS>() / sk_wc<PREC, NT, TRANS>());
 }
-constexpr int ROWB = 144;                     // LDS bytes per 128-byte K row (+16 pad)
+// Non-transposed A tiles and all X tiles: rows of 128 bytes of K (eight
+// 16-byte granules, no padding); granule g of row r sits in slot g ^ s(r).
+// s(r) = r & 7 makes the FP32 / FP64 / BF16 fragment reads (16 rows x 4
+// consecutive granules per wave instruction) free of bank conflicts; the FP8
+// reads (granules 2 g and 2 g + 1 of 16 rows) need row bit 3 as well,
+// s(r) = (r ^ (r >> 3)) & 7.  (Both were picked by measuring the bank-conflict
+// counter over all linear maps from row bits to slots; the row-major tile
+// stores are conflict-free with any of them.)
+constexpr int ROWB = 128;
+template <int PREC> __device__ __forceinline__ int sk_off(int r, int g) {
+    const int sw = PREC == P_FP8 ? (r ^ (r >> 3)) : r;
+    return r * ROWB + 16 * (g ^ (sw & 7));
+}
 
 template <int PREC, int NT, bool TRANS>
 __host__ __device__ constexpr int sk_a_bytes() {
-    // Non-transposed (and 1/2-byte transposed) tiles: BM rows of 128 (+16) bytes.
+    // Non-transposed (and 1/2-byte transposed) tiles: BM rows of 128 bytes.
     // F32/F64 transposed tiles: BK rows of BM elements (+16 bytes).
     return (TRANS && (PREC == P_F32 || PREC == P_F64))
                ? SkCfg<PREC>::BK * (sk_bm<PREC, NT, TRANS>() * PrecT<PREC>::SZ + 16)
@@ -106,9 +121,15 @@ __host__ __device__ constexpr int sk_lds_bytes() {
 
 // Swizzled [output row][K] layout of a transposed BF16 / FP8 tile: row r holds
 // 128 bytes of K (eight 16-byte granules); granule g sits in slot
-// g ^ at_swz(r).  SH = 3 for BF16 (a thread's columns are 8 rows apart),
-// 4 for FP8 (16 rows apart).
-template <int SH> __device__ __forceinline__ int at_swz(int r) { return ((r >> 1) ^ (r >> SH)) & 7; }
+// g ^ at_swz(r).  BF16: a thread's columns are 8 rows apart, and the term
+// r >> 3 spreads the rows one 8-byte store instruction writes.  FP8: a
+// thread's columns are 16 rows apart (r >> 4 spreads those); row bits 1-3 map
+// to slot bits 1, 2, 0, which keeps the FP8 fragment reads conflict-free, and
+// row bit 0 is left out so that rows 2 i and 2 i + 1 share a slot: their
+// 4-byte stores then sit a constant 128 bytes apart and pair into one
+// two-address store instruction.
+__device__ __forceinline__ int at_swz_bf16(int r) { return ((r >> 1) ^ (r >> 3)) & 7; }
+__device__ __forceinline__ int at_swz_fp8(int r) { return ((r & 6) ^ ((r >> 3) & 1) ^ (r >> 4)) & 7; }
 constexpr int AT_ROWB = 128;
 
 // Sixteen zero bytes in global memory: out-of-range rows of a full tile are
@@ -310,7 +331,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
             for (int t = 0; t < A_LD; t++) {
                 int c = tid + t * SK_THREADS;
                 int r = c >> 3, ch = c & 7;
-                *reinterpret_cast<i32x4*>(As + r * ROWB + ch * 16) = ra[t];
+                *reinterpret_cast<i32x4*>(As + sk_off<PREC>(r, ch)) = ra[t];
             }
         } else if constexpr (ATRANS_SCALAR) {
 #pragma unroll
@@ -328,7 +349,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 const uint32_t lo = __builtin_amdgcn_perm((uint32_t)ra[1][d], (uint32_t)ra[0][d], sel);
                 const uint32_t hi = __builtin_amdgcn_perm((uint32_t)ra[3][d], (uint32_t)ra[2][d], sel);
                 const int r = ch * 8 + e;
-                *reinterpret_cast<uint2*>(As + r * AT_ROWB + 16 * (g ^ at_swz<3>(r)) + 8 * (q & 1)) =
+                *reinterpret_cast<uint2*>(As + r * AT_ROWB + 16 * (g ^ at_swz_bf16(r)) + 8 * (q & 1)) =
                     make_uint2(lo, hi);
             }
         } else {
@@ -349,7 +370,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
                     const int r = ch * 16 + 4 * d + b;
-                    *reinterpret_cast<uint32_t*>(As + r * AT_ROWB + 16 * (g ^ at_swz<4>(r)) + 4 * (q & 3)) = o[b];
+                    *reinterpret_cast<uint32_t*>(As + r * AT_ROWB + 16 * (g ^ at_swz_fp8(r)) + 4 * (q & 3)) = o[b];
                 }
             }
         }
@@ -358,7 +379,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
             int c = tid + t * SK_THREADS;
             if (c < X_CHUNKS) {
                 int r = c >> 3, ch = c & 7;
-                *reinterpret_cast<i32x4*>(Xs + r * ROWB + ch * 16) = rx[t];
+                *reinterpret_cast<i32x4*>(Xs + sk_off<PREC>(r, ch)) = rx[t];
             }
         }
     };
@@ -391,7 +412,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                     const int orow = wrow + r * 16 + li;
                     if constexpr (!TRANS) {
                         union { i32x4 v; T e[VEC]; } u;
-                        u.v = *reinterpret_cast<const i32x4*>(As + orow * ROWB + kk * SZ);
+                        u.v = *reinterpret_cast<const i32x4*>(As + sk_off<PREC>(orow, kk * SZ / 16));
 #pragma unroll
                         for (int e = 0; e < VEC; e++) av[r][e] = u.e[e];
                     } else {
@@ -412,7 +433,7 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 for (int c = 0; c < NTW; c++) {
                     const int cc = SK_WC == 1 ? c : min(c0 + c, NT - 1);
                     union { i32x4 v; T e[VEC]; } b;
-                    b.v = *reinterpret_cast<const i32x4*>(Xs + (cc * 16 + li) * ROWB + kk * SZ);
+                    b.v = *reinterpret_cast<const i32x4*>(Xs + sk_off<PREC>(cc * 16 + li, kk * SZ / 16));
 #pragma unroll
                     for (int e = 0; e < VEC; e++) bv[c][e] = b.e[e];
                 }
@@ -437,22 +458,21 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 for (int r = 0; r < SK_RT; r++) {
                     const int orow = wrow + r * 16 + li;
                     if constexpr (TRANS)
-                        av[r] = *reinterpret_cast<const bf16x8*>(As + orow * AT_ROWB + 16 * ((kk >> 3) ^ at_swz<3>(orow)));
+                        av[r] = *reinterpret_cast<const bf16x8*>(As + orow * AT_ROWB + 16 * ((kk >> 3) ^ at_swz_bf16(orow)));
                     else
-                        av[r] = *reinterpret_cast<const bf16x8*>(As + orow * ROWB + kk * 2);
+                        av[r] = *reinterpret_cast<const bf16x8*>(As + sk_off<PREC>(orow, kk >> 3));
                 }
 #pragma unroll
                 for (int c = 0; c < NTW; c++) {
                     const int cc = c0 + c;  // column tile (wave-uniform test)
                     if (SK_WC > 1 && cc >= NT) break;
-                    bf16x8 bv = *reinterpret_cast<const bf16x8*>(Xs + (cc * 16 + li) * ROWB + kk * 2);
+                    bf16x8 bv = *reinterpret_cast<const bf16x8*>(Xs + sk_off<PREC>(cc * 16 + li, kk >> 3));
 #pragma unroll
                     for (int r = 0; r < SK_RT; r++)
                         acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bv, acc[r][c], 0, 0, 0);
                 }
             }
-        } else {  // FP8: one MFMA consumes 32 consecutive K bytes per lane
-            const int kk = lg * 32;
+        } else {  // FP8: one MFMA consumes 32 consecutive K bytes (granules 2 lg, 2 lg + 1) per lane
             i32x8 av[SK_RT];
 #pragma unroll
             for (int r = 0; r < SK_RT; r++) {
@@ -460,13 +480,12 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
                 i32x4 lo, hi;
                 if constexpr (TRANS) {
                     const unsigned char* p = As + orow * AT_ROWB;
-                    const int sw = at_swz<4>(orow);
+                    const int sw = at_swz_fp8(orow);
                     lo = *reinterpret_cast<const i32x4*>(p + 16 * ((2 * lg) ^ sw));
                     hi = *reinterpret_cast<const i32x4*>(p + 16 * ((2 * lg + 1) ^ sw));
                 } else {
-                    const unsigned char* p = As + orow * ROWB + kk;
-                    lo = *reinterpret_cast<const i32x4*>(p);
-                    hi = *reinterpret_cast<const i32x4*>(p + 16);
+                    lo = *reinterpret_cast<const i32x4*>(As + sk_off<PREC>(orow, 2 * lg));
+                    hi = *reinterpret_cast<const i32x4*>(As + sk_off<PREC>(orow, 2 * lg + 1));
                 }
                 av[r] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
             }
@@ -474,9 +493,8 @@ __global__ __launch_bounds__((sk_threads<PREC, NT, TRANS>())) void k_sketch(cons
             for (int c = 0; c < NTW; c++) {
                 const int cc = c0 + c;  // column tile (wave-uniform test)
                 if (SK_WC > 1 && cc >= NT) break;
-                const unsigned char* p = Xs + (cc * 16 + li) * ROWB + kk;
-                i32x4 lo = *reinterpret_cast<const i32x4*>(p);
-                i32x4 hi = *reinterpret_cast<const i32x4*>(p + 16);
+                i32x4 lo = *reinterpret_cast<const i32x4*>(Xs + sk_off<PREC>(cc * 16 + li, 2 * lg));
+                i32x4 hi = *reinterpret_cast<const i32x4*>(Xs + sk_off<PREC>(cc * 16 + li, 2 * lg + 1));
                 i32x8 bv = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 #pragma unroll
                 for (int r = 0; r < SK_RT; r++)
