@@ -582,12 +582,16 @@ hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int it
 // ---------------------------------------------------------------------------
 // dst = src S for a block of AP_ROWS = 16 rows, S an l x l FP64 matrix
 // (R^{-1} of a CholeskyQR pass, or Qs for U = Q1 Qs), on the FP64 MFMA
-// (16x16x4).  Wave w owns quarter w of the column tiles; small blocks give
-// several waves per SIMD, so one wave's load latency hides behind another's
-// MFMAs (64-row blocks with four row tiles per wave measured slower).  Lane
-// group g of a wave takes the K slots g KQ + s (KQ = lp / 4, s < KQ): both
-// operands stream from memory into registers (S is small and stays in
-// cache), four K steps per batch with the next batch's loads in flight.  The
+// (16x16x4).  Wave w owns column tiles w, w + 4, w + 8, ...; small blocks
+// give several waves per SIMD, so one wave's load latency hides behind
+// another's MFMAs (64-row blocks with four row tiles per wave measured
+// slower).  K runs in blocks of 16, MFMA step u of block kb taking
+// K = 16 kb + 4 u + g in lane group g: both operands stream from memory into
+// registers (S is small and stays in cache), half a K block per batch with
+// the next batch's loads in flight.  R^{-1} is upper triangular (its lower part
+// is stored as exact zeros), so column tile c only needs K blocks 0 .. c:
+// the R^{-1} stages skip the rest, about half of the MFMAs and of the reads
+// of S, and the interleaved tiles give the four waves similar shares.  The
 // finished 16 x l tile goes through LDS so that dst (row-major) and the
 // transposed operand copy in the pass format are both written with
 // contiguous runs.  H = column tiles per quarter (compile-time bound of the
@@ -614,7 +618,7 @@ __device__ void write_op_rows(const Prob& P, int side, int64_t r0, int nrows, co
 }
 
 template <int MODE, int H>
-__global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
+__global__ __launch_bounds__(256, H <= 4 ? 5 : 1) void k_apply(const Prob* __restrict__ probs,
                                                const int32_t* __restrict__ pidx,
                                                const int32_t* __restrict__ toff, int cnt,
                                                int side, int iter) {
@@ -627,8 +631,6 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
     if (MODE == AP_QA_RINV_Q && !two) return;
     const int l = P.l, lp = P.lp;
     const int nt = lp / 16;
-    const int qn = (nt + 3) / 4;  // column tiles per quarter
-    const int kq = lp / 4;        // K steps
     const int64_t rows = side == SIDE_M ? P.m : P.n;
     const int64_t r0 = (int64_t)local * AP_ROWS;
     const int nrows = (int)min((int64_t)AP_ROWS, rows - r0);
@@ -644,59 +646,70 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int ct0 = wave * qn;
-    const int nct = min(qn, nt - ct0);  // column tiles of this wave (may be <= 0)
+    const int nct = nt > wave ? (nt - wave + 3) / 4 : 0;  // column tiles of this wave (may be 0)
+    // K blocks this wave visits: up to its last column tile when S = R^{-1}
+    // (upper triangular), all of them for U = Q1 Qs
+    constexpr bool TRI = MODE != AP_Q1_QS_U;
+    const int nkb = nct > 0 ? (TRI ? wave + 4 * (nct - 1) + 1 : nt) : 0;
     const int64_t arow = r0 + li;  // row of src this lane feeds
-    const bool arow_ok = arow < rows;
     const double* __restrict__ arp = src + min(arow, rows - 1) * l;  // clamped: loads are unconditional
-    const int kbase = lg * kq;
 
     f64x4 acc[H];
 #pragma unroll
     for (int t = 0; t < H; t++) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-    constexpr int U = 4;
+    // Batches of U MFMA steps (4 K each), BPK = 4 / U batches per K block.
+    // Two steps per batch keep the kernel at 5 waves per SIMD, so that the
+    // 1250 blocks of a 20000-row apply run in one round of the CU slots (four
+    // steps per batch: 3 waves, 1.6 rounds).
+    constexpr int U = 2, BPK = 4 / U;
     double a0[U], a1[U], b0[U][H], b1[U][H];
-    // Loads are unconditional (clamped addresses, masked values) and every
-    // wave runs H tiles (zero operands past its last tile): straight-line code
-    // lets the compiler wait for one batch while the next is in flight.
+#pragma unroll
+    for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int t = 0; t < H; t++) b0[u][t] = b1[u][t] = 0.0;
     // Operands past the matrices come from clamped addresses (junk rows and
     // columns of the tile are never written) except the K slots past l, whose
-    // A operand is read from a zero word: the loads are unconditional, so
-    // straight-line code waits for one batch while the next is in flight.
+    // A operand is read from a zero word.  Tile t of the wave (column tile
+    // wave + 4 t) takes part in K block kb when t < nct and, for triangular
+    // S, kb <= wave + 4 t: a wave-uniform test, so loads and MFMAs of the
+    // skipped blocks are branched over, not masked.
     gdouble* ag = as_global(arp);
     gdouble* Sg = as_global(S);
     gdouble* zw = as_global(g_zero_word);
     int cc[H];
 #pragma unroll
-    for (int t = 0; t < H; t++) cc[t] = min(16 * (ct0 + t) + li, l - 1);
-    auto load = [&](int s0, double (&a)[U], double (&b)[U][H]) {
+    for (int t = 0; t < H; t++) cc[t] = min(16 * (wave + 4 * t) + li, l - 1);
+    auto part = [&](int kb, int t) { return t < nct && (!TRI || kb <= wave + 4 * t); };
+    const int nbat = nkb * BPK;
+    auto load = [&](int bi, double (&a)[U], double (&b)[U][H]) {
+        const int kb = bi / BPK;
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int k = kbase + s0 + u;  // slots past this group's kq belong to the next group
-            const int kc = min(k, l - 1);
-            a[u] = *((s0 + u < kq && k < l) ? ag + k : zw);
-            gdouble* srow = Sg + (int64_t)kc * l;
+            const int k = 16 * kb + 4 * ((bi % BPK) * U + u) + lg;
+            a[u] = *((bi < nbat && k < l) ? ag + k : zw);
+            gdouble* srow = Sg + (int64_t)min(k, l - 1) * l;
 #pragma unroll
-            for (int t = 0; t < H; t++) b[u][t] = srow[cc[t]];
+            for (int t = 0; t < H; t++)
+                if (part(kb, t)) b[u][t] = srow[cc[t]];
         }
     };
-    // Two register buffers in turn, every prefetch unconditional (K slots past
-    // l or past the group's kq read the zero word): the compiler then waits
-    // exactly for the older batch while the newer one is in flight.
+    auto step = [&](int bi, const double (&a)[U], const double (&b)[U][H]) {
+        const int kb = bi / BPK;
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int t = 0; t < H; t++)
+                if (bi < nbat && part(kb, t))
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u][t], acc[t], 0, 0, 0);
+    };
+    // Two register buffers in turn: the compiler waits for the older batch
+    // while the newer one is in flight.
     load(0, a0, b0);
-    for (int s0 = 0; s0 < (nct > 0 ? kq : 0); s0 += 2 * U) {
-        load(s0 + U, a1, b1);
-#pragma unroll
-        for (int u = 0; u < U; u++)
-#pragma unroll
-            for (int t = 0; t < H; t++)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u][t], acc[t], 0, 0, 0);
-        load(s0 + 2 * U, a0, b0);
-#pragma unroll
-        for (int u = 0; u < U; u++)
-#pragma unroll
-            for (int t = 0; t < H; t++)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u][t], acc[t], 0, 0, 0);
+    for (int bi = 0; bi < nbat; bi += 2) {
+        load(bi + 1, a1, b1);
+        step(bi, a0, b0);
+        load(bi + 2, a0, b0);
+        step(bi + 1, a1, b1);
     }
     // f64 MFMA output: lane (i, g), entry e -> row g + 4e, column i of the tile.
     double* xs = lds;  // 16 x lp
@@ -705,7 +718,7 @@ __global__ __launch_bounds__(256) void k_apply(const Prob* __restrict__ probs,
         if (t < nct)
 #pragma unroll
             for (int e = 0; e < 4; e++)
-                xs[(lg + 4 * e) * lp + 16 * (ct0 + t) + li] = acc[t][e];
+                xs[(lg + 4 * e) * lp + 16 * (wave + 4 * t) + li] = acc[t][e];
     __syncthreads();
     if (MODE == AP_Y_RINV_QA && two) {
         // First factor of the final orthonormalisation.  Rank-deficient
