@@ -313,23 +313,26 @@ hipError_t launch_sum(const LaunchGroup& g, int side, int iter, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Gram partial sums G_b = Z_b^T Z_b of a row chunk Z_b of an FP64 rows x l
-// matrix, on FP64 MFMA 16x16x4.  A block is (row chunk, one upper 16x16
-// tile); its four waves take consecutive quarters of the chunk's rows and
-// stream them from memory straight into MFMA operands (16 lanes read 128
-// contiguous bytes of a row), eight K steps per batch with the next batch's
-// loads in flight; the four partial tiles are added in LDS in wave order (a
-// fixed summation order).  Partials: gpart[chunk][l][l], upper tiles only
-// (every entry with a <= b is written).  The grid is chunks x tiles blocks.
+// matrix, on FP64 MFMA 16x16x4.  A block is (row chunk, one upper 2 x 2
+// group of 16x16 tiles); its four waves take consecutive quarters of the
+// chunk's rows and stream them from memory straight into MFMA operands (16
+// lanes read 128 contiguous bytes of a row): two column fragments of each
+// side feed the four tiles' MFMAs, so every operand loaded serves two MFMAs
+// (one tile per block: one MFMA per operand, and the L2 traffic was twice
+// as high).  Four K steps per batch with the next batch's loads in flight;
+// the four partial tiles are added in LDS in wave order (a fixed summation
+// order).  Partials: gpart[chunk][l][l], upper tiles only (every entry with
+// a <= b is written).  The grid is chunks x tile groups blocks.
 // ---------------------------------------------------------------------------
 // A zero in global memory: operands outside a matrix are loaded from here (an
 // address select instead of a branch or a mask on the loaded value).  Never
 // written.
 __device__ double g_zero_word[2] = {0.0, 0.0};
 
-static_assert(GRAM_THREADS == 256, "four waves per Gram tile");
+static_assert(GRAM_THREADS == 256, "four waves per Gram tile group");
 
 __device__ __forceinline__ void tile_of(int t, int nt, int& ta, int& tb) {
-    // t-th upper tile (ta <= tb) in row-major order over ta.
+    // t-th upper tile (ta <= tb) of an nt x nt grid in row-major order over ta.
     int a = 0, rem = t;
     while (rem >= nt - a) { rem -= nt - a; a++; }
     ta = a;
@@ -341,7 +344,7 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
                                                       const int32_t* __restrict__ pidx,
                                                       const int32_t* __restrict__ toff, int cnt,
                                                       int side, int iter) {
-    __shared__ double part[3][4][64];
+    __shared__ double part[3][4][4][64];  // waves 1-3 x tiles x MFMA entries
     int local;
     const Prob& P = group_prob(probs, pidx, toff, cnt, local);
     constexpr bool CROSS = SRC == GSRC_XM || SRC == GSRC_XA;
@@ -351,8 +354,9 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     if (SRC == GSRC_XY && (!P.fused || iter >= P.q)) return;
     const int l = P.l, lp = P.lp;
     const int nt = lp / 16;
-    // symmetric Grams: the upper tiles; cross products Z1^T Z2: every tile
-    const int ntu = CROSS ? nt * nt : nt * (nt + 1) / 2;
+    const int ns = (nt + 1) / 2;  // groups of 2 x 2 tiles per side
+    // symmetric Grams: the upper groups; cross products Z1^T Z2: every group
+    const int ntu = CROSS ? ns * ns : ns * (ns + 1) / 2;
     const int gb = side == SIDE_M ? P.gb_m : P.gb_n;
     // Blocks are handed to the eight XCDs in turn (block b to XCD b mod 8),
     // each with its own L2: with a multiple of 8 chunks, chunk c's tiles all
@@ -383,58 +387,92 @@ __global__ __launch_bounds__(GRAM_THREADS) void k_gram(const Prob* __restrict__ 
     const int64_t qr = (((c1 - c0) + 3) / 4 + 3) / 4 * 4;
     const int64_t r0 = c0 + wave * qr;
     const int64_t r1 = min(c1, r0 + qr);
-    int ta, tb;
+    int sa, sb;
     if (CROSS) {
-        ta = tt / nt;
-        tb = tt - ta * nt;
+        sa = tt / ns;
+        sb = tt - sa * ns;
     } else {
-        tile_of(tt, nt, ta, tb);
+        tile_of(tt, ns, sa, sb);
     }
-    const int ca = 16 * ta + li, cb = 16 * tb + li;
-    const bool okb = cb < l;
+    // tiles (2 sa + i, 2 sb + j); of a diagonal group of a symmetric Gram the
+    // tile below the diagonal is skipped, as are tiles past the last one
+    auto live = [&](int i, int j) {
+        return 2 * sa + i < nt && 2 * sb + j < nt && (CROSS || sa != sb || i <= j);
+    };
     // MFMA K slot g of step s is row rs + 4 s + g; U steps per batch, the next
     // batch's loads in flight while this batch's MFMAs run.
-    constexpr int U = 8;
-    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
-    double xa[U], xb[U], ya[U], yb[U];
+    constexpr int U = 2;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double xa[U][2], xb[U][2], ya[U][2], yb[U][2];
     // Loads are unconditional: columns past l are read at column l - 1 (their
     // tile entries are never written); rows past the wave's range are read
     // from a zero word.  Straight-line code lets the compiler wait for the
     // older batch while the newer one is in flight.
-    const int cac = min(ca, l - 1), cbc = min(cb, l - 1);
+    int cac[2], cbc[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        cac[i] = min(16 * (2 * sa + i) + li, l - 1);
+        cbc[i] = min(16 * (2 * sb + i) + li, l - 1);
+    }
     gdouble* Zg = as_global(Z);
     gdouble* Z2g = as_global(Z2);
     gdouble* zw = as_global(g_zero_word);
-    auto load = [&](int64_t rs, double (&va)[U], double (&vb)[U]) {
+    auto load = [&](int64_t rs, double (&va)[U][2], double (&vb)[U][2]) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int64_t r = rs + 4 * u + lg;
             const bool okr = r < r1;
-            va[u] = *(okr ? Zg + r * l + cac : zw);
-            vb[u] = *(okr ? Z2g + r * l + cbc : zw);
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                va[u][i] = *(okr ? Zg + r * l + cac[i] : zw);
+                vb[u][i] = *(okr ? Z2g + r * l + cbc[i] : zw);
+            }
         }
+    };
+    auto step = [&](const double (&va)[U][2], const double (&vb)[U][2]) {
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+                    if (live(i, j)) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u][i], vb[u][j], acc[i][j], 0, 0, 0);
     };
     load(r0, xa, xb);
     for (int64_t rs = r0; rs < r1; rs += 8 * U) {
         load(rs + 4 * U, ya, yb);
-#pragma unroll
-        for (int u = 0; u < U; u++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u], xb[u], acc, 0, 0, 0);
+        step(xa, xb);
         load(rs + 8 * U, xa, xb);
-#pragma unroll
-        for (int u = 0; u < U; u++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[u], yb[u], acc, 0, 0, 0);
+        step(ya, yb);
     }
     if (wave > 0)
 #pragma unroll
-        for (int e = 0; e < 4; e++) part[wave - 1][e][lane] = acc[e];
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) part[wave - 1][2 * i + j][e][lane] = acc[i][j][e];
     __syncthreads();
     if (wave != 0) return;
     double* out = P.gpart + (int64_t)chunk * l * l;
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
-        const double v = ((acc[e] + part[0][e][lane]) + part[1][e][lane]) + part[2][e][lane];
-        const int ga = 16 * ta + lg + 4 * e;  // f64 MFMA output row
-        if (ga < l && okb) out[(int64_t)ga * l + cb] = v;
-    }
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            if (!live(i, j)) continue;
+            const int cb = 16 * (2 * sb + j) + li;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int q = 2 * i + j;
+                const double v = ((acc[i][j][e] + part[0][q][e][lane]) + part[1][q][e][lane]) + part[2][q][e][lane];
+                const int ga = 16 * (2 * sa + i) + lg + 4 * e;  // f64 MFMA output row
+                if (ga < l && cb < l) out[(int64_t)ga * l + cb] = v;
+            }
+        }
 }
 
 template <int SRC>

@@ -135,9 +135,10 @@ static int32_t scale_chunks(int64_t rows) {
     return (int32_t)std::min<int64_t>(SCALE_CHUNKS, std::max<int64_t>(1, cdiv(rows, 128)));
 }
 
-static int gram_groups(int lp) {  // blocks per row chunk: the upper 16 x 16 tiles
-    const int nt = lp / 16;
-    return nt * (nt + 1) / 2;
+static int gram_side(int lp) { return (lp / 16 + 1) / 2; }  // 2 x 2 tile groups per side
+static int gram_groups(int lp) {  // blocks per row chunk: the upper 2 x 2 tile groups
+    const int ns = gram_side(lp);
+    return ns * (ns + 1) / 2;
 }
 
 static void gram_chunks(int64_t rows, int lp, int target, int32_t* rb, int32_t* gb) {
@@ -511,9 +512,9 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
     auto R_r2 = per([&](int i) { return (int64_t)P->lay[i].nt * P->lay[i].nt; });
     auto R_norm = per([&](int) { return (int64_t)64; });
     auto R_xgM = per([&](int i) {
-        return mmode == M_EXPLICIT ? (int64_t)P->lay[i].gb_m * P->lay[i].nt * P->lay[i].nt : 0; });
+        return mmode == M_EXPLICIT ? (int64_t)P->lay[i].gb_m * gram_side(P->lay[i].lp) * gram_side(P->lay[i].lp) : 0; });
     auto R_xgN = per([&](int i) {
-        return mmode == M_APPROX ? (int64_t)P->lay[i].gb_n * P->lay[i].nt * P->lay[i].nt : 0; });
+        return mmode == M_APPROX ? (int64_t)P->lay[i].gb_n * gram_side(P->lay[i].lp) * gram_side(P->lay[i].lp) : 0; });
     auto R_xred = per([&](int i) {
         return mmode != M_R2T ? cdiv((int64_t)P->lay[i].l * P->lay[i].l, 64) : 0; });
     auto R_keepx = per([&](int i) {
