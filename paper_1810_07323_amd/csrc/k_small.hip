@@ -10,6 +10,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <utility>
 
 namespace cor {
 
@@ -110,11 +111,50 @@ struct CholShared {
     int clamped;
 };
 
+// Lane J of each 16-lane row of the wave, to every lane of that row (DPP
+// row_newbcast: one 64-bit VGPR move, no trip through scalar registers).
+template <int J> __device__ __forceinline__ double row_bcast(double v) {
+    return __longlong_as_double(__builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + J, 0xF, 0xF, false));
+}
+
+// Pivot step J of chol_factor16 (lane a of each 16 holds row a in t).  Every
+// lane runs it (the broadcasts read lane J, which must be active); rows at or
+// above the pivot take m = 0, which leaves them unchanged.  Each broadcast
+// feeds its FMA at once, so only one row value is live at a time.
+template <int J>
+__device__ __forceinline__ void chol_pivot16(double (&t)[16], int a, int K, int n, double tol,
+                                             double& myd, double& myy, bool& myck) {
+    const double raw = row_bcast<J>(t[J]);
+    const double d = fmax(raw, tol);
+    const bool ck = !(raw > tol) && 16 * K + J < n;
+    const double y = recip3(d);
+    if (a == J) {
+        myd = d;
+        myy = y;
+        myck = ck;
+    }
+    const bool below = a > J;
+    const double m = below ? t[J] * y : 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; c++)
+        if (c != J) t[c] = fma(-m, row_bcast<J>(t[c]), t[c]);
+    if (below) t[J] = -m;
+}
+
+template <int... J>
+__device__ __forceinline__ void chol_pivots16(double (&t)[16], int a, int K, int n, double tol,
+                                              double& myd, double& myy, bool& myck,
+                                              std::integer_sequence<int, J...>) {
+    (chol_pivot16<J>(t, a, K, n, tol, myd, myy, myck), ...);
+}
+
 // A: factor diagonal tile K (x: upper triangle = Schur complement, strict
 // lower triangle zero).  Lane a (of each 16) keeps row a of the symmetric
 // block in t[0..15]; entries left of the diagonal turn into the E row as
 // their pivot step passes (t[j] = -m), so a pivot step is the same fifteen
-// FMAs t[c] -= m t_j[c] for every c != j in every row below the pivot.
+// FMAs t[c] -= m t_j[c] for every c != j in every row below the pivot.  Row j
+// reaches the other lanes of its 16 by DPP broadcasts (16 VGPR moves per
+// step; 32 scalar read-lanes took about twice as long per step).
 __device__ __forceinline__ void chol_factor16(f64x4& x, int K, int n, double tol, int g, int i,
                                               CholShared& sh) {
     const int lane = threadIdx.x & 63, a = lane & 15;
@@ -127,29 +167,7 @@ __device__ __forceinline__ void chol_factor16(f64x4& x, int K, int n, double tol
     for (int c = 0; c < 16; c++) t[c] = c >= a ? dt[a][c] : dt[c][a];
     double myd = 0.0, myy = 0.0;
     bool myck = false;
-#pragma unroll
-    for (int j = 0; j < 16; j++) {
-        const double raw = readlane_d(t[j], j);
-        double rt[16];
-#pragma unroll
-        for (int c = 0; c < 16; c++)
-            if (c != j) rt[c] = readlane_d(t[c], j);
-        const double d = fmax(raw, tol);
-        const bool ck = !(raw > tol) && 16 * K + j < n;
-        const double y = recip3(d);
-        if (a == j) {
-            myd = d;
-            myy = y;
-            myck = ck;
-        }
-        if (a > j) {
-            const double m = t[j] * y;
-#pragma unroll
-            for (int c = 0; c < 16; c++)
-                if (c != j) t[c] = fma(-m, rt[c], t[c]);
-            t[j] = -m;
-        }
-    }
+    chol_pivots16(t, a, K, n, tol, myd, myy, myck, std::make_integer_sequence<int, 16>{});
     if (lane < 16) {
 #pragma unroll
         for (int c = 0; c < 16; c++) dt[a][c] = t[c];
