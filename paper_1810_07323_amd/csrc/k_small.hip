@@ -117,14 +117,26 @@ template <int J> __device__ __forceinline__ double row_bcast(double v) {
     return __longlong_as_double(__builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + J, 0xF, 0xF, false));
 }
 
-// Pivot step J of chol_factor16 (lane a of each 16 holds row a in t).  Every
-// lane runs it (the broadcasts read lane J, which must be active); rows at or
-// above the pivot take m = 0, which leaves them unchanged.  Each broadcast
-// feeds its FMA at once, so only one row value is live at a time.
+// Value v of lane `src` of the wave (any lane; all lanes must be active).
+__device__ __forceinline__ double lane_fetch(double v, int src) {
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Pivot step J of chol_factor16.  Lane (g, a) of the wave holds columns
+// 4 g .. 4 g + 3 of row a in t[0..3].  The pivot row's four values for those
+// columns come from lane J of the lane's own 16-lane row (DPP broadcast), the
+// pivot from lane (J / 4, J), and the lane's own entry in column J from lane
+// (J / 4, a).  Every lane runs the step (the broadcasts read other lanes,
+// which must be active); rows at or above the pivot take m = 0, which leaves
+// them unchanged.
 template <int J>
-__device__ __forceinline__ void chol_pivot16(double (&t)[16], int a, int K, int n, double tol,
+__device__ __forceinline__ void chol_pivot16(double (&t)[4], int g, int a, int K, int n, double tol,
                                              double& myd, double& myy, bool& myck) {
-    const double raw = row_bcast<J>(t[J]);
+    constexpr int JG = J >> 2, JQ = J & 3;
+    const double raw = readlane_d(t[JQ], 16 * JG + J);
+    const double colj = lane_fetch(t[JQ], 16 * JG + a);
     const double d = fmax(raw, tol);
     const bool ck = !(raw > tol) && 16 * K + J < n;
     const double y = recip3(d);
@@ -134,27 +146,32 @@ __device__ __forceinline__ void chol_pivot16(double (&t)[16], int a, int K, int 
         myck = ck;
     }
     const bool below = a > J;
-    const double m = below ? t[J] * y : 0.0;
+    const double m = below ? colj * y : 0.0;
 #pragma unroll
-    for (int c = 0; c < 16; c++)
-        if (c != J) t[c] = fma(-m, row_bcast<J>(t[c]), t[c]);
-    if (below) t[J] = -m;
+    for (int q = 0; q < 4; q++) {
+        const double u = fma(-m, row_bcast<J>(t[q]), t[q]);
+        // column J itself (lane group J / 4, slot J % 4) becomes -m below the pivot
+        t[q] = (q == JQ && g == JG) ? (below ? -m : t[q]) : u;
+    }
 }
 
 template <int... J>
-__device__ __forceinline__ void chol_pivots16(double (&t)[16], int a, int K, int n, double tol,
+__device__ __forceinline__ void chol_pivots16(double (&t)[4], int g, int a, int K, int n, double tol,
                                               double& myd, double& myy, bool& myck,
                                               std::integer_sequence<int, J...>) {
-    (chol_pivot16<J>(t, a, K, n, tol, myd, myy, myck), ...);
+    (chol_pivot16<J>(t, g, a, K, n, tol, myd, myy, myck), ...);
 }
 
 // A: factor diagonal tile K (x: upper triangle = Schur complement, strict
-// lower triangle zero).  Lane a (of each 16) keeps row a of the symmetric
-// block in t[0..15]; entries left of the diagonal turn into the E row as
-// their pivot step passes (t[j] = -m), so a pivot step is the same fifteen
-// FMAs t[c] -= m t_j[c] for every c != j in every row below the pivot.  Row j
-// reaches the other lanes of its 16 by DPP broadcasts (16 VGPR moves per
-// step; 32 scalar read-lanes took about twice as long per step).
+// lower triangle zero).  Row a of the symmetric block is spread over the four
+// lane groups (lane (g, a): columns 4 g .. 4 g + 3); entries left of the
+// diagonal turn into the E row as their pivot step passes (t = -m), so a
+// pivot step is the same FMA t_c -= m t_j[c] for every column c != j in every
+// row below the pivot, four per lane.  Row j reaches the lanes by DPP
+// broadcasts within each 16-lane row, column j by one cross-row permute.
+// (With every lane holding a whole row, 16 FMAs and 16 broadcasts per lane and
+// step, a tile took 2.9 us; 32 scalar read-lanes per step instead of the
+// broadcasts, 3.2 us.)
 __device__ __forceinline__ void chol_factor16(f64x4& x, int K, int n, double tol, int g, int i,
                                               CholShared& sh) {
     const int lane = threadIdx.x & 63, a = lane & 15;
@@ -162,15 +179,19 @@ __device__ __forceinline__ void chol_factor16(f64x4& x, int K, int n, double tol
 #pragma unroll
     for (int r = 0; r < 4; r++) dt[4 * r + g][i] = x[r];
     wave_lds_sync();
-    double t[16];
+    double t[4];
 #pragma unroll
-    for (int c = 0; c < 16; c++) t[c] = c >= a ? dt[a][c] : dt[c][a];
+    for (int q = 0; q < 4; q++) {
+        const int c = 4 * g + q;
+        t[q] = c >= a ? dt[a][c] : dt[c][a];
+    }
     double myd = 0.0, myy = 0.0;
     bool myck = false;
-    chol_pivots16(t, a, K, n, tol, myd, myy, myck, std::make_integer_sequence<int, 16>{});
-    if (lane < 16) {
+    chol_pivots16(t, g, a, K, n, tol, myd, myy, myck, std::make_integer_sequence<int, 16>{});
+    wave_lds_sync();  // every lane has read dt before it is overwritten
 #pragma unroll
-        for (int c = 0; c < 16; c++) dt[a][c] = t[c];
+    for (int q = 0; q < 4; q++) dt[a][4 * g + q] = t[q];
+    if (lane < 16) {
         sh.inv[K & 1][a] = myy;
         sh.d[16 * K + a] = myd;
         sh.dm[16 * K + a] = myck ? 1.0 : 0.0;
