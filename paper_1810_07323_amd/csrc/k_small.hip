@@ -541,8 +541,17 @@ __global__ __launch_bounds__(CRT_THREADS) void k_chol_rt(const Prob* __restrict_
     if (tid == 0) s_clamped_any = 0;
     if (k == 0) {
         if (tid < 64) {
+            // the diagonal's loads all issued before the first is used
+            constexpr int NU = (LMAX + 63) / 64;
+            double dv[NU];
+#pragma unroll
+            for (int u = 0; u < NU; u++) {
+                const int i = tid + 64 * u;
+                dv[u] = i < l ? fabs(G[i * l + i]) : 0.0;
+            }
             double mx = 0.0;
-            for (int i = tid; i < l; i += 64) mx = fmax(mx, fabs(G[i * l + i]));
+#pragma unroll
+            for (int u = 0; u < NU; u++) mx = fmax(mx, dv[u]);
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
             if (tid == 0) {
