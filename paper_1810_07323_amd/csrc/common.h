@@ -164,6 +164,12 @@ __device__ __forceinline__ double sum8_dpp(double v) {
     v += dpp_mov<0x141>(v);
     return v;
 }
+// Sum over each 16-lane row (the 8-lane sums, then the mirrored half).
+__device__ __forceinline__ double sum16_dpp(double v) {
+    v = sum8_dpp(v);
+    v += dpp_mov<0x140>(v);
+    return v;
+}
 
 // Binary32 -> bfloat16, round to nearest even (NaN kept quiet).
 __device__ __forceinline__ uint16_t f32_to_bf16(float x) {

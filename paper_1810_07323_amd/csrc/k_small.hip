@@ -1780,19 +1780,27 @@ hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
 // The reflectors of the QRCP applied to rows: where u_via_qs, to the rows of
 // the l x l identity, giving Qs = H_0 H_1 ... H_{l-1} diag(sign) in G (free
 // after the last Cholesky), and U = Q1 Qs is then one FP64 MFMA product
-// (k_apply); otherwise straight to the rows of Q1, giving U.  Eight lanes share a
-// row; lane k holds the entries a = k (mod 8) in registers, so a reflector
-// costs a dot product (four partial sums), a three-step shuffle reduction and
-// an axpy.  The reflectors stream through LDS in panels of 32.
+// (k_apply); otherwise straight to the rows of Q1, giving U.  Sixteen lanes
+// share a row; lane k holds the entries a = k (mod 16) in registers, so a
+// reflector costs a dot product (four partial sums), a four-step DPP
+// reduction and an axpy.  Each row is a chain of l dependent reflectors, so
+// the time is that chain's, and work-groups of 16 rows put one wave on each
+// SIMD: 65 us at l = 220 (99 us with 8 lanes per row in 32-row groups, 81 us
+// with 16 lanes per row in 32-row groups, two waves per SIMD).  The
+// reflectors stream through LDS in panels of 32; the next reflector's entries
+// are read while the current one is applied.
 // ---------------------------------------------------------------------------
-constexpr int FU_ROWS = 32;
+constexpr int FU_ROWS = FORMQS_ROWS;              // 16
 constexpr int FU_PANEL = 32;
+constexpr int FU_LANES = 16;                      // lanes per row
+constexpr int FU_THREADS = FU_ROWS * FU_LANES;    // 256
+constexpr int FU_TNMAX = (LMAX + FU_LANES - 1) / FU_LANES;
 
 template <int TN>
-__global__ __launch_bounds__(256) void k_form_qs(const Prob* __restrict__ probs,
+__global__ __launch_bounds__(FU_THREADS) void k_form_qs(const Prob* __restrict__ probs,
                                                 const int32_t* __restrict__ pidx,
                                                 const int32_t* __restrict__ toff, int cnt) {
-    constexpr int LPAD = 8 * TN;                   // reflector rows padded with zeros
+    constexpr int LPAD = FU_LANES * TN;            // reflector rows padded with zeros
     extern __shared__ __align__(16) double vt[];   // FU_PANEL x LPAD
     __shared__ double s_tau[FU_PANEL];
     int local;
@@ -1800,62 +1808,69 @@ __global__ __launch_bounds__(256) void k_form_qs(const Prob* __restrict__ probs,
     const int l = P.l;
     const bool ident = u_via_qs(P.m, l);
     const int tid = threadIdx.x;
-    const int rr = tid >> 3, k = tid & 7;
+    const int rr = tid / FU_LANES, k = tid % FU_LANES;
     const int64_t row = (int64_t)local * FU_ROWS + rr;
     const bool rv = row < (ident ? (int64_t)l : P.m);
     double u[TN];
 #pragma unroll
     for (int t = 0; t < TN; t++) {
-        const int a = k + 8 * t;
+        const int a = k + FU_LANES * t;
         u[t] = ident ? ((rv && a == row) ? 1.0 : 0.0) : ((rv && a < l) ? P.Q1[row * l + a] : 0.0);
     }
     for (int j0 = 0; j0 < l; j0 += FU_PANEL) {
         const int pj = min(FU_PANEL, l - j0);
         __syncthreads();
         {
-            // the panel (FU_PANEL x LPAD = 256 TN entries): TN loads per
-            // thread, all in flight (entries outside Qt read a zero word)
-            static_assert(FU_PANEL * 8 == 256, "TN entries of a panel per thread");
+            // the panel (FU_PANEL x LPAD entries, NLD per thread), all
+            // loads in flight (entries outside Qt read a zero word)
+            constexpr int NLD = FU_PANEL * LPAD / FU_THREADS;
+            static_assert(NLD * FU_THREADS == FU_PANEL * LPAD, "whole panel entries per thread");
             gdouble* qt = as_global(P.Qt);
             gdouble* zw = as_global(g_zero_chol);
-            double pv[TN];
+            double pv[NLD];
 #pragma unroll
-            for (int u = 0; u < TN; u++) {
-                const int e = tid + 256 * u;
+            for (int u = 0; u < NLD; u++) {
+                const int e = tid + FU_THREADS * u;
                 const int jj = e / LPAD, a = e - (e / LPAD) * LPAD;
                 pv[u] = *((jj < pj && a < l) ? qt + (int64_t)(j0 + jj) * l + a : zw);
             }
 #pragma unroll
-            for (int u = 0; u < TN; u++) vt[tid + 256 * u] = pv[u];
+            for (int u = 0; u < NLD; u++) vt[tid + FU_THREADS * u] = pv[u];
         }
         if (tid < pj) s_tau[tid] = P.tau[j0 + tid];
         __syncthreads();
-        for (int jj = 0; jj < pj; jj++) {
-            const double* v = vt + jj * LPAD + k;
-            double vv[TN];
+        // the next reflector's entries are read while this one is applied
+        double vv[TN];
 #pragma unroll
-            for (int t = 0; t < TN; t++) vv[t] = v[8 * t];
+        for (int t = 0; t < TN; t++) vv[t] = vt[k + FU_LANES * t];
+        for (int jj = 0; jj < pj; jj++) {
+            const double* vnx = vt + min(jj + 1, pj - 1) * LPAD + k;
+            double vn[TN];
+#pragma unroll
+            for (int t = 0; t < TN; t++) vn[t] = vnx[FU_LANES * t];
             double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int t = 0; t < TN; t++) d4[t & 3] = fma(u[t], vv[t], d4[t & 3]);
-            const double d = sum8_dpp((d4[0] + d4[1]) + (d4[2] + d4[3]));
+            const double d = sum16_dpp((d4[0] + d4[1]) + (d4[2] + d4[3]));
             const double w = s_tau[jj] * d;
 #pragma unroll
             for (int t = 0; t < TN; t++) u[t] -= w * vv[t];
+#pragma unroll
+            for (int t = 0; t < TN; t++) vv[t] = vn[t];
         }
     }
     if (!rv) return;
 #pragma unroll
     for (int t = 0; t < TN; t++) {
-        const int a = k + 8 * t;
+        const int a = k + FU_LANES * t;
         if (a < l) (ident ? P.G : P.U)[row * l + a] = u[t] * P.tau[LMAX + a];
     }
 }
 
 hipError_t launch_form_qs(const LaunchGroup& g, int l, hipStream_t s) {
     if (g.blocks <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * FU_PANEL * 8 * 33;
-    const int tn = (l + 7) / 8;
+    const size_t lds = sizeof(double) * FU_PANEL * FU_LANES * FU_TNMAX;
+    const int tn = (l + FU_LANES - 1) / FU_LANES;
 #define FU_CASE(N)                                                                              \
     if (tn <= N) {                                                                              \
         static bool attr = false;                                                               \
@@ -1866,11 +1881,12 @@ hipError_t launch_form_qs(const LaunchGroup& g, int l, hipStream_t s) {
             if (e != hipSuccess) return e;                                                      \
             attr = true;                                                                        \
         }                                                                                       \
-        hipLaunchKernelGGL(k_form_qs<N>, dim3(g.blocks), dim3(256), lds, s, g.probs, g.pidx,     \
+        hipLaunchKernelGGL(k_form_qs<N>, dim3(g.blocks), dim3(FU_THREADS), lds, s, g.probs,      \
+                           g.pidx,                                                              \
                            g.toff, g.count);                                                    \
         return hipGetLastError();                                                               \
     }
-    FU_CASE(4) FU_CASE(8) FU_CASE(16) FU_CASE(24) FU_CASE(33)
+    FU_CASE(2) FU_CASE(4) FU_CASE(8) FU_CASE(12) FU_CASE(FU_TNMAX)
 #undef FU_CASE
     return hipErrorInvalidValue;
 }

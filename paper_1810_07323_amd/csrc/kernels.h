@@ -67,6 +67,8 @@ constexpr int MO_ROWS = 64;
 constexpr int MO_COLS = 16;
 // dst = src R^{-1}, row blocks of APPLY_ROWS; lmax = largest l of the group.
 constexpr int APPLY_ROWS = 16;
+// Rows per work-group of the reflector product (k_form_qs).
+constexpr int FORMQS_ROWS = 16;
 enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2,
                            AP_Q1_QS_U = 3,   // U = Q1 Qs (Qs in G, after the QRCP)
                            AP_Y_RINV_Y = 4 };  // Y <- Y R1^{-1} in place (fused power step)
