@@ -1784,23 +1784,25 @@ hipError_t launch_qrcp(const LaunchGroup& g, int lmax, hipStream_t s) {
 // share a row; lane k holds the entries a = k (mod 16) in registers, so a
 // reflector costs a dot product (four partial sums), a four-step DPP
 // reduction and an axpy.  Each row is a chain of l dependent reflectors, so
-// the time is that chain's, and work-groups of 16 rows put one wave on each
-// SIMD: 65 us at l = 220 (99 us with 8 lanes per row in 32-row groups, 81 us
-// with 16 lanes per row in 32-row groups, two waves per SIMD).  The
-// reflectors stream through LDS in panels of 32; the next reflector's entries
-// are read while the current one is applied.
+// the time is that chain's, and for l > 128 work-groups of 16 rows put one
+// wave on each SIMD: 65 us at l = 220 (99 us with 8 lanes per row in 32-row
+// groups, 81 us with 16 lanes per row in 32-row groups, two waves per SIMD).
+// Smaller l keeps 32-row groups (half the reflector panel loads for the many
+// rows of Q1 or of a batch of small problems).  The reflectors stream
+// through LDS in panels of 32; the next reflector's entries are read while
+// the current one is applied.
 // ---------------------------------------------------------------------------
-constexpr int FU_ROWS = FORMQS_ROWS;              // 16
 constexpr int FU_PANEL = 32;
 constexpr int FU_LANES = 16;                      // lanes per row
-constexpr int FU_THREADS = FU_ROWS * FU_LANES;    // 256
 constexpr int FU_TNMAX = (LMAX + FU_LANES - 1) / FU_LANES;
 
 template <int TN>
-__global__ __launch_bounds__(FU_THREADS) void k_form_qs(const Prob* __restrict__ probs,
+__global__ __launch_bounds__(formqs_rows(FU_LANES * TN) * FU_LANES) void k_form_qs(const Prob* __restrict__ probs,
                                                 const int32_t* __restrict__ pidx,
                                                 const int32_t* __restrict__ toff, int cnt) {
     constexpr int LPAD = FU_LANES * TN;            // reflector rows padded with zeros
+    constexpr int FU_ROWS = formqs_rows(LPAD);     // rows per work-group
+    constexpr int FU_THREADS = FU_ROWS * FU_LANES;
     extern __shared__ __align__(16) double vt[];   // FU_PANEL x LPAD
     __shared__ double s_tau[FU_PANEL];
     int local;
@@ -1881,7 +1883,8 @@ hipError_t launch_form_qs(const LaunchGroup& g, int l, hipStream_t s) {
             if (e != hipSuccess) return e;                                                      \
             attr = true;                                                                        \
         }                                                                                       \
-        hipLaunchKernelGGL(k_form_qs<N>, dim3(g.blocks), dim3(FU_THREADS), lds, s, g.probs,      \
+        hipLaunchKernelGGL(k_form_qs<N>, dim3(g.blocks), dim3(formqs_rows(FU_LANES * N) * FU_LANES), \
+                           lds, s, g.probs,                                                     \
                            g.pidx,                                                              \
                            g.toff, g.count);                                                    \
         return hipGetLastError();                                                               \

@@ -67,8 +67,10 @@ constexpr int MO_ROWS = 64;
 constexpr int MO_COLS = 16;
 // dst = src R^{-1}, row blocks of APPLY_ROWS; lmax = largest l of the group.
 constexpr int APPLY_ROWS = 16;
-// Rows per work-group of the reflector product (k_form_qs).
-constexpr int FORMQS_ROWS = 16;
+// Rows per work-group of the reflector product (k_form_qs): 16 for l > 128
+// (one wave per SIMD on the few rows of Qs), 32 below (many rows of Q1 or of
+// a batch's small problems: half the reflector panel loads).
+__host__ __device__ constexpr int formqs_rows(int l) { return l > 128 ? 16 : 32; }
 enum ApplyMode : int32_t { AP_Y_RINV_QA = 0, AP_QA_RINV_Q = 1, AP_Y_RINV_Q = 2,
                            AP_Q1_QS_U = 3,   // U = Q1 Qs (Qs in G, after the QRCP)
                            AP_Y_RINV_Y = 4 };  // Y <- Y R1^{-1} in place (fused power step)

@@ -539,7 +539,8 @@ cor_status plan_create(const cor_problem* probs, int32_t count, const cor_opts* 
         std::vector<int64_t> b;
         int lmax = 0;
         for (int i : kv.second) {
-            b.push_back(cdiv(u_via_qs(probs[i].m, P->lay[i].l) ? (int64_t)P->lay[i].l : probs[i].m, FORMQS_ROWS));
+            b.push_back(cdiv(u_via_qs(probs[i].m, P->lay[i].l) ? (int64_t)P->lay[i].l : probs[i].m,
+                             formqs_rows(kv.first > 16 ? 129 : 128)));
             lmax = std::max(lmax, (int)P->lay[i].l);
         }
         urefs.push_back({lmax, tb.add(kv.second, b)});
