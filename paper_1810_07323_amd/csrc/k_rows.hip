@@ -632,7 +632,7 @@ hipError_t launch_gram_reduce(const LaunchGroup& g, int side, int second, int it
 // of S, and the interleaved tiles give the four waves similar shares.  The
 // finished 16 x l tile goes through LDS so that dst (row-major) and the
 // transposed operand copy in the pass format are both written with
-// contiguous runs.  H = column tiles per quarter (compile-time bound of the
+// contiguous runs.  H = column tiles per wave, ceil(nt / 4) (compile-time bound of the
 // accumulator array).
 // The stage (source, destination) is a template parameter: a run-time switch
 // over these pointers was mis-compiled by the gfx950 backend (the default
