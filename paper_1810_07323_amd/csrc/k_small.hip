@@ -1311,10 +1311,14 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
 #pragma unroll
             for (int u = 0; u < RR; u += 2)
                 *reinterpret_cast<double2*>(pv + LR + u) = make_double2(col[u], col[u + 1]);
+            // LDS rows in blocks of 16 rows that lie above j are not read from
+            // the pivot buffer again (the archive takes them from s_m)
 #pragma unroll
-            for (int k = 0; k < LR; k++) {
-                pv[k] = s_m[tid * LRP + k];
-                if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // 4 rows in flight
+            for (int q = 0; q < LR / 4; q++) {
+                if (16 * q + 15 < j) continue;
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++) pv[4 * q + kk] = s_m[tid * LRP + 4 * q + kk];
+                __builtin_amdgcn_sched_barrier(0);  // 4 rows in flight
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -1343,8 +1347,13 @@ __global__ __launch_bounds__(4 * QHY_LMAX) void k_qrcp_hy(const Prob* __restrict
             active = false;
         }
         __syncthreads();
-        // archive the raw pivot column (global stores, off the pivot group's path)
-        if (tid < l) arc[j * l + tid] = s_pv[(tid & 3) * ST + (tid >> 2)];
+        // archive the raw pivot column (global stores, off the pivot group's
+        // path); rows of LDS blocks above j come from the pivot group's s_m
+        if (tid < l) {
+            const int k = tid >> 2;
+            arc[j * l + tid] = (k < LR && 16 * (k >> 2) + 15 < j) ? s_m[(4 * p + (tid & 3)) * LRP + k]
+                                                                    : s_pv[(tid & 3) * ST + k];
+        }
         if (active) {
             const double tau = s_tau[j], scale = s_scale[j];
             const double* pv = s_pv + t * ST;
